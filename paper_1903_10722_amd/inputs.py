@@ -1,0 +1,103 @@
+"""Seeded synthetic inputs: flow-shop instances, permutations, workload shapes.
+
+This module holds none of the method's arithmetic.  It only draws the numbers
+that define a workload (machine counts, processing times, batch shapes, test
+permutations) from numpy's Philox generator, so that the HIP path, the oracle,
+the tests and the benchmark all see the same inputs for the same seed.
+
+The paper measures on generated instances (Section 5, Table 1: processing times
+uniform over a small integer range, several machines per stage); the workloads
+below keep that structure -- independent uniform integer processing times, a
+uniform machine count per stage -- at the sizes of the benchmarked configurations.
+"""
+from __future__ import annotations
+
+import numpy as np
+
+
+def _rng(seed: int, stream: int = 0) -> np.random.Generator:
+    return np.random.Generator(np.random.Philox(key=[seed & (2**64 - 1), stream]))
+
+
+def make_instance(n: int, S: int, m_lo: int, m_hi: int, p_lo: int = 1, p_hi: int = 99,
+                  seed: int = 1, machines=None):
+    """(m[S], p[n][S]) int32; m uniform in [m_lo, m_hi] unless `machines` is given,
+    p uniform in [p_lo, p_hi], job-major."""
+    g = _rng(seed, 1)
+    if machines is None:
+        m = g.integers(m_lo, m_hi + 1, size=S).astype(np.int32)
+    else:
+        m = np.asarray(machines, dtype=np.int32)
+        assert m.shape == (S,)
+    p = g.integers(p_lo, p_hi + 1, size=(n, S)).astype(np.int32)
+    return m, p
+
+
+def random_perms(count: int, n: int, seed: int = 0) -> np.ndarray:
+    """count x n int32, each row a uniformly random permutation of 0..n-1."""
+    g = _rng(seed, 2)
+    keys = g.random((count, n))
+    return np.argsort(keys, axis=1).astype(np.int32)
+
+
+def cellular(rows: int, cols: int, pc: float, pm: float) -> dict:
+    return dict(kind=0, rows=rows, cols=cols, size=rows * cols, pc=pc, pm=pm)
+
+
+def pseudo(size: int, pc: float, pm: float) -> dict:
+    return dict(kind=1, rows=0, cols=0, size=size, pc=pc, pm=pm)
+
+
+# Rates: the cellular island uses crossover 0.9 / swap mutation 0.1; the pseudo
+# island crossover 0.75 (Section 5's pseudo-GA rate) and no mutation.
+CELL_PC, CELL_PM = 0.9, 0.1
+PAIR_PC, PAIR_PM = 0.75, 0.0
+
+
+def workload(name: str, seed: int = 1, scale: int = 1) -> dict:
+    """Instance + island layout + schedule of a named workload.
+
+    `scale` > 1 shrinks every island side (and pseudo size) by that factor,
+    keeping n, S and the distributions -- used for oracle-sized parity runs."""
+    if name == "tiny":
+        m, p = make_instance(20, 3, 2, 2, seed=seed, machines=[2, 2, 2])
+        side = max(3, 8 // scale)
+        isl = [cellular(side, side, CELL_PC, CELL_PM), pseudo(2 * ((side * side) // 2), PAIR_PC, PAIR_PM)]
+        return dict(name=name, m=m, p=p, islands=isl, generations=100, interval=10, theta=1.0, topology=0)
+    if name == "medium":
+        m, p = make_instance(100, 5, 1, 5, seed=seed)
+        side = max(3, 64 // scale)
+        isl = [cellular(side, side, CELL_PC, CELL_PM), pseudo(side * side - (side * side) % 2, PAIR_PC, PAIR_PM)]
+        return dict(name=name, m=m, p=p, islands=isl, generations=500, interval=20, theta=1.0, topology=0)
+    if name == "large":
+        m, p = make_instance(500, 10, 3, 5, seed=seed)
+        side = max(3, 128 // scale)
+        ps = side * side - (side * side) % 2
+        isl = [cellular(side, side, CELL_PC, CELL_PM) for _ in range(8)] + \
+              [pseudo(ps, PAIR_PC, PAIR_PM) for _ in range(8)]
+        return dict(name=name, m=m, p=p, islands=isl, generations=1000, interval=20, theta=1.0, topology=1)
+    if name == "surrogate":
+        m, p = make_instance(1000, 20, 2, 6, seed=seed)
+        side = max(3, 64 // scale)
+        isl = [cellular(side, side, CELL_PC, CELL_PM), pseudo(side * side - (side * side) % 2, PAIR_PC, PAIR_PM)]
+        return dict(name=name, m=m, p=p, islands=isl, generations=500, interval=20, theta=1.0, topology=0)
+    raise KeyError(name)
+
+
+def batched_workloads(count: int = 256, batch_seed: int = 7, scale: int = 1, n_choices=None) -> list[dict]:
+    """The uneven batch: per instance n in {20,50,100,200,500}, S in {5,10,20},
+    machines per stage uniform [1,5], p uniform [1,99], a dual island with an
+    L x L cellular grid (L uniform in 32..128) and a pseudo island of L*L."""
+    g = _rng(batch_seed, 3)
+    n_choices = n_choices or [20, 50, 100, 200, 500]
+    out = []
+    for i in range(count):
+        n = int(g.choice(n_choices))
+        S = int(g.choice([5, 10, 20]))
+        L = int(g.integers(32, 129))
+        Ls = max(3, L // scale)
+        m, p = make_instance(n, S, 1, 5, seed=batch_seed * 100003 + i + 1)
+        isl = [cellular(Ls, Ls, CELL_PC, CELL_PM), pseudo(Ls * Ls - (Ls * Ls) % 2, PAIR_PC, PAIR_PM)]
+        out.append(dict(name=f"batched[{i}]", m=m, p=p, islands=isl, generations=50, interval=10,
+                        theta=1.0, topology=0))
+    return out
