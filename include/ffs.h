@@ -1,0 +1,167 @@
+/*
+ * ffs.h -- C ABI of the MI355X (gfx950) library for the dual heterogeneous
+ * island genetic algorithm on the flexible flow shop (Luo & El Baz,
+ * arXiv 1903.10722).
+ *
+ * Problem (paper, Section 3): J jobs pass S stages in the same order; stage s
+ * has M_s machines; every operation runs on one machine of its stage without
+ * preemption.  In this library the machines of a stage are identical (one
+ * processing time p[j][s] per job and stage), there are no release or due
+ * dates, and the objective is the makespan C_max.  A solution is a job
+ * permutation, decoded by list scheduling: stage 1 in permutation order,
+ * every later stage first-in-first-out by the previous stage's completion
+ * time (ties: earlier dispatch first), each job to the machine that becomes
+ * free first (ties: lowest machine index).
+ *
+ * Conventions for every function:
+ *   - Return value: FFS_OK (0) or a negative FFS_E* status.  No C++
+ *     exception crosses this boundary.  On error, outputs are left untouched
+ *     and ffs_last_error() describes the failure.
+ *   - Ownership: input arrays are read during the call only (copied where
+ *     kept); the caller keeps ownership of every buffer it passes.  The
+ *     library allocates no device memory: the caller supplies one device
+ *     workspace (ffs_workspace_size / ffs_bind_workspace) and owns it.
+ *   - Streams: all device work of a context is enqueued on the HIP stream
+ *     given at ffs_ctx_create, in call order.  Functions marked "(syncs)"
+ *     wait for that stream before returning.
+ *   - Threading: a context must not be used from two threads at once.
+ *   - Pointers are host pointers unless the argument says "device".
+ */
+#ifndef FFS_H
+#define FFS_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct ffs_ctx ffs_ctx;
+
+enum {
+    FFS_OK = 0,
+    FFS_EINVAL = -1,        /* an argument is out of range or inconsistent      */
+    FFS_ENOMEM = -2,        /* the bound workspace is too small                 */
+    FFS_EDEVICE = -3,       /* a HIP call failed or a kernel reported a fault   */
+    FFS_ESTATE = -4,        /* call out of order (e.g. evolve before bind)      */
+    FFS_EUNSUPPORTED = -5   /* valid problem outside this build's limits        */
+};
+
+/* One island.  Paper Section 4.1: island A runs the cellular GA, island B the
+ * pseudo GA, each with its own crossover / mutation rates (parameter level).
+ *   kind 0 (cellular): individuals on a rows x cols torus (rows, cols >= 3);
+ *          each cell mates the two best of its von Neumann neighbourhood
+ *          (self, north, east, south, west), applies order crossover with
+ *          probability p_c and a swap mutation with probability p_m, and
+ *          keeps the child only if its makespan is strictly lower.
+ *   kind 1 (pseudo): `size` individuals (even, >= 2) in fixed pairs; each pair
+ *          mates its better member with that member's complement (the
+ *          reversed permutation) and both children replace the pair.
+ * Island sizes are limited to 16384 individuals in this build.             */
+typedef struct {
+    int32_t kind;
+    int32_t rows, cols;   /* kind 0 */
+    int32_t size;         /* kind 1; ignored for kind 0 (rows*cols)           */
+    double p_c, p_m;      /* in [0, 1]                                        */
+} ffs_island_spec;
+
+/* Migration (paper Section 4.3).  Islands are paired (i, i + H), H = half the
+ * island count, which must be even.  Every `migration_interval` generations
+ * (0 = never) one migration epoch runs:
+ *   topology 0: for each pair, the penetration rule of equations (1)-(2):
+ *               fitness = E - best makespan with E = sum of all processing
+ *               times; migrate iff the fitnesses differ and 1 - beta < theta;
+ *               ceil(alpha * min(N_A, N_B)) best individuals of the fitter
+ *               island overwrite as many worst individuals of the other.
+ *   topology 1: first a ring (island order 0, H, 1, H+1, ...): every island's
+ *               best overwrites its successor's worst; then topology 0.    */
+typedef struct {
+    int32_t migration_interval;
+    int32_t topology;
+    double theta;         /* in [0, 1]; the paper's experiments use 1.0       */
+} ffs_ga_config;
+
+/* Create / destroy a context bound to a HIP stream (hipStream_t as void*;
+ * NULL = the null stream).  The device current at creation is used.        */
+int ffs_ctx_create(void *hip_stream, ffs_ctx **out);
+void ffs_ctx_destroy(ffs_ctx *ctx);
+
+/* Text of the last error on this context (never NULL; static storage owned
+ * by the context, valid until the next call on it).                         */
+const char *ffs_last_error(const ffs_ctx *ctx);
+
+/* Register one FFS instance with its islands (Section 3's problem statement).
+ *   n_jobs >= 1, n_stages in [1, 64]; machines[n_stages], each in [1, 16];
+ *   p[n_jobs * n_stages], job-major (p[j * n_stages + s]), each in [1, 65535];
+ *   islands[n_islands], n_islands even >= 2 (or 1 with no migration);
+ *   seed: the random stream key together with the instance id.
+ * Limits of this build: n_jobs <= 4096, and the packed schedule key
+ * needs sum(p) < 2^(32 - ceil(log2 n_jobs)) - 1 (FFS_EUNSUPPORTED otherwise).
+ * Must be called before ffs_bind_workspace.  *out_instance_id = 0, 1, ...  */
+int ffs_create_instance(ffs_ctx *ctx, int32_t n_jobs, int32_t n_stages,
+                        const int32_t *machines, const int32_t *p,
+                        const ffs_island_spec *islands, int32_t n_islands,
+                        const ffs_ga_config *cfg, uint64_t seed,
+                        int32_t *out_instance_id);
+
+/* Tile shape of the generation kernels: waves per workgroup (1, 2, 4 or 8).
+ * Results never depend on it.  Before ffs_bind_workspace only.              */
+int ffs_set_waves_per_block(ffs_ctx *ctx, int32_t waves);
+
+/* Device bytes needed by all instances created so far.                      */
+int ffs_workspace_size(const ffs_ctx *ctx, size_t *bytes);
+
+/* Bind a device workspace (>= ffs_workspace_size bytes, 256-byte aligned,
+ * owned by the caller, kept alive until ffs_ctx_destroy) and enqueue
+ * generation 0: random permutations (Fisher-Yates), complementary pairs on
+ * pseudo islands, decode of every individual, best-ever record.  (syncs)    */
+int ffs_bind_workspace(ffs_ctx *ctx, void *device_ptr, size_t bytes);
+
+/* Decode `count` permutations of instance `inst` (paper Section 3; the
+ * rule is stated at the top of this header).
+ *   perms: device, int32 [count * n_jobs], row-major, one permutation per row;
+ *   out_makespans: device, int32 [count].
+ * A row that is not a permutation of 0..n_jobs-1 gets makespan -1 and the
+ * call returns FFS_EINVAL after the valid rows are written.  (syncs)        */
+int ffs_evaluate(ffs_ctx *ctx, int32_t inst, const int32_t *perms, int32_t count,
+                 int32_t *out_makespans);
+
+/* Run `generations` generations of every instance.  Per generation: every
+ * cellular cell and pseudo pair produces its children from generation g-1
+ * (synchronous update), the best-ever record is updated, and when
+ * g % migration_interval == 0 a migration epoch follows.  evolve(a) then
+ * evolve(b) equals evolve(a + b).  Asynchronous (enqueued on the stream).  */
+int ffs_evolve(ffs_ctx *ctx, int32_t generations);
+
+/* Run one migration epoch of instance `inst` now, outside the schedule.    */
+int ffs_migrate(ffs_ctx *ctx, int32_t inst);
+
+/* Best-ever individual of `inst`: makespan, the generation it was found,
+ * and (if out_perm != NULL) its permutation, int32 [n_jobs].  (syncs)      */
+int ffs_best(ffs_ctx *ctx, int32_t inst, int32_t *out_makespan, int32_t *out_generation,
+             int32_t *out_perm);
+
+/* Current population of one island: genes int32 [size * n_jobs] (row per
+ * slot; cellular slot = row * cols + col) and makespans int32 [size];
+ * either pointer may be NULL.  (syncs)                                      */
+int ffs_get_population(ffs_ctx *ctx, int32_t inst, int32_t island, int32_t *genes,
+                       int32_t *makespans);
+
+/* Generations completed so far (0 after bind).                              */
+int ffs_generation(const ffs_ctx *ctx, int32_t *out_generation);
+
+/* Migration counters of `inst` since bind: epochs with a migration, and
+ * individuals moved by the adaptive rule (ring moves not counted).  (syncs) */
+int ffs_migration_counters(ffs_ctx *ctx, int32_t inst, int64_t *migrations, int64_t *migrants);
+
+/* Timing of the generation kernel: when enabled, every launch of it is
+ * bracketed by HIP events on the context's stream; ffs_kernel_time returns
+ * the summed milliseconds and the launch count since enabling.  (syncs)     */
+int ffs_set_timing(ffs_ctx *ctx, int32_t enable);
+int ffs_kernel_time(ffs_ctx *ctx, double *total_ms, int64_t *launches);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* FFS_H */

@@ -84,6 +84,8 @@ def _load():
     lib.or_ga_best.argtypes = [ctypes.c_void_p, _i64p, ctypes.POINTER(ctypes.c_int),
                                ctypes.POINTER(ctypes.c_int), ctypes.POINTER(ctypes.c_int), _i32p]
     lib.or_ga_counters.argtypes = [ctypes.c_void_p, _i64p, _i64p]
+    lib.or_ga_set_generation.argtypes = [ctypes.c_void_p, ctypes.c_int]
+    lib.or_ga_step_island.argtypes = [ctypes.c_void_p, ctypes.c_int]
     _lib = lib
     return lib
 
@@ -216,6 +218,13 @@ class GA:
         mk = _i32(mk)
         assert genes.shape == (self.sizes[island], self.n)
         self._lib.or_ga_set(self._h, island, _ptr(genes, _i32p), _ptr(mk, _i32p))
+
+    def set_generation(self, gen: int):
+        self._lib.or_ga_set_generation(self._h, gen)
+
+    def step_island(self, island: int):
+        """Next generation of one island only (no migration, counters kept)."""
+        self._lib.or_ga_step_island(self._h, island)
 
     def best(self):
         mk = ctypes.c_int64()

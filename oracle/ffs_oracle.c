@@ -515,6 +515,20 @@ void or_ga_evolve(void *h, int G)
 
 int or_ga_generation(void *h) { return ((or_ga_t *)h)->gen; }
 
+/* Test access: set the generation counter (with or_ga_set this restores a
+ * state taken from elsewhere), and run the step of one island for the next
+ * generation without touching the others, the counter or the best record. */
+void or_ga_set_generation(void *h, int gen) { ((or_ga_t *)h)->gen = gen; }
+
+void or_ga_step_island(void *h, int island)
+{
+    or_ga_t *g = (or_ga_t *)h;
+    g->gen += 1;
+    if (g->isl[island].kind == 0) cellular_step(g, island);
+    else pseudo_step(g, island);
+    g->gen -= 1;
+}
+
 void or_ga_get(void *h, int island, int *genes, int *mk)
 {
     or_ga_t *g = (or_ga_t *)h;

@@ -1,0 +1,220 @@
+"""ctypes binding of include/ffs.h: argument marshalling only.
+
+Every step of the hot path runs in the HIP library; this module converts
+numpy / torch arguments into the C structs and pointers the ABI expects and
+raises FFSError on a negative status.  PyTorch provides the device workspace
+and the stream.  The library must be built (see build.py); loading fails
+loudly otherwise -- there is no fallback.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_LIB_PATH = os.path.join(_HERE, "_build", "libffs.so")
+
+FFS_OK, FFS_EINVAL, FFS_ENOMEM, FFS_EDEVICE, FFS_ESTATE, FFS_EUNSUPPORTED = 0, -1, -2, -3, -4, -5
+
+EXPORTS = [
+    "ffs_ctx_create", "ffs_ctx_destroy", "ffs_last_error", "ffs_create_instance",
+    "ffs_set_waves_per_block", "ffs_workspace_size", "ffs_bind_workspace", "ffs_evaluate",
+    "ffs_evolve", "ffs_migrate", "ffs_best", "ffs_get_population", "ffs_generation",
+    "ffs_migration_counters", "ffs_set_timing", "ffs_kernel_time",
+]
+
+
+class FFSError(RuntimeError):
+    def __init__(self, code: int, msg: str):
+        super().__init__(f"ffs error {code}: {msg}")
+        self.code = code
+
+
+class IslandSpec(ctypes.Structure):
+    _fields_ = [("kind", ctypes.c_int32), ("rows", ctypes.c_int32), ("cols", ctypes.c_int32),
+                ("size", ctypes.c_int32), ("p_c", ctypes.c_double), ("p_m", ctypes.c_double)]
+
+
+class GAConfig(ctypes.Structure):
+    _fields_ = [("migration_interval", ctypes.c_int32), ("topology", ctypes.c_int32),
+                ("theta", ctypes.c_double)]
+
+
+_lib = None
+
+
+def library_path() -> str:
+    return _LIB_PATH
+
+
+def load_library():
+    """Load the built HIP library (raises if it was never built)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(_LIB_PATH):
+        raise RuntimeError(f"HIP library missing: {_LIB_PATH} (build it with __graft_entry__.build())")
+    lib = ctypes.CDLL(_LIB_PATH)
+    P = ctypes.c_void_p
+    i32, i64, u64 = ctypes.c_int32, ctypes.c_int64, ctypes.c_uint64
+    pi32 = ctypes.POINTER(i32)
+    lib.ffs_ctx_create.argtypes = [P, ctypes.POINTER(P)]
+    lib.ffs_ctx_destroy.argtypes = [P]
+    lib.ffs_ctx_destroy.restype = None
+    lib.ffs_last_error.argtypes = [P]
+    lib.ffs_last_error.restype = ctypes.c_char_p
+    lib.ffs_create_instance.argtypes = [P, i32, i32, pi32, pi32, ctypes.POINTER(IslandSpec), i32,
+                                        ctypes.POINTER(GAConfig), u64, pi32]
+    lib.ffs_set_waves_per_block.argtypes = [P, i32]
+    lib.ffs_workspace_size.argtypes = [P, ctypes.POINTER(ctypes.c_size_t)]
+    lib.ffs_bind_workspace.argtypes = [P, P, ctypes.c_size_t]
+    lib.ffs_evaluate.argtypes = [P, i32, P, i32, P]
+    lib.ffs_evolve.argtypes = [P, i32]
+    lib.ffs_migrate.argtypes = [P, i32]
+    lib.ffs_best.argtypes = [P, i32, pi32, pi32, pi32]
+    lib.ffs_get_population.argtypes = [P, i32, i32, pi32, pi32]
+    lib.ffs_generation.argtypes = [P, pi32]
+    lib.ffs_migration_counters.argtypes = [P, i32, ctypes.POINTER(i64), ctypes.POINTER(i64)]
+    lib.ffs_set_timing.argtypes = [P, i32]
+    lib.ffs_kernel_time.argtypes = [P, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(i64)]
+    for name in EXPORTS:
+        if name not in ("ffs_ctx_destroy", "ffs_last_error"):
+            getattr(lib, name).restype = ctypes.c_int
+    _lib = lib
+    return lib
+
+
+def _i32(a) -> np.ndarray:
+    return np.ascontiguousarray(np.asarray(a, dtype=np.int32))
+
+
+def _p32(a: np.ndarray):
+    return a.ctypes.data_as(ctypes.POINTER(ctypes.c_int32))
+
+
+class Context:
+    """One library context on a torch CUDA (HIP) stream.
+
+    Usage: add_instance(...) for every instance, then bind(), then evolve /
+    evaluate / best / population."""
+
+    def __init__(self, device: int = 0, stream=None, waves_per_block: int | None = None):
+        import torch
+        self._torch = torch
+        self.lib = load_library()
+        self.device = torch.device("cuda", device)
+        torch.cuda.set_device(self.device)
+        self.stream = stream if stream is not None else torch.cuda.current_stream(self.device)
+        h = ctypes.c_void_p()
+        self._check(self.lib.ffs_ctx_create(ctypes.c_void_p(self.stream.cuda_stream), ctypes.byref(h)), None)
+        self._h = h
+        self.ws = None
+        self.instances = []
+        if waves_per_block is not None:
+            self._check(self.lib.ffs_set_waves_per_block(self._h, waves_per_block))
+
+    def _check(self, rc: int, h="self"):
+        if rc != FFS_OK:
+            msg = self.lib.ffs_last_error(self._h).decode() if h == "self" else "context creation failed"
+            raise FFSError(rc, msg)
+
+    def close(self):
+        if getattr(self, "_h", None):
+            self.lib.ffs_ctx_destroy(self._h)
+            self._h = None
+        self.ws = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def add_instance(self, m, p, islands, interval: int, theta: float = 1.0, topology: int = 0,
+                     seed: int = 1) -> int:
+        m = _i32(m)
+        p = _i32(p)
+        n, S = p.shape
+        specs = (IslandSpec * len(islands))()
+        for i, x in enumerate(islands):
+            specs[i] = IslandSpec(int(x["kind"]), int(x.get("rows", 0)), int(x.get("cols", 0)),
+                                  int(x.get("size", 0)), float(x["pc"]), float(x["pm"]))
+        cfg = GAConfig(int(interval), int(topology), float(theta))
+        out = ctypes.c_int32()
+        self._check(self.lib.ffs_create_instance(self._h, n, S, _p32(m), _p32(p), specs, len(islands),
+                                                 ctypes.byref(cfg), ctypes.c_uint64(seed), ctypes.byref(out)))
+        sizes = [int(x["rows"]) * int(x["cols"]) if int(x["kind"]) == 0 else int(x["size"]) for x in islands]
+        self.instances.append(dict(n=n, S=S, sizes=sizes))
+        return out.value
+
+    def workspace_size(self) -> int:
+        b = ctypes.c_size_t()
+        self._check(self.lib.ffs_workspace_size(self._h, ctypes.byref(b)))
+        return int(b.value)
+
+    def bind(self):
+        torch = self._torch
+        nbytes = self.workspace_size()
+        with torch.cuda.stream(self.stream):
+            self.ws = torch.empty(nbytes + 256, dtype=torch.uint8, device=self.device)
+        ptr = self.ws.data_ptr()
+        ptr = (ptr + 255) & ~255
+        self._check(self.lib.ffs_bind_workspace(self._h, ctypes.c_void_p(ptr), ctypes.c_size_t(nbytes)))
+
+    def evaluate(self, inst: int, perms, check: bool = True):
+        """Makespans (torch int32, device) of the rows of `perms`."""
+        torch = self._torch
+        t = perms if isinstance(perms, torch.Tensor) else torch.from_numpy(_i32(perms))
+        t = t.to(device=self.device, dtype=torch.int32).contiguous()
+        count = t.shape[0]
+        out = torch.empty(count, dtype=torch.int32, device=self.device)
+        rc = self.lib.ffs_evaluate(self._h, inst, ctypes.c_void_p(t.data_ptr()), count,
+                                   ctypes.c_void_p(out.data_ptr()))
+        if check:
+            self._check(rc)
+        return out if check else (out, rc)
+
+    def evolve(self, generations: int):
+        self._check(self.lib.ffs_evolve(self._h, int(generations)))
+
+    def migrate(self, inst: int):
+        self._check(self.lib.ffs_migrate(self._h, inst))
+
+    def best(self, inst: int) -> dict:
+        n = self.instances[inst]["n"]
+        mk = ctypes.c_int32()
+        gen = ctypes.c_int32()
+        perm = np.zeros(n, dtype=np.int32)
+        self._check(self.lib.ffs_best(self._h, inst, ctypes.byref(mk), ctypes.byref(gen), _p32(perm)))
+        return dict(makespan=mk.value, generation=gen.value, perm=perm)
+
+    def population(self, inst: int, island: int):
+        info = self.instances[inst]
+        N = info["sizes"][island]
+        genes = np.zeros((N, info["n"]), dtype=np.int32)
+        mk = np.zeros(N, dtype=np.int32)
+        self._check(self.lib.ffs_get_population(self._h, inst, island, _p32(genes), _p32(mk)))
+        return genes, mk
+
+    @property
+    def generation(self) -> int:
+        g = ctypes.c_int32()
+        self._check(self.lib.ffs_generation(self._h, ctypes.byref(g)))
+        return g.value
+
+    def migration_counters(self, inst: int):
+        a = ctypes.c_int64()
+        b = ctypes.c_int64()
+        self._check(self.lib.ffs_migration_counters(self._h, inst, ctypes.byref(a), ctypes.byref(b)))
+        return a.value, b.value
+
+    def set_timing(self, enable: bool):
+        self._check(self.lib.ffs_set_timing(self._h, 1 if enable else 0))
+
+    def kernel_time(self):
+        ms = ctypes.c_double()
+        n = ctypes.c_int64()
+        self._check(self.lib.ffs_kernel_time(self._h, ctypes.byref(ms), ctypes.byref(n)))
+        return ms.value, n.value

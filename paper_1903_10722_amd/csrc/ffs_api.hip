@@ -1,0 +1,701 @@
+// ffs_api.hip -- host side of the C ABI declared in include/ffs.h.
+//
+// Host orchestration: instance validation, workspace layout (the library
+// never allocates device memory), descriptor upload, kernel selection by the
+// largest machine count (template MMAX) and the processing-time width, the
+// generation loop with the migration schedule, and result download.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <climits>
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "ffs.h"
+#include "ffs_kernels.h"
+
+using namespace flowshop;
+
+namespace {
+
+struct HostIsland {
+    ffs_island_spec spec;
+    int size;
+    size_t off_genes[2], off_mk[2], off_genkey, off_minmax, off_sorted;
+};
+
+struct HostInstance {
+    int n, S;
+    std::vector<int> m, p;
+    long long E;
+    int maxP, mmax, jb, n_pad, G;
+    std::vector<HostIsland> isl;
+    ffs_ga_config cfg;
+    uint64_t seed;
+    size_t off_pT, off_best_perm, off_best_rec, off_counters;
+};
+
+using GenKernel = void (*)(const InstDesc*, const IslandDesc*, const WorkItem*, Control*, int, int);
+using EvalKernel = void (*)(const InstDesc*, const int*, int, int*, Control*);
+
+template <int M, typename PT>
+void* gen_ptr() { return reinterpret_cast<void*>(&k_generation<M, PT>); }
+template <int M, typename PT>
+void* eval_ptr() { return reinterpret_cast<void*>(&k_evaluate<M, PT>); }
+
+const int kMmaxList[] = {2, 3, 4, 5, 6, 8, 16};
+
+void* pick_gen(int mm, int ptb)
+{
+#define FFS_CASE(M)                                                          \
+    if (mm == M) return ptb == 1 ? gen_ptr<M, uint8_t>() : gen_ptr<M, uint16_t>();
+    FFS_CASE(2) FFS_CASE(3) FFS_CASE(4) FFS_CASE(5) FFS_CASE(6) FFS_CASE(8) FFS_CASE(16)
+#undef FFS_CASE
+    return nullptr;
+}
+
+void* pick_eval(int mm, int ptb)
+{
+#define FFS_CASE(M)                                                          \
+    if (mm == M) return ptb == 1 ? eval_ptr<M, uint8_t>() : eval_ptr<M, uint16_t>();
+    FFS_CASE(2) FFS_CASE(3) FFS_CASE(4) FFS_CASE(5) FFS_CASE(6) FFS_CASE(8) FFS_CASE(16)
+#undef FFS_CASE
+    return nullptr;
+}
+
+int round_mmax(int m)
+{
+    for (int v : kMmaxList)
+        if (m <= v) return v;
+    return -1;
+}
+
+int fifo_r(int mm) { return (mm + 1 <= 16) ? 16 : 32; }
+
+size_t al256(size_t x) { return (x + 255) & ~(size_t)255; }
+
+uint64_t rate_threshold(double p)
+{
+    if (p <= 0.0) return 0;
+    if (p >= 1.0) return 4294967296ull;
+    return (uint64_t)std::floor(p * 4294967296.0);
+}
+
+}  // namespace
+
+struct ffs_ctx {
+    hipStream_t stream = nullptr;
+    int device = 0;
+    std::vector<HostInstance> inst;
+    int wpb = 4;
+    bool bound = false;
+    char* ws = nullptr;
+    size_t ws_bytes = 0;
+    int gen = 0;
+    std::string err;
+    // layout
+    size_t off_ctl = 0, off_insts = 0, off_isls = 0, off_work = 0, off_pairs = 0, total = 0;
+    int n_isl = 0, n_work = 0, n_pairs = 0, max_size = 0;
+    int mm = 2, ptb = 1;
+    size_t lds_gen = 0, lds_sort = 0;
+    bool any_ring = false;
+    void* kgen = nullptr;
+    void* keval = nullptr;
+    std::vector<WorkItem> work;
+    std::vector<PairDesc> pairs;
+    // timing
+    bool timing = false;
+    std::vector<hipEvent_t> ev_pool;
+    std::vector<std::pair<hipEvent_t, hipEvent_t>> ev_used;
+    double timed_ms = 0.0;
+    long long timed_launches = 0;
+};
+
+namespace {
+
+int fail(ffs_ctx* c, int code, const char* fmt, ...)
+{
+    char buf[512];
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(buf, sizeof buf, fmt, ap);
+    va_end(ap);
+    if (c) c->err = buf;
+    return code;
+}
+
+#define HIP_TRY(c, call)                                                                    \
+    do {                                                                                    \
+        hipError_t e_ = (call);                                                             \
+        if (e_ != hipSuccess) return fail((c), FFS_EDEVICE, "%s: %s", #call, hipGetErrorString(e_)); \
+    } while (0)
+
+// Compute offsets of everything in the workspace (a pure function of the
+// instances and the tile shape).
+void layout(ffs_ctx* c)
+{
+    size_t off = 0;
+    auto take = [&](size_t bytes) {
+        size_t o = off;
+        off += al256(bytes);
+        return o;
+    };
+    c->n_isl = 0;
+    c->max_size = 0;
+    c->any_ring = false;
+    int mmax = 1, maxP = 1;
+    for (auto& I : c->inst) {
+        c->n_isl += (int)I.isl.size();
+        mmax = std::max(mmax, I.mmax);
+        maxP = std::max(maxP, I.maxP);
+        if (I.cfg.topology == 1 && I.cfg.migration_interval >= 0) c->any_ring = true;
+        for (auto& L : I.isl) c->max_size = std::max(c->max_size, L.size);
+    }
+    c->mm = round_mmax(mmax);
+    c->ptb = (maxP <= 255) ? 1 : 2;
+    // work items: per island, chunks of (waves per block) x G chromosomes,
+    // ordered by cost (n * S * count), largest first
+    c->work.clear();
+    c->pairs.clear();
+    int isl_base = 0;
+    for (size_t ii = 0; ii < c->inst.size(); ++ii) {
+        auto& I = c->inst[ii];
+        const int chunk = c->wpb * I.G;
+        for (size_t x = 0; x < I.isl.size(); ++x) {
+            for (int s0 = 0; s0 < I.isl[x].size; s0 += chunk) {
+                WorkItem w;
+                w.island = isl_base + (int)x;
+                w.slot0 = s0;
+                w.count = std::min(chunk, I.isl[x].size - s0);
+                w.inst = (int)ii;
+                c->work.push_back(w);
+            }
+        }
+        const int H = (int)I.isl.size() / 2;
+        for (int i = 0; i < H; ++i) c->pairs.push_back(PairDesc{isl_base + i, isl_base + i + H, (int)ii, 0});
+        isl_base += (int)I.isl.size();
+    }
+    std::stable_sort(c->work.begin(), c->work.end(), [&](const WorkItem& a, const WorkItem& b) {
+        const auto& A = c->inst[a.inst];
+        const auto& B = c->inst[b.inst];
+        return (long long)A.n * A.S * a.count > (long long)B.n * B.S * b.count;
+    });
+    c->n_work = (int)c->work.size();
+    c->n_pairs = (int)c->pairs.size();
+
+    c->off_ctl = take(sizeof(Control));
+    c->off_insts = take(sizeof(InstDesc) * c->inst.size());
+    c->off_isls = take(sizeof(IslandDesc) * (size_t)c->n_isl);
+    // reserve room for the finest tile (one wave per block) so that the
+    // workspace size does not depend on the tile shape chosen at bind
+    size_t max_work = 0;
+    for (auto& I : c->inst)
+        for (auto& L : I.isl) max_work += (size_t)((L.size + I.G - 1) / I.G);
+    c->off_work = take(sizeof(WorkItem) * std::max<size_t>(1, max_work));
+    c->off_pairs = take(sizeof(PairDesc) * (size_t)std::max(1, c->n_pairs));
+    c->lds_gen = 0;
+    for (auto& I : c->inst) {
+        I.off_pT = take((size_t)I.S * I.n_pad * c->ptb);
+        I.off_best_perm = take((size_t)I.n_pad * 2);
+        I.off_best_rec = take(4 * sizeof(int));
+        I.off_counters = take(2 * sizeof(long long));
+        for (auto& L : I.isl) {
+            for (int b = 0; b < 2; ++b) {
+                L.off_genes[b] = take((size_t)L.size * I.n_pad * 2);
+                L.off_mk[b] = take((size_t)L.size * sizeof(int));
+            }
+            L.off_genkey = take(8);
+            L.off_minmax = take(16);
+            L.off_sorted = take((size_t)L.size * sizeof(int));
+        }
+        const size_t lds = align16((size_t)I.S * I.n_pad * c->ptb) +
+                           (size_t)c->wpb * wave_lds_bytes(I.G, I.n_pad, fifo_r(c->mm));
+        c->lds_gen = std::max(c->lds_gen, lds);
+    }
+    int P = 1;
+    while (P < c->max_size) P <<= 1;
+    c->lds_sort = (size_t)P * 8;
+    c->total = off;
+}
+
+int check_bound(ffs_ctx* c)
+{
+    if (!c) return FFS_EINVAL;
+    if (!c->bound) return fail(c, FFS_ESTATE, "workspace not bound");
+    return FFS_OK;
+}
+
+int read_ctl(ffs_ctx* c, Control* out)
+{
+    HIP_TRY(c, hipMemcpyAsync(out, c->ws + c->off_ctl, sizeof(Control), hipMemcpyDeviceToHost, c->stream));
+    HIP_TRY(c, hipStreamSynchronize(c->stream));
+    return FFS_OK;
+}
+
+int check_faults(ffs_ctx* c)
+{
+    Control ctl;
+    int rc = read_ctl(c, &ctl);
+    if (rc) return rc;
+    if (ctl.err & 2) return fail(c, FFS_EDEVICE, "decode kernel exceeded its step bound");
+    return FFS_OK;
+}
+
+int launch_generation(ffs_ctx* c, int mode)
+{
+    const InstDesc* di = reinterpret_cast<const InstDesc*>(c->ws + c->off_insts);
+    const IslandDesc* dl = reinterpret_cast<const IslandDesc*>(c->ws + c->off_isls);
+    const WorkItem* dw = reinterpret_cast<const WorkItem*>(c->ws + c->off_work);
+    Control* ctl = reinterpret_cast<Control*>(c->ws + c->off_ctl);
+    int n_inst = (int)c->inst.size();
+    void* args[] = {(void*)&di, (void*)&dl, (void*)&dw, (void*)&ctl, (void*)&n_inst, (void*)&mode};
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    if (c->timing && mode == 0) {
+        while (c->ev_pool.size() < 2) {
+            hipEvent_t e;
+            HIP_TRY(c, hipEventCreate(&e));
+            c->ev_pool.push_back(e);
+        }
+        e0 = c->ev_pool.back();
+        c->ev_pool.pop_back();
+        e1 = c->ev_pool.back();
+        c->ev_pool.pop_back();
+        HIP_TRY(c, hipEventRecord(e0, c->stream));
+    }
+    HIP_TRY(c, hipLaunchKernel(c->kgen, dim3(c->n_work), dim3(64 * c->wpb), args, c->lds_gen, c->stream));
+    if (e0) {
+        HIP_TRY(c, hipEventRecord(e1, c->stream));
+        c->ev_used.emplace_back(e0, e1);
+    }
+    return FFS_OK;
+}
+
+int launch_migration(ffs_ctx* c, int force_inst)
+{
+    const InstDesc* di = reinterpret_cast<const InstDesc*>(c->ws + c->off_insts);
+    const IslandDesc* dl = reinterpret_cast<const IslandDesc*>(c->ws + c->off_isls);
+    const PairDesc* dp = reinterpret_cast<const PairDesc*>(c->ws + c->off_pairs);
+    const Control* ctl = reinterpret_cast<const Control*>(c->ws + c->off_ctl);
+    if (c->any_ring) {
+        hipLaunchKernelGGL(k_mig_minmax, dim3(c->n_isl), dim3(256), 0, c->stream, di, dl, ctl, force_inst);
+        hipLaunchKernelGGL(k_mig_ring, dim3(c->n_isl), dim3(256), 0, c->stream, di, dl, ctl, force_inst);
+    }
+    hipLaunchKernelGGL(k_mig_sort, dim3(c->n_isl), dim3(1024), c->lds_sort, c->stream, di, dl, ctl, force_inst);
+    if (c->n_pairs > 0) {
+        const int chunks = (c->max_size + kMigRows - 1) / kMigRows;
+        hipLaunchKernelGGL(k_mig_adapt, dim3(c->n_pairs, chunks), dim3(256), 0, c->stream, di, dl, dp, ctl,
+                           force_inst);
+    }
+    HIP_TRY(c, hipGetLastError());
+    return FFS_OK;
+}
+
+bool migration_due(const ffs_ctx* c, int g)
+{
+    for (auto& I : c->inst)
+        if (I.cfg.migration_interval > 0 && g % I.cfg.migration_interval == 0 && I.isl.size() >= 2) return true;
+    return false;
+}
+
+}  // namespace
+
+extern "C" {
+
+int ffs_ctx_create(void* hip_stream, ffs_ctx** out)
+{
+    if (!out) return FFS_EINVAL;
+    ffs_ctx* c = new (std::nothrow) ffs_ctx();
+    if (!c) return FFS_ENOMEM;
+    c->stream = reinterpret_cast<hipStream_t>(hip_stream);
+    if (hipGetDevice(&c->device) != hipSuccess) {
+        delete c;
+        return FFS_EDEVICE;
+    }
+    *out = c;
+    return FFS_OK;
+}
+
+void ffs_ctx_destroy(ffs_ctx* c)
+{
+    if (!c) return;
+    if (c->bound) (void)hipStreamSynchronize(c->stream);
+    for (auto e : c->ev_pool) (void)hipEventDestroy(e);
+    for (auto& pr : c->ev_used) {
+        (void)hipEventDestroy(pr.first);
+        (void)hipEventDestroy(pr.second);
+    }
+    delete c;
+}
+
+const char* ffs_last_error(const ffs_ctx* c)
+{
+    if (!c) return "null context";
+    return c->err.c_str();
+}
+
+int ffs_create_instance(ffs_ctx* c, int32_t n, int32_t S, const int32_t* machines, const int32_t* p,
+                        const ffs_island_spec* islands, int32_t n_islands, const ffs_ga_config* cfg,
+                        uint64_t seed, int32_t* out_id)
+{
+    if (!c) return FFS_EINVAL;
+    if (c->bound) return fail(c, FFS_ESTATE, "instances must be created before the workspace is bound");
+    if (!machines || !p || !islands || !cfg || !out_id) return fail(c, FFS_EINVAL, "null argument");
+    if (n < 1) return fail(c, FFS_EINVAL, "n_jobs must be >= 1");
+    if (S < 1 || S > kMaxStages) return fail(c, FFS_EINVAL, "n_stages must be in [1, %d]", kMaxStages);
+    if (n > 4096) return fail(c, FFS_EUNSUPPORTED, "n_jobs above 4096 is outside this build's limits");
+    if (n_islands < 1) return fail(c, FFS_EINVAL, "need at least one island");
+    if (n_islands > 1 && (n_islands % 2) != 0) return fail(c, FFS_EINVAL, "island count must be even (pairs)");
+    if (cfg->migration_interval < 0) return fail(c, FFS_EINVAL, "migration_interval must be >= 0");
+    if (cfg->topology != 0 && cfg->topology != 1) return fail(c, FFS_EINVAL, "topology must be 0 or 1");
+    if (!(cfg->theta >= 0.0 && cfg->theta <= 1.0)) return fail(c, FFS_EINVAL, "theta must be in [0, 1]");
+    HostInstance I;
+    I.n = n;
+    I.S = S;
+    I.m.assign(machines, machines + S);
+    I.p.assign(p, p + (size_t)n * S);
+    I.mmax = 1;
+    for (int k = 0; k < S; ++k) {
+        if (I.m[k] < 1 || I.m[k] > kMaxMachines)
+            return fail(c, FFS_EINVAL, "machines[%d] = %d outside [1, %d]", k, I.m[k], kMaxMachines);
+        I.mmax = std::max(I.mmax, I.m[k]);
+    }
+    I.E = 0;
+    I.maxP = 1;
+    for (size_t i = 0; i < I.p.size(); ++i) {
+        if (I.p[i] < 1 || I.p[i] > 65535) return fail(c, FFS_EINVAL, "p[%zu] = %d outside [1, 65535]", i, I.p[i]);
+        I.E += I.p[i];
+        I.maxP = std::max(I.maxP, I.p[i]);
+    }
+    int jb = 1;
+    while ((1 << jb) < n) ++jb;
+    I.jb = jb;
+    if (I.E >= ((1ll << (32 - jb)) - 1))
+        return fail(c, FFS_EUNSUPPORTED, "sum of processing times %lld too large for the packed key (limit %lld)",
+                    I.E, (1ll << (32 - jb)) - 1);
+    I.n_pad = (n + 31) & ~31;
+    // chromosomes per wave: one lane per stage, capped so that a wave's
+    // three LDS rows per chromosome stay within 32 KB
+    I.G = std::min(kWave / S, std::max(1, 32768 / (6 * I.n_pad)));
+    for (int x = 0; x < n_islands; ++x) {
+        const ffs_island_spec& sp = islands[x];
+        HostIsland L;
+        L.spec = sp;
+        if (!(sp.p_c >= 0.0 && sp.p_c <= 1.0 && sp.p_m >= 0.0 && sp.p_m <= 1.0))
+            return fail(c, FFS_EINVAL, "island %d: rates must be in [0, 1]", x);
+        if (sp.kind == 0) {
+            if (sp.rows < 3 || sp.cols < 3) return fail(c, FFS_EINVAL, "island %d: grid must be at least 3x3", x);
+            if ((long long)sp.rows * sp.cols > 16384)
+                return fail(c, FFS_EUNSUPPORTED, "island %d: more than 16384 individuals", x);
+            L.size = sp.rows * sp.cols;
+        } else if (sp.kind == 1) {
+            if (sp.size < 2 || (sp.size % 2) != 0) return fail(c, FFS_EINVAL, "island %d: pseudo size must be even >= 2", x);
+            if (sp.size > 16384) return fail(c, FFS_EUNSUPPORTED, "island %d: more than 16384 individuals", x);
+            L.size = sp.size;
+        } else {
+            return fail(c, FFS_EINVAL, "island %d: kind must be 0 or 1", x);
+        }
+        I.isl.push_back(L);
+    }
+    I.cfg = *cfg;
+    I.seed = seed;
+    c->inst.push_back(I);
+    *out_id = (int32_t)(c->inst.size() - 1);
+    return FFS_OK;
+}
+
+int ffs_set_waves_per_block(ffs_ctx* c, int32_t waves)
+{
+    if (!c) return FFS_EINVAL;
+    if (c->bound) return fail(c, FFS_ESTATE, "tile shape is fixed once the workspace is bound");
+    if (waves != 1 && waves != 2 && waves != 4 && waves != 8) return fail(c, FFS_EINVAL, "waves must be 1, 2, 4 or 8");
+    c->wpb = waves;
+    return FFS_OK;
+}
+
+int ffs_workspace_size(const ffs_ctx* cc, size_t* bytes)
+{
+    ffs_ctx* c = const_cast<ffs_ctx*>(cc);
+    if (!c || !bytes) return FFS_EINVAL;
+    if (c->inst.empty()) return fail(c, FFS_ESTATE, "no instance created");
+    layout(c);
+    *bytes = c->total;
+    return FFS_OK;
+}
+
+int ffs_bind_workspace(ffs_ctx* c, void* dptr, size_t bytes)
+{
+    if (!c) return FFS_EINVAL;
+    if (c->bound) return fail(c, FFS_ESTATE, "workspace already bound");
+    if (c->inst.empty()) return fail(c, FFS_ESTATE, "no instance created");
+    if (!dptr) return fail(c, FFS_EINVAL, "null workspace");
+    if (reinterpret_cast<uintptr_t>(dptr) % 256 != 0) return fail(c, FFS_EINVAL, "workspace must be 256-byte aligned");
+    layout(c);
+    if (bytes < c->total) return fail(c, FFS_ENOMEM, "workspace too small: %zu < %zu", bytes, c->total);
+    int max_lds = 0;
+    HIP_TRY(c, hipDeviceGetAttribute(&max_lds, hipDeviceAttributeMaxSharedMemoryPerBlock, c->device));
+    while (c->lds_gen > (size_t)max_lds && c->wpb > 1) {
+        c->wpb >>= 1;
+        layout(c);
+    }
+    if (c->lds_gen > (size_t)max_lds)
+        return fail(c, FFS_EUNSUPPORTED, "instance needs %zu bytes of LDS per workgroup (limit %d)", c->lds_gen, max_lds);
+    if (c->lds_sort > (size_t)max_lds)
+        return fail(c, FFS_EUNSUPPORTED, "island sort needs %zu bytes of LDS (limit %d)", c->lds_sort, max_lds);
+    c->kgen = pick_gen(c->mm, c->ptb);
+    c->keval = pick_eval(c->mm, c->ptb);
+    if (!c->kgen || !c->keval) return fail(c, FFS_EUNSUPPORTED, "no kernel for %d machines", c->mm);
+    HIP_TRY(c, hipFuncSetAttribute(c->kgen, hipFuncAttributeMaxDynamicSharedMemorySize, (int)c->lds_gen));
+    HIP_TRY(c, hipFuncSetAttribute(c->keval, hipFuncAttributeMaxDynamicSharedMemorySize, max_lds));
+    HIP_TRY(c, hipFuncSetAttribute(reinterpret_cast<const void*>(&k_mig_sort),
+                                   hipFuncAttributeMaxDynamicSharedMemorySize, (int)c->lds_sort));
+    c->ws = reinterpret_cast<char*>(dptr);
+    c->ws_bytes = bytes;
+
+    // host images of the descriptors and per-instance tables
+    std::vector<InstDesc> hi(c->inst.size());
+    std::vector<IslandDesc> hl;
+    int isl_base = 0;
+    for (size_t ii = 0; ii < c->inst.size(); ++ii) {
+        auto& I = c->inst[ii];
+        InstDesc d;
+        memset(&d, 0, sizeof d);
+        d.pT = c->ws + I.off_pT;
+        d.best_perm = reinterpret_cast<uint16_t*>(c->ws + I.off_best_perm);
+        d.best_rec = reinterpret_cast<int*>(c->ws + I.off_best_rec);
+        d.counters = reinterpret_cast<long long*>(c->ws + I.off_counters);
+        d.seed = I.seed;
+        d.theta_T = rate_threshold(I.cfg.theta);
+        d.E = I.E;
+        d.inst_id = (int)ii;
+        d.n = I.n;
+        d.S = I.S;
+        d.n_pad = I.n_pad;
+        d.jb = I.jb;
+        d.G = I.G;
+        d.island0 = isl_base;
+        d.n_islands = (int)I.isl.size();
+        d.interval = (I.isl.size() >= 2) ? I.cfg.migration_interval : 0;
+        d.topology = I.cfg.topology;
+        for (int k = 0; k < I.S; ++k) d.mach[k] = I.m[k];
+        hi[ii] = d;
+        for (size_t x = 0; x < I.isl.size(); ++x) {
+            auto& L = I.isl[x];
+            IslandDesc e;
+            memset(&e, 0, sizeof e);
+            for (int b = 0; b < 2; ++b) {
+                e.genes[b] = reinterpret_cast<uint16_t*>(c->ws + L.off_genes[b]);
+                e.mk[b] = reinterpret_cast<int*>(c->ws + L.off_mk[b]);
+            }
+            e.genkey = reinterpret_cast<unsigned long long*>(c->ws + L.off_genkey);
+            e.minmax = reinterpret_cast<unsigned long long*>(c->ws + L.off_minmax);
+            e.sorted = reinterpret_cast<int*>(c->ws + L.off_sorted);
+            e.tc = rate_threshold(L.spec.p_c);
+            e.tm = rate_threshold(L.spec.p_m);
+            e.kind = L.spec.kind;
+            e.rows = L.spec.kind == 0 ? L.spec.rows : 0;
+            e.cols = L.spec.kind == 0 ? L.spec.cols : 0;
+            e.size = L.size;
+            e.inst = (int)ii;
+            e.local = (int)x;
+            hl.push_back(e);
+        }
+        isl_base += (int)I.isl.size();
+    }
+    Control ctl;
+    memset(&ctl, 0, sizeof ctl);
+    HIP_TRY(c, hipMemcpy(c->ws + c->off_ctl, &ctl, sizeof ctl, hipMemcpyHostToDevice));
+    HIP_TRY(c, hipMemcpy(c->ws + c->off_insts, hi.data(), sizeof(InstDesc) * hi.size(), hipMemcpyHostToDevice));
+    HIP_TRY(c, hipMemcpy(c->ws + c->off_isls, hl.data(), sizeof(IslandDesc) * hl.size(), hipMemcpyHostToDevice));
+    if (c->n_work)
+        HIP_TRY(c, hipMemcpy(c->ws + c->off_work, c->work.data(), sizeof(WorkItem) * c->work.size(),
+                             hipMemcpyHostToDevice));
+    if (c->n_pairs)
+        HIP_TRY(c, hipMemcpy(c->ws + c->off_pairs, c->pairs.data(), sizeof(PairDesc) * c->pairs.size(),
+                             hipMemcpyHostToDevice));
+    for (auto& I : c->inst) {
+        // processing times, stage-major, padded rows
+        std::vector<uint8_t> pt((size_t)I.S * I.n_pad * c->ptb, 0);
+        for (int k = 0; k < I.S; ++k)
+            for (int j = 0; j < I.n; ++j) {
+                const int v = I.p[(size_t)j * I.S + k];
+                if (c->ptb == 1) pt[(size_t)k * I.n_pad + j] = (uint8_t)v;
+                else reinterpret_cast<uint16_t*>(pt.data())[(size_t)k * I.n_pad + j] = (uint16_t)v;
+            }
+        HIP_TRY(c, hipMemcpy(c->ws + I.off_pT, pt.data(), pt.size(), hipMemcpyHostToDevice));
+        const int rec[4] = {INT_MAX, -1, -1, -1};
+        HIP_TRY(c, hipMemcpy(c->ws + I.off_best_rec, rec, sizeof rec, hipMemcpyHostToDevice));
+        const long long cnt[2] = {0, 0};
+        HIP_TRY(c, hipMemcpy(c->ws + I.off_counters, cnt, sizeof cnt, hipMemcpyHostToDevice));
+        for (auto& L : I.isl) {
+            const unsigned long long gk = ~0ull;
+            HIP_TRY(c, hipMemcpy(c->ws + L.off_genkey, &gk, 8, hipMemcpyHostToDevice));
+        }
+    }
+    c->bound = true;
+    c->gen = 0;
+    int rc = launch_generation(c, 1);
+    if (rc) return rc;
+    HIP_TRY(c, hipGetLastError());
+    HIP_TRY(c, hipStreamSynchronize(c->stream));
+    return check_faults(c);
+}
+
+int ffs_evaluate(ffs_ctx* c, int32_t inst, const int32_t* perms, int32_t count, int32_t* out)
+{
+    int rc = check_bound(c);
+    if (rc) return rc;
+    if (inst < 0 || inst >= (int)c->inst.size()) return fail(c, FFS_EINVAL, "no instance %d", inst);
+    if (count < 0) return fail(c, FFS_EINVAL, "count must be >= 0");
+    if (count == 0) return FFS_OK;
+    if (!perms || !out) return fail(c, FFS_EINVAL, "null buffer");
+    const auto& I = c->inst[inst];
+    const InstDesc* di = reinterpret_cast<const InstDesc*>(c->ws + c->off_insts) + inst;
+    Control* ctl = reinterpret_cast<Control*>(c->ws + c->off_ctl);
+    const int per_block = c->wpb * I.G;
+    const int blocks = (count + per_block - 1) / per_block;
+    const size_t lds = align16((size_t)I.S * I.n_pad * c->ptb) + (size_t)c->wpb * wave_lds_bytes(I.G, I.n_pad, fifo_r(c->mm));
+    void* args[] = {(void*)&di, (void*)&perms, (void*)&count, (void*)&out, (void*)&ctl};
+    HIP_TRY(c, hipLaunchKernel(c->keval, dim3(blocks), dim3(64 * c->wpb), args, lds, c->stream));
+    Control h;
+    rc = read_ctl(c, &h);
+    if (rc) return rc;
+    if (h.err & 2) return fail(c, FFS_EDEVICE, "decode kernel exceeded its step bound");
+    if (h.err & 1) {
+        // clear the flag for the next call (small host-to-device copy)
+        h.err &= ~1;
+        HIP_TRY(c, hipMemcpyAsync(c->ws + c->off_ctl + offsetof(Control, err), &h.err, sizeof(int),
+                                  hipMemcpyHostToDevice, c->stream));
+        HIP_TRY(c, hipStreamSynchronize(c->stream));
+        return fail(c, FFS_EINVAL, "some rows are not permutations of 0..%d (makespan -1)", I.n - 1);
+    }
+    return FFS_OK;
+}
+
+int ffs_evolve(ffs_ctx* c, int32_t generations)
+{
+    int rc = check_bound(c);
+    if (rc) return rc;
+    if (generations < 0) return fail(c, FFS_EINVAL, "generations must be >= 0");
+    for (int it = 0; it < generations; ++it) {
+        const int g = c->gen + 1;
+        rc = launch_generation(c, 0);
+        if (rc) return rc;
+        c->gen = g;
+        if (migration_due(c, g)) {
+            rc = launch_migration(c, -1);
+            if (rc) return rc;
+        }
+    }
+    HIP_TRY(c, hipGetLastError());
+    return FFS_OK;
+}
+
+int ffs_migrate(ffs_ctx* c, int32_t inst)
+{
+    int rc = check_bound(c);
+    if (rc) return rc;
+    if (inst < 0 || inst >= (int)c->inst.size()) return fail(c, FFS_EINVAL, "no instance %d", inst);
+    if (c->inst[inst].isl.size() < 2) return FFS_OK;
+    return launch_migration(c, inst);
+}
+
+int ffs_best(ffs_ctx* c, int32_t inst, int32_t* out_mk, int32_t* out_gen, int32_t* out_perm)
+{
+    int rc = check_bound(c);
+    if (rc) return rc;
+    if (inst < 0 || inst >= (int)c->inst.size()) return fail(c, FFS_EINVAL, "no instance %d", inst);
+    const auto& I = c->inst[inst];
+    int rec[4];
+    std::vector<uint16_t> perm((size_t)I.n_pad);
+    HIP_TRY(c, hipMemcpyAsync(rec, c->ws + I.off_best_rec, sizeof rec, hipMemcpyDeviceToHost, c->stream));
+    HIP_TRY(c, hipMemcpyAsync(perm.data(), c->ws + I.off_best_perm, perm.size() * 2, hipMemcpyDeviceToHost, c->stream));
+    rc = check_faults(c);
+    if (rc) return rc;
+    if (out_mk) *out_mk = rec[0];
+    if (out_gen) *out_gen = rec[1];
+    if (out_perm)
+        for (int j = 0; j < I.n; ++j) out_perm[j] = perm[j];
+    return FFS_OK;
+}
+
+int ffs_get_population(ffs_ctx* c, int32_t inst, int32_t island, int32_t* genes, int32_t* mk)
+{
+    int rc = check_bound(c);
+    if (rc) return rc;
+    if (inst < 0 || inst >= (int)c->inst.size()) return fail(c, FFS_EINVAL, "no instance %d", inst);
+    const auto& I = c->inst[inst];
+    if (island < 0 || island >= (int)I.isl.size()) return fail(c, FFS_EINVAL, "no island %d", island);
+    const auto& L = I.isl[island];
+    const int par = c->gen & 1;
+    std::vector<uint16_t> g;
+    if (genes) {
+        g.resize((size_t)L.size * I.n_pad);
+        HIP_TRY(c, hipMemcpyAsync(g.data(), c->ws + L.off_genes[par], g.size() * 2, hipMemcpyDeviceToHost, c->stream));
+    }
+    if (mk) HIP_TRY(c, hipMemcpyAsync(mk, c->ws + L.off_mk[par], (size_t)L.size * 4, hipMemcpyDeviceToHost, c->stream));
+    rc = check_faults(c);
+    if (rc) return rc;
+    if (genes)
+        for (int s = 0; s < L.size; ++s)
+            for (int j = 0; j < I.n; ++j) genes[(size_t)s * I.n + j] = g[(size_t)s * I.n_pad + j];
+    return FFS_OK;
+}
+
+int ffs_generation(const ffs_ctx* c, int32_t* out)
+{
+    if (!c || !out) return FFS_EINVAL;
+    *out = c->gen;
+    return FFS_OK;
+}
+
+int ffs_migration_counters(ffs_ctx* c, int32_t inst, int64_t* migrations, int64_t* migrants)
+{
+    int rc = check_bound(c);
+    if (rc) return rc;
+    if (inst < 0 || inst >= (int)c->inst.size()) return fail(c, FFS_EINVAL, "no instance %d", inst);
+    long long v[2];
+    HIP_TRY(c, hipMemcpyAsync(v, c->ws + c->inst[inst].off_counters, sizeof v, hipMemcpyDeviceToHost, c->stream));
+    HIP_TRY(c, hipStreamSynchronize(c->stream));
+    if (migrations) *migrations = v[0];
+    if (migrants) *migrants = v[1];
+    return FFS_OK;
+}
+
+int ffs_set_timing(ffs_ctx* c, int32_t enable)
+{
+    if (!c) return FFS_EINVAL;
+    HIP_TRY(c, hipStreamSynchronize(c->stream));
+    for (auto& pr : c->ev_used) {
+        c->ev_pool.push_back(pr.first);
+        c->ev_pool.push_back(pr.second);
+    }
+    c->ev_used.clear();
+    c->timing = enable != 0;
+    c->timed_ms = 0.0;
+    c->timed_launches = 0;
+    return FFS_OK;
+}
+
+int ffs_kernel_time(ffs_ctx* c, double* total_ms, int64_t* launches)
+{
+    if (!c) return FFS_EINVAL;
+    HIP_TRY(c, hipStreamSynchronize(c->stream));
+    for (auto& pr : c->ev_used) {
+        float ms = 0.f;
+        HIP_TRY(c, hipEventElapsedTime(&ms, pr.first, pr.second));
+        c->timed_ms += ms;
+        c->timed_launches += 1;
+        c->ev_pool.push_back(pr.first);
+        c->ev_pool.push_back(pr.second);
+    }
+    c->ev_used.clear();
+    if (total_ms) *total_ms = c->timed_ms;
+    if (launches) *launches = c->timed_launches;
+    return FFS_OK;
+}
+
+}  // extern "C"

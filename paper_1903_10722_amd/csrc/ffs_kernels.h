@@ -1,0 +1,690 @@
+// ffs_kernels.h -- gfx950 kernels of the island GA hot path.
+//
+// Mapping (one wave = 64 lanes):
+//   * a wave holds G = floor(64 / S) chromosomes; lane g*S + k works on
+//     stage k of chromosome g ("group" g).  Lanes beyond G*S idle.
+//   * decode (paper Section 3 problem; list-scheduling rule documented in
+//     include/ffs.h) runs as a systolic pipeline along the group: the lane of
+//     stage k keeps the m_k machine-free times of its stage, sorted, in
+//     registers, dispatches one job per step and releases finished jobs, in
+//     (completion, dispatch order), through a small LDS ring to stage k+1.
+//     A job can be released once the stage has started a later job at or
+//     after its completion time: later starts never decrease and every
+//     processing time is >= 1, so no later completion can precede it.
+//   * the genetic operators (Section 4.1-4.2: neighbourhood choice, order
+//     crossover, swap mutation, complementary pairs) run on the same group of
+//     lanes on chromosomes staged in LDS; the crossover's fill uses a wave
+//     ballot and a per-group prefix count.
+//   * populations live in HBM as rows of n_pad uint16 genes (slot-major,
+//     64-byte aligned rows), double buffered by generation parity.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "philox.h"
+
+namespace flowshop {
+
+constexpr int kWave = 64;
+constexpr int kMaxStages = 64;
+constexpr int kMaxMachines = 16;
+
+// FIFO slots per lane: occupancy between two stages never exceeds m_k + 1.
+template <int MMAX>
+struct Fifo {
+    static constexpr int R = (MMAX + 1 <= 16) ? 16 : 32;
+};
+
+struct InstDesc {
+    const void* pT;          // [S][n_pad] processing times, uint8 or uint16
+    uint16_t* best_perm;     // [n_pad]
+    int* best_rec;           // makespan, generation, island (local), slot
+    long long* counters;     // migration epochs with moves, migrants
+    unsigned long long seed;
+    unsigned long long theta_T;  // floor(theta * 2^32)
+    long long E;                 // sum of all processing times
+    int inst_id;
+    int n, S, n_pad, jb, G;
+    int island0, n_islands;
+    int interval, topology;
+    int mach[kMaxStages];
+};
+
+struct IslandDesc {
+    uint16_t* genes[2];          // [size][n_pad] per generation parity
+    int* mk[2];                  // [size]
+    unsigned long long* genkey;  // min of (makespan << 32 | slot) this generation
+    unsigned long long* minmax;  // [2] min / max keys (ring migration)
+    int* sorted;                 // [size] slots by (makespan, slot) (migration)
+    unsigned long long tc, tm;   // crossover / mutation thresholds (< tc, < tm)
+    int kind, rows, cols, size;
+    int inst;
+    int local;                   // island index inside its instance
+};
+
+struct WorkItem {
+    int island, slot0, count, inst;
+};
+
+struct PairDesc {
+    int a, b, inst, pad;
+};
+
+struct Control {
+    int gen;
+    unsigned int done;
+    int err;                     // bit 0: invalid permutation, bit 1: decode fault
+    int pad;
+};
+
+extern __shared__ __align__(16) unsigned char ffs_smem[];
+
+__device__ __forceinline__ void wave_sync()
+{
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+__host__ __device__ inline size_t align16(size_t x) { return (x + 15) & ~(size_t)15; }
+
+// LDS bytes of one wave: FIFO ring per lane + three n_pad rows per group.
+__host__ __device__ inline size_t wave_lds_bytes(int G, int n_pad, int fifo_r)
+{
+    return (size_t)kWave * fifo_r * 8 + (size_t)G * 3 * n_pad * 2;
+}
+
+// ---- row copies by the S lanes of a group (16-byte vectors) ---------------
+__device__ __forceinline__ void row_g2l(uint16_t* dst, const uint16_t* src, int n_pad, int k, int S)
+{
+    const uint4* s4 = reinterpret_cast<const uint4*>(src);
+    uint4* d4 = reinterpret_cast<uint4*>(dst);
+    const int nv = n_pad >> 3;
+#pragma unroll 4
+    for (int v = k; v < nv; v += S) d4[v] = s4[v];
+}
+
+__device__ __forceinline__ void row_l2g(uint16_t* dst, const uint16_t* src, int n_pad, int k, int S)
+{
+    const uint4* s4 = reinterpret_cast<const uint4*>(src);
+    uint4* d4 = reinterpret_cast<uint4*>(dst);
+    const int nv = n_pad >> 3;
+#pragma unroll 4
+    for (int v = k; v < nv; v += S) d4[v] = s4[v];
+}
+
+// ---- pipelined decode -----------------------------------------------------
+template <int MMAX>
+__device__ __forceinline__ void release(const uint32_t (&key)[MMAX], int& rp, uint32_t& tail, uint2* out,
+                                        uint32_t thr)
+{
+    constexpr int R = Fifo<MMAX>::R;
+    const uint32_t base = tail - (uint32_t)rp;
+    int nrel = 0;
+#pragma unroll
+    for (int i = 0; i < MMAX; ++i) {
+        const bool rl = (i >= rp) && (key[i] < thr);
+        if (rl) out[(base + i) & (R - 1)] = make_uint2(key[i], base + i);
+        nrel += rl ? 1 : 0;
+    }
+    tail += nrel;
+    rp += nrel;
+}
+
+// Returns the makespan on the lane of the last stage (other lanes: partial).
+// Keys pack (completion << jb) | job; a machine entry that never held a job
+// has key 0 ("free at 0"), a padding entry (stage with fewer than MMAX
+// machines) key 0xFFFFFFFF.  Entries [0, rp) are already released.
+template <int MMAX, typename PT>
+__device__ __forceinline__ uint32_t decode_pipelined(const uint16_t* A, const PT* prow, uint2* fifo_wave,
+                                                     int lane, int k, int S, int n, int mstage, int jb,
+                                                     bool active, int* err)
+{
+    constexpr int R = Fifo<MMAX>::R;
+    uint32_t key[MMAX];
+#pragma unroll
+    for (int i = 0; i < MMAX; ++i) key[i] = (i < mstage) ? 0u : 0xFFFFFFFFu;
+    int rp = mstage;
+    uint32_t cnt = 0, tail = 0, cmax = 0;
+    uint2* out = fifo_wave + lane * R;
+    const uint2* in = fifo_wave + (lane > 0 ? lane - 1 : 0) * R;
+#pragma unroll
+    for (int i = 0; i < R; ++i) out[i] = make_uint2(0u, 0xFFFFFFFFu);
+    const bool last = (k == S - 1);
+    const uint32_t jmask = (1u << jb) - 1u;
+    bool done = !active;
+    const int cap = n + S * (MMAX + 2) + 8;
+    int iter = 0;
+    wave_sync();
+    while (__any(!done)) {
+        const uint32_t g0 = A[cnt < (uint32_t)n ? cnt : 0u];
+        const uint2 e = in[cnt & (R - 1)];
+        const bool have = !done && (k == 0 || e.y == cnt);
+        const uint32_t j = (k == 0) ? g0 : (e.x & jmask);
+        const uint32_t r = (k == 0) ? 0u : (e.x >> jb);
+        if (have) {
+            const uint32_t f = key[0] >> jb;
+            const uint32_t s = f > r ? f : r;
+            const uint32_t c = s + (uint32_t)prow[j];
+            if (!last) release<MMAX>(key, rp, tail, out, (s + 1u) << jb);
+            // entry 0 (the machine free first) is released; it takes the job
+            const uint32_t nk = (c << jb) | j;
+            const uint32_t ithr = (c + 1u) << jb;
+            uint32_t nkey[MMAX];
+            bool prev = true;
+#pragma unroll
+            for (int i = 0; i < MMAX; ++i) {
+                const bool lt = (i + 1 < MMAX) ? (key[(i + 1 < MMAX) ? i + 1 : i] < ithr) : false;
+                nkey[i] = lt ? key[(i + 1 < MMAX) ? i + 1 : i] : (prev ? nk : key[i]);
+                prev = lt;
+            }
+#pragma unroll
+            for (int i = 0; i < MMAX; ++i) key[i] = nkey[i];
+            rp -= 1;
+            ++cnt;
+            cmax = c > cmax ? c : cmax;
+            if (cnt == (uint32_t)n) {
+                if (!last) release<MMAX>(key, rp, tail, out, 0xFFFFFFFFu);
+                done = true;
+            }
+        }
+        if (++iter > cap) {
+            if (!done) atomicOr(err, 2);
+            done = true;
+        }
+        __asm__ volatile("" ::: "memory");
+    }
+    return cmax;
+}
+
+// ---- order crossover on a group -------------------------------------------
+// A = parent 1 (becomes the child), B = parent 2, V = scratch for the inverse
+// of parent 1.  child[a..b] = P1[a..b]; P2 read cyclically from b+1 fills
+// b+1, ..., n-1, 0, ..., a-1 with the genes not in the segment.
+__device__ __forceinline__ void ox_group(uint16_t* A, const uint16_t* B, uint16_t* V, int n, int a, int b,
+                                         bool doit, int k, int S, int g)
+{
+    if (doit)
+        for (int t = k; t < n; t += S) V[A[t]] = (uint16_t)t;
+    wave_sync();
+    const uint64_t gmask = (S >= 64) ? ~0ull : ((1ull << S) - 1ull);
+    const int shift = g * S;
+    const uint64_t below_me = (1ull << k) - 1ull;
+    int base = 0;
+    for (int c0 = 0; c0 < n; c0 += S) {
+        const int t = c0 + k;
+        bool keep = false;
+        uint32_t gene = 0;
+        if (doit && t < n) {
+            int pos = b + 1 + t;
+            if (pos >= n) pos -= n;
+            gene = B[pos];
+            const int iv = V[gene];
+            keep = (iv < a) || (iv > b);
+        }
+        const uint64_t bal = __ballot(keep);
+        const uint64_t gm = (shift < 64 ? (bal >> shift) : 0ull) & gmask;
+        if (keep) {
+            int dst = b + 1 + base + __popcll(gm & below_me);
+            if (dst >= n) dst -= n;
+            A[dst] = (uint16_t)gene;
+        }
+        base += __popcll(gm);
+    }
+    wave_sync();
+}
+
+__device__ __forceinline__ void swap_genes(uint16_t* A, bool doit, int i, int j)
+{
+    if (doit) {
+        const uint16_t x = A[i], y = A[j];
+        A[i] = y;
+        A[j] = x;
+    }
+    wave_sync();
+}
+
+// ---- one generation (mode 0) or generation 0 (mode 1) of every island -----
+template <int MMAX, typename PT>
+__global__ void __launch_bounds__(512) k_generation(const InstDesc* __restrict__ insts,
+                                                    const IslandDesc* __restrict__ isls,
+                                                    const WorkItem* __restrict__ work, Control* ctl, int n_inst,
+                                                    int mode)
+{
+    constexpr int R = Fifo<MMAX>::R;
+    const WorkItem wi = work[blockIdx.x];
+    const InstDesc* I = insts + wi.inst;
+    const IslandDesc* L = isls + wi.island;
+    const int n = I->n, S = I->S, n_pad = I->n_pad, jb = I->jb, G = I->G;
+    const int gen = (mode == 1) ? 0 : (ctl->gen + 1);
+    const int cur = (gen + 1) & 1, nxt = gen & 1;
+
+    PT* pT = reinterpret_cast<PT*>(ffs_smem);
+    {
+        const uint4* src = reinterpret_cast<const uint4*>(I->pT);
+        uint4* dst = reinterpret_cast<uint4*>(pT);
+        const int nv = (int)((size_t)S * n_pad * sizeof(PT) / 16);
+        for (int v = threadIdx.x; v < nv; v += blockDim.x) dst[v] = src[v];
+    }
+    __syncthreads();
+
+    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    unsigned char* wbase = ffs_smem + align16((size_t)S * n_pad * sizeof(PT)) + wave * wave_lds_bytes(G, n_pad, R);
+    uint2* fifo = reinterpret_cast<uint2*>(wbase);
+    uint16_t* gbase = reinterpret_cast<uint16_t*>(wbase + (size_t)kWave * R * 8);
+    const int g = lane / S, k = lane - g * S;
+    const int local = wave * G + g;
+    const bool active = (g < G) && (local < wi.count);
+    uint16_t* A = gbase + (size_t)(active ? g : 0) * 3 * n_pad;
+    uint16_t* B = A + n_pad;
+    uint16_t* V = B + n_pad;
+    const int slot = wi.slot0 + (active ? local : 0);
+    const int mstage = I->mach[k];
+    const PT* prow = pT + (size_t)k * n_pad;
+    const uint64_t seed = I->seed, iid = (uint64_t)I->inst_id;
+    const uint32_t isl_local = (uint32_t)L->local;
+
+    if (mode == 1) {
+        // generation 0: Fisher-Yates from the INIT stream; a pseudo pair is a
+        // permutation (even slot) and its reversal (odd slot).
+        const int fy_slot = (L->kind == 0) ? slot : (slot >> 1);
+        const bool rev = (L->kind == 1) && (slot & 1);
+        uint32_t* D = reinterpret_cast<uint32_t*>(B);   // B..V: n_pad words >= n - 1
+        const int nblk = (n - 1 + 7) / 8;
+        if (active) {
+            for (int blk = k; blk < nblk; blk += S) {
+                const Block4 bb = stream_block(seed, iid, isl_local, (uint32_t)fy_slot, 0, 0, kInit, (uint32_t)blk);
+#pragma unroll
+                for (int d = 0; d < 8; ++d) {
+                    const int idx = blk * 8 + d;
+                    if (idx < n - 1) D[idx] = draw32(bb, d);
+                }
+            }
+            for (int t = k; t < n; t += S) A[t] = (uint16_t)t;
+        }
+        wave_sync();
+        if (active && k == 0) {
+            for (int i = n - 1; i >= 1; --i) {
+                const int j = (int)below(D[n - 1 - i], (uint32_t)(i + 1));
+                const uint16_t x = A[i], y = A[j];
+                A[i] = y;
+                A[j] = x;
+            }
+        }
+        wave_sync();
+        if (active && rev) {
+            for (int t = k; t < n / 2; t += S) {
+                const uint16_t x = A[t], y = A[n - 1 - t];
+                A[t] = y;
+                A[n - 1 - t] = x;
+            }
+        }
+        wave_sync();
+    } else if (L->kind == 0) {
+        // cellular: two best of (self, N, E, S, W) by (makespan, that order)
+        const int* mkp = L->mk[cur];
+        const int rows = L->rows, cols = L->cols;
+        const int r = slot / cols, c = slot - r * cols;
+        const int nb0 = slot;
+        const int nb1 = ((r == 0) ? rows - 1 : r - 1) * cols + c;
+        const int nb2 = r * cols + ((c == cols - 1) ? 0 : c + 1);
+        const int nb3 = ((r == rows - 1) ? 0 : r + 1) * cols + c;
+        const int nb4 = r * cols + ((c == 0) ? cols - 1 : c - 1);
+        const int v0 = mkp[nb0], v1 = mkp[nb1], v2 = mkp[nb2], v3 = mkp[nb3], v4 = mkp[nb4];
+        int bv = v0, bs = nb0, bo = 0;
+        if (v1 < bv) { bv = v1; bs = nb1; bo = 1; }
+        if (v2 < bv) { bv = v2; bs = nb2; bo = 2; }
+        if (v3 < bv) { bv = v3; bs = nb3; bo = 3; }
+        if (v4 < bv) { bv = v4; bs = nb4; bo = 4; }
+        int sv = 0x7FFFFFFF, ss = -1;
+        if (bo != 0 && v0 < sv) { sv = v0; ss = nb0; }
+        if (bo != 1 && v1 < sv) { sv = v1; ss = nb1; }
+        if (bo != 2 && v2 < sv) { sv = v2; ss = nb2; }
+        if (bo != 3 && v3 < sv) { sv = v3; ss = nb3; }
+        if (bo != 4 && v4 < sv) { sv = v4; ss = nb4; }
+        if (ss < 0) ss = nb1;   // only when every makespan is INT_MAX (never)
+        const Block4 bk = stream_block(seed, iid, isl_local, (uint32_t)slot, 0, (uint32_t)gen, kCell, 0);
+        const bool cx = (uint64_t)draw32(bk, 0) < L->tc;
+        const int u = (int)below(draw32(bk, 1), (uint32_t)n), w = (int)below(draw32(bk, 2), (uint32_t)n);
+        const int a = u < w ? u : w, b = u < w ? w : u;
+        const bool mx = (uint64_t)draw32(bk, 3) < L->tm;
+        const int mi = (int)below(draw32(bk, 4), (uint32_t)n);
+        int mj = mi + 1 + (int)below(draw32(bk, 5), (uint32_t)(n - 1));
+        if (mj >= n) mj -= n;
+        const uint16_t* gp = L->genes[cur];
+        if (active) {
+            row_g2l(A, gp + (size_t)bs * n_pad, n_pad, k, S);
+            row_g2l(B, gp + (size_t)ss * n_pad, n_pad, k, S);
+        }
+        wave_sync();
+        ox_group(A, B, V, n, a, b, cx && active, k, S, g);
+        swap_genes(A, mx && active && k == 0, mi, mj);
+    } else {
+        // pseudo: X = better of the pair, Y = reverse(X); even slot gets
+        // OX(X, Y), odd slot OX(Y, X), with shared cut points.
+        const int* mkp = L->mk[cur];
+        const int q = slot >> 1;
+        const bool odd = slot & 1;
+        const int xs = (mkp[2 * q] <= mkp[2 * q + 1]) ? 2 * q : 2 * q + 1;
+        const Block4 b0 = stream_block(seed, iid, isl_local, (uint32_t)q, 0, (uint32_t)gen, kPair, 0);
+        const Block4 b1 = stream_block(seed, iid, isl_local, (uint32_t)q, 0, (uint32_t)gen, kPair, 1);
+        const bool cx = (uint64_t)draw32(b0, 0) < L->tc;
+        const int u = (int)below(draw32(b0, 1), (uint32_t)n), w = (int)below(draw32(b0, 2), (uint32_t)n);
+        const int a = u < w ? u : w, b = u < w ? w : u;
+        const uint32_t dm = odd ? draw32(b0, 6) : draw32(b0, 3);
+        const uint32_t di = odd ? draw32(b0, 7) : draw32(b0, 4);
+        const uint32_t dj = odd ? draw32(b1, 0) : draw32(b0, 5);
+        const bool mx = (uint64_t)dm < L->tm;
+        const int mi = (int)below(di, (uint32_t)n);
+        int mj = mi + 1 + (int)below(dj, (uint32_t)(n - 1));
+        if (mj >= n) mj -= n;
+        if (active) row_g2l(V, L->genes[cur] + (size_t)xs * n_pad, n_pad, k, S);
+        wave_sync();
+        if (active) {
+            for (int t = k; t < n; t += S) {
+                const uint16_t x = V[t], xr = V[n - 1 - t];
+                A[t] = odd ? xr : x;
+                B[t] = odd ? x : xr;
+            }
+        }
+        wave_sync();
+        ox_group(A, B, V, n, a, b, cx && active, k, S, g);
+        swap_genes(A, mx && active && k == 0, mi, mj);
+    }
+
+    const uint32_t cm = decode_pipelined<MMAX, PT>(A, prow, fifo, lane, k, S, n, mstage, jb, active, &ctl->err);
+    const int src = active ? (g * S + S - 1) : lane;
+    const int cmg = __shfl((int)cm, src, 64);
+
+    if (active) {
+        uint16_t* dstrow = L->genes[nxt] + (size_t)slot * n_pad;
+        int mk_new;
+        if (mode == 1 || L->kind == 1) {
+            mk_new = cmg;
+            row_l2g(dstrow, A, n_pad, k, S);
+        } else {
+            const int mk_old = L->mk[cur][slot];
+            const bool rep = cmg < mk_old;
+            mk_new = rep ? cmg : mk_old;
+            if (rep) {
+                row_l2g(dstrow, A, n_pad, k, S);
+            } else {
+                const uint4* s4 = reinterpret_cast<const uint4*>(L->genes[cur] + (size_t)slot * n_pad);
+                uint4* d4 = reinterpret_cast<uint4*>(dstrow);
+                for (int v = k; v < (n_pad >> 3); v += S) d4[v] = s4[v];
+            }
+        }
+        if (k == 0) {
+            L->mk[nxt][slot] = mk_new;
+            atomicMin(L->genkey, ((unsigned long long)(unsigned)mk_new << 32) | (unsigned)slot);
+        }
+    }
+
+    // ---- the last workgroup to finish updates the best-ever records --------
+    __shared__ int s_last;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        __threadfence();
+        const unsigned prev = atomicAdd(&ctl->done, 1u);
+        s_last = (prev == gridDim.x - 1) ? 1 : 0;
+    }
+    __syncthreads();
+    if (!s_last) return;
+    __threadfence();
+    // the staging LDS is free now: reuse it for the per-instance results
+    int* s_imp = reinterpret_cast<int*>(ffs_smem);
+    int* s_isl = s_imp + blockDim.x;
+    int* s_slot = s_isl + blockDim.x;
+    for (int base = 0; base < n_inst; base += blockDim.x) {
+        const int ii = base + threadIdx.x;
+        int imp = 0, bisl = -1, bslot = -1;
+        if (ii < n_inst) {
+            const InstDesc* J = insts + ii;
+            unsigned long long bkey = ~0ull;
+            for (int x = 0; x < J->n_islands; ++x) {
+                unsigned long long* gk = isls[J->island0 + x].genkey;
+                const unsigned long long v = __hip_atomic_load(gk, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                // (makespan, island, slot): strict on makespan keeps the lowest island
+                if (bisl < 0 || (v >> 32) < (bkey >> 32)) {
+                    bkey = v;
+                    bisl = x;
+                }
+                __hip_atomic_store(gk, ~0ull, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            }
+            bslot = (int)(bkey & 0xFFFFFFFFu);
+            const int bmk = (int)(bkey >> 32);
+            if (bmk < J->best_rec[0]) {
+                J->best_rec[0] = bmk;
+                J->best_rec[1] = gen;
+                J->best_rec[2] = bisl;
+                J->best_rec[3] = bslot;
+                imp = 1;
+            }
+        }
+        s_imp[threadIdx.x] = imp;
+        s_isl[threadIdx.x] = bisl;
+        s_slot[threadIdx.x] = bslot;
+        __syncthreads();
+        const int lim = (n_inst - base) < (int)blockDim.x ? (n_inst - base) : (int)blockDim.x;
+        for (int t = 0; t < lim; ++t) {
+            if (!s_imp[t]) continue;
+            const InstDesc* J = insts + base + t;
+            const IslandDesc* X = isls + J->island0 + s_isl[t];
+            const uint4* s4 = reinterpret_cast<const uint4*>(X->genes[nxt] + (size_t)s_slot[t] * J->n_pad);
+            uint4* d4 = reinterpret_cast<uint4*>(J->best_perm);
+            for (int v = threadIdx.x; v < (J->n_pad >> 3); v += blockDim.x) d4[v] = s4[v];
+        }
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) {
+        ctl->done = 0;
+        ctl->gen = gen;
+        __threadfence();
+    }
+}
+
+// ---- decode of caller-supplied permutations -------------------------------
+template <int MMAX, typename PT>
+__global__ void __launch_bounds__(512) k_evaluate(const InstDesc* __restrict__ I, const int* __restrict__ perms,
+                                                  int count, int* __restrict__ out, Control* ctl)
+{
+    constexpr int R = Fifo<MMAX>::R;
+    const int n = I->n, S = I->S, n_pad = I->n_pad, jb = I->jb, G = I->G;
+    PT* pT = reinterpret_cast<PT*>(ffs_smem);
+    {
+        const uint4* src = reinterpret_cast<const uint4*>(I->pT);
+        uint4* dst = reinterpret_cast<uint4*>(pT);
+        const int nv = (int)((size_t)S * n_pad * sizeof(PT) / 16);
+        for (int v = threadIdx.x; v < nv; v += blockDim.x) dst[v] = src[v];
+    }
+    __syncthreads();
+    const int wpb = blockDim.x >> 6;
+    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    unsigned char* wbase = ffs_smem + align16((size_t)S * n_pad * sizeof(PT)) + wave * wave_lds_bytes(G, n_pad, R);
+    uint2* fifo = reinterpret_cast<uint2*>(wbase);
+    uint16_t* gbase = reinterpret_cast<uint16_t*>(wbase + (size_t)kWave * R * 8);
+    const int g = lane / S, k = lane - g * S;
+    const long long idx = ((long long)blockIdx.x * wpb + wave) * G + g;
+    const bool active = (g < G) && (idx < count);
+    uint16_t* A = gbase + (size_t)(active ? g : 0) * 3 * n_pad;
+    uint16_t* V = A + 2 * n_pad;
+    bool bad = false;
+    if (active) {
+        const int* row = perms + idx * (long long)n;
+        for (int t = k; t < n; t += S) {
+            const int x = row[t];
+            const bool ob = (unsigned)x >= (unsigned)n;
+            bad |= ob;
+            A[t] = ob ? (uint16_t)0 : (uint16_t)x;
+            if (!ob) V[x] = (uint16_t)t;
+        }
+    }
+    wave_sync();
+    if (active)
+        for (int t = k; t < n; t += S) bad |= (V[A[t]] != (uint16_t)t);
+    const uint64_t gmask = (S >= 64) ? ~0ull : ((1ull << S) - 1ull);
+    const uint64_t bb = __ballot(bad && active);
+    const int shift = g * S;
+    const bool gbad = ((shift < 64 ? (bb >> shift) : 0ull) & gmask) != 0ull;
+    const uint32_t cm = decode_pipelined<MMAX, PT>(A, pT + (size_t)k * n_pad, fifo, lane, k, S, n, I->mach[k], jb,
+                                                   active, &ctl->err);
+    if (active && k == S - 1) out[idx] = gbad ? -1 : (int)cm;
+    if (active && k == 0 && gbad) atomicOr(&ctl->err, 1);
+}
+
+// ---- migration (paper Section 4.3) -----------------------------------------
+__device__ __forceinline__ bool migrating_now(const InstDesc* I, int inst, int gen, int force_inst)
+{
+    if (force_inst >= 0) return inst == force_inst;
+    return I->interval > 0 && gen > 0 && (gen % I->interval) == 0;
+}
+
+__global__ void __launch_bounds__(256) k_mig_minmax(const InstDesc* __restrict__ insts,
+                                                    const IslandDesc* __restrict__ isls, const Control* ctl,
+                                                    int force_inst)
+{
+    const IslandDesc* L = isls + blockIdx.x;
+    const InstDesc* I = insts + L->inst;
+    const int gen = ctl->gen;
+    if (!migrating_now(I, L->inst, gen, force_inst) || I->topology != 1) return;
+    const int* mk = L->mk[gen & 1];
+    unsigned long long mn = ~0ull, mx = 0ull;
+    for (int s = threadIdx.x; s < L->size; s += blockDim.x) {
+        const unsigned long long v = ((unsigned long long)(unsigned)mk[s] << 32) | (unsigned)s;
+        mn = v < mn ? v : mn;
+        mx = v > mx ? v : mx;
+    }
+    __shared__ unsigned long long smn[256], smx[256];
+    smn[threadIdx.x] = mn;
+    smx[threadIdx.x] = mx;
+    __syncthreads();
+    for (int w = 128; w > 0; w >>= 1) {
+        if ((int)threadIdx.x < w) {
+            smn[threadIdx.x] = smn[threadIdx.x + w] < smn[threadIdx.x] ? smn[threadIdx.x + w] : smn[threadIdx.x];
+            smx[threadIdx.x] = smx[threadIdx.x + w] > smx[threadIdx.x] ? smx[threadIdx.x + w] : smx[threadIdx.x];
+        }
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) {
+        L->minmax[0] = smn[0];
+        L->minmax[1] = smx[0];
+    }
+}
+
+// ring c0, p0, c1, p1, ...: island x receives its predecessor's best into its worst slot
+__global__ void __launch_bounds__(256) k_mig_ring(const InstDesc* __restrict__ insts,
+                                                  const IslandDesc* __restrict__ isls, const Control* ctl,
+                                                  int force_inst)
+{
+    const IslandDesc* L = isls + blockIdx.x;
+    const InstDesc* I = insts + L->inst;
+    const int gen = ctl->gen;
+    if (!migrating_now(I, L->inst, gen, force_inst) || I->topology != 1) return;
+    const int H = I->n_islands / 2;
+    if (H == 0) return;
+    const int l = L->local;
+    const int pos = (l < H) ? 2 * l : 2 * (l - H) + 1;
+    const int pp = (pos == 0) ? 2 * H - 1 : pos - 1;
+    const int pl = (pp & 1) ? H + (pp >> 1) : (pp >> 1);
+    const IslandDesc* P = isls + I->island0 + pl;
+    const int par = gen & 1;
+    const int ss = (int)(P->minmax[0] & 0xFFFFFFFFu);
+    const int ds = (int)(L->minmax[1] & 0xFFFFFFFFu);
+    const int n_pad = I->n_pad;
+    const uint4* s4 = reinterpret_cast<const uint4*>(P->genes[par] + (size_t)ss * n_pad);
+    uint4* d4 = reinterpret_cast<uint4*>(L->genes[par] + (size_t)ds * n_pad);
+    for (int v = threadIdx.x; v < (n_pad >> 3); v += blockDim.x) d4[v] = s4[v];
+    if (threadIdx.x == 0) L->mk[par][ds] = P->mk[par][ss];
+}
+
+// bitonic sort of (makespan << 32 | slot) keys of one island in LDS
+__global__ void __launch_bounds__(1024) k_mig_sort(const InstDesc* __restrict__ insts,
+                                                   const IslandDesc* __restrict__ isls, const Control* ctl,
+                                                   int force_inst)
+{
+    const IslandDesc* L = isls + blockIdx.x;
+    const InstDesc* I = insts + L->inst;
+    const int gen = ctl->gen;
+    if (!migrating_now(I, L->inst, gen, force_inst)) return;
+    const int N = L->size;
+    int P = 1;
+    while (P < N) P <<= 1;
+    unsigned long long* keys = reinterpret_cast<unsigned long long*>(ffs_smem);
+    const int* mk = L->mk[gen & 1];
+    for (int i = threadIdx.x; i < P; i += blockDim.x)
+        keys[i] = (i < N) ? (((unsigned long long)(unsigned)mk[i] << 32) | (unsigned)i) : ~0ull;
+    __syncthreads();
+    for (int kk = 2; kk <= P; kk <<= 1) {
+        for (int j = kk >> 1; j > 0; j >>= 1) {
+            for (int i = threadIdx.x; i < P; i += blockDim.x) {
+                const int ixj = i ^ j;
+                if (ixj > i) {
+                    const unsigned long long x = keys[i], y = keys[ixj];
+                    const bool up = (i & kk) == 0;
+                    if ((x > y) == up) {
+                        keys[i] = y;
+                        keys[ixj] = x;
+                    }
+                }
+            }
+            __syncthreads();
+        }
+    }
+    for (int i = threadIdx.x; i < N; i += blockDim.x) L->sorted[i] = (int)(keys[i] & 0xFFFFFFFFu);
+}
+
+// adaptive penetration rule of equations (1)-(2) on one island pair, and the
+// copy of the r-th best emigrant over the r-th worst immigrant
+constexpr int kMigRows = 32;
+
+__global__ void __launch_bounds__(256) k_mig_adapt(const InstDesc* __restrict__ insts,
+                                                   const IslandDesc* __restrict__ isls,
+                                                   const PairDesc* __restrict__ pairs, const Control* ctl,
+                                                   int force_inst)
+{
+    const PairDesc pd = pairs[blockIdx.x];
+    const InstDesc* I = insts + pd.inst;
+    const int gen = ctl->gen;
+    if (!migrating_now(I, pd.inst, gen, force_inst)) return;
+    const IslandDesc* A = isls + pd.a;
+    const IslandDesc* B = isls + pd.b;
+    const int par = gen & 1;
+    const long long ba = A->mk[par][A->sorted[0]], bb = B->mk[par][B->sorted[0]];
+    long long fa = I->E - ba, fb = I->E - bb;
+    if (fa < 0) fa = 0;
+    if (fb < 0) fb = 0;
+    if (fa == fb) return;
+    const unsigned long long hi = (unsigned long long)(fa > fb ? fa : fb);
+    const unsigned long long lo = (unsigned long long)(fa > fb ? fb : fa);
+    if (hi == 0) return;
+    if (!(((hi - lo) << 32) < I->theta_T * hi)) return;
+    const unsigned long long N = (unsigned long long)(A->size < B->size ? A->size : B->size);
+    unsigned long long count = (N * (hi - lo) + hi - 1) / hi;
+    if (count > N) count = N;
+    const IslandDesc* Em = (fa > fb) ? A : B;
+    const IslandDesc* Im = (fa > fb) ? B : A;
+    if (blockIdx.y == 0 && threadIdx.x == 0) {
+        atomicAdd((unsigned long long*)&I->counters[0], 1ull);
+        atomicAdd((unsigned long long*)&I->counters[1], count);
+    }
+    const int r0 = blockIdx.y * kMigRows;
+    const int r1 = (int)((unsigned long long)(r0 + kMigRows) < count ? (unsigned long long)(r0 + kMigRows) : count);
+    if (r0 >= r1) return;
+    const int n_pad = I->n_pad, nv = n_pad >> 3;
+    const int rows = r1 - r0;
+    for (int e = threadIdx.x; e < rows * nv; e += blockDim.x) {
+        const int r = r0 + e / nv, v = e - (e / nv) * nv;
+        const int ss = Em->sorted[r];
+        const int ds = Im->sorted[Im->size - 1 - r];
+        const uint4* s4 = reinterpret_cast<const uint4*>(Em->genes[par] + (size_t)ss * n_pad);
+        uint4* d4 = reinterpret_cast<uint4*>(Im->genes[par] + (size_t)ds * n_pad);
+        d4[v] = s4[v];
+    }
+    for (int r = r0 + threadIdx.x; r < r1; r += blockDim.x) {
+        const int ss = Em->sorted[r];
+        const int ds = Im->sorted[Im->size - 1 - r];
+        Im->mk[par][ds] = Em->mk[par][ss];
+    }
+}
+
+}  // namespace flowshop

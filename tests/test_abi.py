@@ -1,0 +1,63 @@
+"""The C-ABI library builds, loads and exports every entry point that
+include/ffs.h declares (no device calls: runs without a GPU)."""
+import ctypes
+import os
+import re
+import subprocess
+
+import pytest
+
+from paper_1903_10722_amd import binding
+from paper_1903_10722_amd.build import build_library
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def _declared():
+    src = open(os.path.join(ROOT, "include", "ffs.h")).read()
+    src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
+    return sorted(set(re.findall(r"\b(ffs_[a-z_]+)\s*\(", src)))
+
+
+@pytest.fixture(scope="module")
+def lib_path():
+    if not os.path.exists(binding.library_path()):
+        build_library()
+    return binding.library_path()
+
+
+def test_header_declares_the_boundary():
+    names = _declared()
+    for must in ["ffs_create_instance", "ffs_evaluate", "ffs_evolve", "ffs_migrate", "ffs_best"]:
+        assert must in names
+
+
+def test_library_exports_every_declared_symbol(lib_path):
+    out = subprocess.run(["nm", "-D", "--defined-only", lib_path], capture_output=True, text=True, check=True).stdout
+    exported = set(re.findall(r"\bT (ffs_[a-z_]+)\b", out))
+    missing = [n for n in _declared() if n not in exported]
+    assert not missing, missing
+    assert sorted(binding.EXPORTS) == sorted(_declared())
+
+
+def test_library_loads_and_reports_errors_without_device(lib_path):
+    lib = binding.load_library()
+    for n in _declared():
+        assert hasattr(lib, n)
+    # argument checks that need no device
+    assert lib.ffs_ctx_create(None, None) == binding.FFS_EINVAL
+    assert lib.ffs_last_error(None) == b"null context"
+
+
+def test_oracle_and_library_share_no_code():
+    """The oracle is plain C built by gcc; the HIP sources never include it and
+    the oracle never includes the HIP headers."""
+    csrc = os.path.join(ROOT, "paper_1903_10722_amd", "csrc")
+    for f in os.listdir(csrc):
+        txt = open(os.path.join(csrc, f)).read()
+        assert "oracle" not in txt.lower()
+    otxt = open(os.path.join(ROOT, "oracle", "ffs_oracle.c")).read()
+    assert "#include \"" not in otxt
+    for f in os.listdir(os.path.join(ROOT, "paper_1903_10722_amd")):
+        if f.endswith(".py"):
+            assert "import oracle" not in open(os.path.join(ROOT, "paper_1903_10722_amd", f)).read()

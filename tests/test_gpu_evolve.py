@@ -1,0 +1,206 @@
+"""GPU parity of the whole generation loop (ffs_evolve / ffs_migrate /
+ffs_best / ffs_get_population) against the oracle: same seed, same
+trajectory, bit-exact genes and makespans of every island."""
+import numpy as np
+import pytest
+
+import oracle
+from gpu_util import assert_same_state, ensure_built, make_ctx, oracle_ga, say
+from paper_1903_10722_amd import inputs
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.mark.parametrize("inst_seed", [1, 2])
+def test_tiny_trajectory(inst_seed):
+    """Tiny workload at its full size: 8x8 cellular + 64 pseudo, n=20, S=3,
+    100 generations, migration every 10; compared after every chunk."""
+    ensure_built()
+    w = inputs.workload("tiny", seed=inst_seed)
+    say(f"[evolve] tiny inst_seed={inst_seed}")
+    ctx = make_ctx([w])
+    ga = oracle_ga(w)
+    assert_same_state(ctx, ga, 0, 2, "generation 0")
+    done = 0
+    for chunk in [1, 4, 5, 10, 7, 13, 20, 40]:
+        ctx.evolve(chunk)
+        ga.evolve(chunk)
+        done += chunk
+        assert ctx.generation == done
+        assert_same_state(ctx, ga, 0, 2, f"generation {done}")
+        b1, b2 = ctx.best(0), ga.best()
+        assert b1["makespan"] == b2["makespan"] and b1["generation"] == b2["generation"]
+        assert b1["perm"].tolist() == b2["perm"].tolist()
+    assert ctx.migration_counters(0) == ga.counters()
+    ctx.close()
+
+
+def test_medium_scaled_trajectory():
+    """Medium instance (n=100, S=5, m in [1,5]) on 32x32 + 1024 islands,
+    60 generations with adaptive migration every 20."""
+    ensure_built()
+    w = inputs.workload("medium", seed=1, scale=2)
+    say("[evolve] medium scale=2")
+    ctx = make_ctx([w])
+    ga = oracle_ga(w)
+    for g in (19, 1, 20, 20):
+        ctx.evolve(g)
+        ga.evolve(g)
+        assert_same_state(ctx, ga, 0, 2, f"generation {ctx.generation}")
+    assert ctx.best(0)["makespan"] == ga.best()["makespan"]
+    assert ctx.migration_counters(0) == ga.counters()
+    ctx.close()
+
+
+def test_medium_full_size_generations():
+    """The benchmarked medium workload at full size (64x64 + 4096): the GPU
+    state after 19 generations is loaded into the oracle, then generation 20
+    (with its migration epoch) and 21 are compared exactly."""
+    ensure_built()
+    w = inputs.workload("medium", seed=1)
+    say("[evolve] medium full size")
+    ctx = make_ctx([w])
+    ga = oracle_ga(w)
+    # generation 0 must already agree (initialisation + decode of 8192 individuals)
+    assert_same_state(ctx, ga, 0, 2, "generation 0")
+    ctx.evolve(19)
+    for isl in range(2):
+        genes, mk = ctx.population(0, isl)
+        ga.set_population(isl, genes, mk)
+    ga.set_generation(19)
+    for g in (20, 21):
+        ctx.evolve(1)
+        ga.evolve(1)
+        assert_same_state(ctx, ga, 0, 2, f"generation {g}")
+    ctx.close()
+
+
+def test_sixteen_islands_ring_then_adaptive():
+    """Large instance (n=500, S=10, m in [3,5]) on 16 islands (8 cellular
+    8x8, 8 pseudo 64), ring-then-adaptive migration every 20, 40 generations,
+    plus one forced epoch."""
+    ensure_built()
+    w = inputs.workload("large", seed=1, scale=16)
+    say("[evolve] large scale=16, 16 islands, topology 1")
+    ctx = make_ctx([w])
+    ga = oracle_ga(w)
+    for g in (20, 20):
+        ctx.evolve(g)
+        ga.evolve(g)
+        assert_same_state(ctx, ga, 0, 16, f"generation {ctx.generation}")
+    ctx.migrate(0)
+    ga.migrate()
+    assert_same_state(ctx, ga, 0, 16, "forced epoch")
+    ctx.evolve(3)
+    ga.evolve(3)
+    assert_same_state(ctx, ga, 0, 16, "after forced epoch")
+    assert ctx.best(0)["makespan"] == ga.best()["makespan"]
+    ctx.close()
+
+
+def test_large_full_size_one_generation_sampled():
+    """The large workload at full size (16 islands of 16384, n=500, S=10):
+    generation 0 of two islands, then generation 1 of one cellular and one
+    pseudo island recomputed by the oracle from the GPU's generation-0 state."""
+    ensure_built()
+    w = inputs.workload("large", seed=1)
+    say("[evolve] large full size")
+    ctx = make_ctx([w])
+    ga = oracle_ga(w)
+    for isl in (0, 8):
+        g1, m1 = ctx.population(0, isl)
+        g2, m2 = ga.population(isl)
+        assert np.array_equal(m1, m2) and np.array_equal(g1, g2), f"generation 0 island {isl}"
+    ctx.evolve(1)
+    for isl in (3, 12):
+        ga.step_island(isl)
+        g1, m1 = ctx.population(0, isl)
+        g2, m2 = ga.population(isl)
+        assert np.array_equal(m1, m2) and np.array_equal(g1, g2), f"generation 1 island {isl}"
+    ctx.close()
+
+
+def test_batched_uneven_instances():
+    """Eight instances of the uneven batch (n in {20..500}, S in {5,10,20},
+    grids shrunk 8x) in one context: each matches its own oracle run."""
+    ensure_built()
+    ws = inputs.batched_workloads(count=8, batch_seed=7, scale=8)
+    say("[evolve] batched 8 instances " + str([(w["p"].shape, w["islands"][0]["rows"]) for w in ws]))
+    ctx = make_ctx(ws)
+    gas = [oracle_ga(w, inst=i) for i, w in enumerate(ws)]
+    for g in (10, 15):
+        ctx.evolve(g)
+        for i, ga in enumerate(gas):
+            ga.evolve(g)
+            assert_same_state(ctx, ga, i, 2, f"instance {i} generation {ctx.generation}")
+            assert ctx.best(i)["makespan"] == ga.best()["makespan"]
+    ctx.close()
+
+
+def test_tile_shapes_give_identical_trajectories():
+    ensure_built()
+    w = inputs.workload("tiny", seed=3)
+    ref = None
+    for wpb in (1, 2, 8):
+        say(f"[evolve] tiny waves_per_block={wpb}")
+        ctx = make_ctx([w], waves_per_block=wpb)
+        ctx.evolve(30)
+        st = [ctx.population(0, i) for i in range(2)]
+        ctx.close()
+        if ref is None:
+            ga = oracle_ga(w)
+            ga.evolve(30)
+            ref = [ga.population(i) for i in range(2)]
+        for a, b in zip(st, ref):
+            assert np.array_equal(a[0], b[0]) and np.array_equal(a[1], b[1])
+
+
+@pytest.mark.parametrize("variant", ["no_operators", "always_mutate", "n2_S1", "theta0", "odd_shapes"])
+def test_edge_workloads(variant):
+    ensure_built()
+    if variant == "no_operators":
+        m, p = inputs.make_instance(15, 3, 1, 3, seed=3)
+        isl = [inputs.cellular(3, 4, 0.0, 0.0), inputs.pseudo(10, 0.0, 0.0)]
+        w = dict(m=m, p=p, islands=isl, interval=5)
+    elif variant == "always_mutate":
+        m, p = inputs.make_instance(25, 4, 1, 4, seed=4)
+        isl = [inputs.cellular(5, 3, 1.0, 1.0), inputs.pseudo(12, 1.0, 1.0)]
+        w = dict(m=m, p=p, islands=isl, interval=3)
+    elif variant == "n2_S1":
+        m, p = inputs.make_instance(2, 1, 1, 1, seed=5, machines=[1])
+        isl = [inputs.cellular(3, 3, 0.9, 0.5), inputs.pseudo(4, 0.75, 0.5)]
+        w = dict(m=m, p=p, islands=isl, interval=2)
+    elif variant == "theta0":
+        m, p = inputs.make_instance(30, 5, 1, 5, seed=6)
+        isl = [inputs.cellular(4, 4, 0.9, 0.1), inputs.pseudo(16, 0.75, 0.0)]
+        w = dict(m=m, p=p, islands=isl, interval=4, theta=0.0)
+    else:
+        m, p = inputs.make_instance(33, 7, 1, 6, seed=7)
+        isl = [inputs.cellular(3, 11, 0.9, 0.1), inputs.pseudo(130, 0.75, 0.05)]
+        w = dict(m=m, p=p, islands=isl, interval=6)
+    say(f"[evolve] edge {variant}")
+    ctx = make_ctx([w])
+    ga = oracle_ga(w)
+    for g in (1, 6, 13):
+        ctx.evolve(g)
+        ga.evolve(g)
+        assert_same_state(ctx, ga, 0, 2, f"{variant} generation {ctx.generation}")
+    assert ctx.best(0)["makespan"] == ga.best()["makespan"]
+    ctx.close()
+
+
+def test_stored_makespans_match_redecode():
+    """Invariant on the GPU's own state: every stored makespan equals the
+    oracle's decode of the stored permutation, which is a permutation."""
+    ensure_built()
+    w = inputs.workload("medium", seed=2, scale=4)
+    say("[evolve] redecode medium scale=4")
+    ctx = make_ctx([w])
+    ctx.evolve(25)
+    for isl in range(2):
+        genes, mk = ctx.population(0, isl)
+        rows = np.arange(0, len(mk), 7)
+        for r in rows:
+            assert sorted(genes[r].tolist()) == list(range(w["p"].shape[0]))
+        assert np.array_equal(mk[rows], oracle.decode_many(w["m"], w["p"], genes[rows]))
+    ctx.close()
