@@ -74,8 +74,6 @@ int round_mmax(int m)
     return -1;
 }
 
-int fifo_r(int mm) { return (mm + 1 <= 16) ? 16 : 32; }
-
 size_t al256(size_t x) { return (x + 255) & ~(size_t)255; }
 
 uint64_t rate_threshold(double p)
@@ -213,7 +211,7 @@ void layout(ffs_ctx* c)
             L.off_sorted = take((size_t)L.size * sizeof(int));
         }
         const size_t lds = align16((size_t)I.S * I.n_pad * c->ptb) +
-                           (size_t)c->wpb * wave_lds_bytes(I.G, I.n_pad, fifo_r(c->mm));
+                           (size_t)c->wpb * wave_lds_bytes(I.G, I.n_pad);
         c->lds_gen = std::max(c->lds_gen, lds);
     }
     int P = 1;
@@ -557,7 +555,7 @@ int ffs_evaluate(ffs_ctx* c, int32_t inst, const int32_t* perms, int32_t count, 
     Control* ctl = reinterpret_cast<Control*>(c->ws + c->off_ctl);
     const int per_block = c->wpb * I.G;
     const int blocks = (count + per_block - 1) / per_block;
-    const size_t lds = align16((size_t)I.S * I.n_pad * c->ptb) + (size_t)c->wpb * wave_lds_bytes(I.G, I.n_pad, fifo_r(c->mm));
+    const size_t lds = align16((size_t)I.S * I.n_pad * c->ptb) + (size_t)c->wpb * wave_lds_bytes(I.G, I.n_pad);
     void* args[] = {(void*)&di, (void*)&perms, (void*)&count, (void*)&out, (void*)&ctl};
     HIP_TRY(c, hipLaunchKernel(c->keval, dim3(blocks), dim3(64 * c->wpb), args, lds, c->stream));
     Control h;

@@ -29,12 +29,6 @@ constexpr int kWave = 64;
 constexpr int kMaxStages = 64;
 constexpr int kMaxMachines = 16;
 
-// FIFO slots per lane: occupancy between two stages never exceeds m_k + 1.
-template <int MMAX>
-struct Fifo {
-    static constexpr int R = (MMAX + 1 <= 16) ? 16 : 32;
-};
-
 struct InstDesc {
     const void* pT;          // [S][n_pad] processing times, uint8 or uint16
     uint16_t* best_perm;     // [n_pad]
@@ -88,10 +82,10 @@ __device__ __forceinline__ void wave_sync()
 
 __host__ __device__ inline size_t align16(size_t x) { return (x + 15) & ~(size_t)15; }
 
-// LDS bytes of one wave: FIFO ring per lane + three n_pad rows per group.
-__host__ __device__ inline size_t wave_lds_bytes(int G, int n_pad, int fifo_r)
+// LDS bytes of one wave: three n_pad rows of uint16 per group.
+__host__ __device__ inline size_t wave_lds_bytes(int G, int n_pad)
 {
-    return (size_t)kWave * fifo_r * 8 + (size_t)G * 3 * n_pad * 2;
+    return (size_t)G * 3 * n_pad * 2;
 }
 
 // ---- row copies by the S lanes of a group (16-byte vectors) ---------------
@@ -114,62 +108,76 @@ __device__ __forceinline__ void row_l2g(uint16_t* dst, const uint16_t* src, int 
 }
 
 // ---- pipelined decode -----------------------------------------------------
-template <int MMAX>
-__device__ __forceinline__ void release(const uint32_t (&key)[MMAX], int& rp, uint32_t& tail, uint2* out,
-                                        uint32_t thr)
+// Value of `x` held by lane - 1 (whole-wave shift right by one lane, DPP).
+__device__ __forceinline__ uint32_t from_prev_lane(uint32_t x)
 {
-    constexpr int R = Fifo<MMAX>::R;
-    const uint32_t base = tail - (uint32_t)rp;
-    int nrel = 0;
-#pragma unroll
-    for (int i = 0; i < MMAX; ++i) {
-        const bool rl = (i >= rp) && (key[i] < thr);
-        if (rl) out[(base + i) & (R - 1)] = make_uint2(key[i], base + i);
-        nrel += rl ? 1 : 0;
-    }
-    tail += nrel;
-    rp += nrel;
+    return (uint32_t)__builtin_amdgcn_update_dpp(0, (int)x, 0x138 /* wave_shr:1 */, 0xF, 0xF, false);
 }
 
-// Returns the makespan on the lane of the last stage (other lanes: partial).
-// Keys pack (completion << jb) | job; a machine entry that never held a job
-// has key 0 ("free at 0"), a padding entry (stage with fewer than MMAX
-// machines) key 0xFFFFFFFF.  Entries [0, rp) are already released.
+// One group of S lanes decodes one permutation; lane k runs stage k.
+//
+// Stage k keeps its m_k machine-free times as a sorted list of keys
+// (completion << jb | job) in registers; a machine that has not run a job yet
+// holds key 0, a padding entry (fewer than MMAX machines) 0xFFFFFFFF.  Each
+// step dispatches the next job: it takes the machine of entry 0 (free first;
+// ties on time only relabel machines), starts at max(free, ready) and inserts
+// its completion.  The removed entry 0 is handed to stage k+1: entries leave
+// the list in (completion, dispatch order) order, which is the order in which
+// stage k+1 must dispatch them.  After its last job a stage hands on its
+// remaining entries, one per step.
+//
+// The timing of this pipeline does not depend on the data: stage k acts in
+// steps [a_k, a_k + n) (dispatch) and, unless it is the last stage, in
+// [a_k + n, a_k + n + m_k) (hand-on of the rest); the first m_k entries it
+// removes are the never-used machines, so its real jobs leave in steps
+// [a_k + m_k, a_k + m_k + n) and stage k+1 starts at a_{k+1} = a_k + m_k + 1.
+// The decode therefore runs exactly n + sum_{k<S-1} (m_k + 1) steps, and a
+// job handed on in one step is taken by the next lane in the next step, so
+// one register pair per lane carries it: (key, processing time at k+1).
+//
+// AP[t] = (p[job][0] << 16) | job for the permutation's t-th job.  Returns
+// the makespan on the lane of the last stage.
 template <int MMAX, typename PT>
-__device__ __forceinline__ uint32_t decode_pipelined(const uint16_t* A, const PT* prow, uint2* fifo_wave,
-                                                     int lane, int k, int S, int n, int mstage, int jb,
-                                                     bool active, int* err)
+__device__ __forceinline__ uint32_t decode_pipelined(const uint32_t* AP, const PT* prow_next, const int* mach,
+                                                     int k, int S, int n, int jb, bool active)
 {
-    constexpr int R = Fifo<MMAX>::R;
+    constexpr uint32_t PAD = 0xFFFFFFFFu;
+    int a_k = 0, total = n;
+    for (int i = 0; i + 1 < S; ++i) {
+        const int step = mach[i] + 1;
+        if (i < k) a_k += step;
+        total += step;
+    }
+    const int mstage = mach[k];
     uint32_t key[MMAX];
 #pragma unroll
-    for (int i = 0; i < MMAX; ++i) key[i] = (i < mstage) ? 0u : 0xFFFFFFFFu;
-    int rp = mstage;
-    uint32_t cnt = 0, tail = 0, cmax = 0;
-    uint2* out = fifo_wave + lane * R;
-    const uint2* in = fifo_wave + (lane > 0 ? lane - 1 : 0) * R;
-#pragma unroll
-    for (int i = 0; i < R; ++i) out[i] = make_uint2(0u, 0xFFFFFFFFu);
-    const bool last = (k == S - 1);
+    for (int i = 0; i < MMAX; ++i) key[i] = (i < mstage) ? 0u : PAD;
+    uint32_t cmax = 0;
+    uint32_t o_key = 0, o_p = 0;
+    const bool first = (k == 0), last = (k == S - 1);
     const uint32_t jmask = (1u << jb) - 1u;
-    bool done = !active;
-    const int cap = n + S * (MMAX + 2) + 8;
-    int iter = 0;
-    wave_sync();
-    while (__any(!done)) {
-        const uint32_t g0 = A[cnt < (uint32_t)n ? cnt : 0u];
-        const uint2 e = in[cnt & (R - 1)];
-        const bool have = !done && (k == 0 || e.y == cnt);
-        const uint32_t j = (k == 0) ? g0 : (e.x & jmask);
-        const uint32_t r = (k == 0) ? 0u : (e.x >> jb);
-        if (have) {
-            const uint32_t f = key[0] >> jb;
+    const uint32_t un = (uint32_t)n;
+    const uint32_t n_act = active ? (last ? un : un + (uint32_t)mstage) : 0u;
+    uint32_t ap0 = AP[0], ap1 = AP[n > 1 ? 1 : 0];
+    uint32_t pn_pre = (uint32_t)prow_next[0];
+    for (int it = 0; it < total; ++it) {
+        const uint32_t in_key = from_prev_lane(o_key);
+        const uint32_t in_p = from_prev_lane(o_p);
+        const uint32_t ap = ap0;
+        ap0 = ap1;
+        ap1 = AP[(it + 2 < n) ? it + 2 : n - 1];
+        const uint32_t rel = (uint32_t)(it - a_k);
+        if (rel < n_act) {
+            const bool have = rel < un;
+            const uint32_t j = first ? (ap & 0xFFFFu) : (in_key & jmask);
+            const uint32_t r = first ? 0u : (in_key >> jb);
+            const uint32_t pj = first ? (ap >> 16) : in_p;
+            const uint32_t o = key[0];
+            const uint32_t f = o >> jb;
             const uint32_t s = f > r ? f : r;
-            const uint32_t c = s + (uint32_t)prow[j];
-            if (!last) release<MMAX>(key, rp, tail, out, (s + 1u) << jb);
-            // entry 0 (the machine free first) is released; it takes the job
-            const uint32_t nk = (c << jb) | j;
-            const uint32_t ithr = (c + 1u) << jb;
+            const uint32_t c = s + pj;
+            const uint32_t nk = have ? ((c << jb) | j) : PAD;
+            const uint32_t ithr = have ? ((c + 1u) << jb) : PAD;
             uint32_t nkey[MMAX];
             bool prev = true;
 #pragma unroll
@@ -180,21 +188,27 @@ __device__ __forceinline__ uint32_t decode_pipelined(const uint16_t* A, const PT
             }
 #pragma unroll
             for (int i = 0; i < MMAX; ++i) key[i] = nkey[i];
-            rp -= 1;
-            ++cnt;
-            cmax = c > cmax ? c : cmax;
-            if (cnt == (uint32_t)n) {
-                if (!last) release<MMAX>(key, rp, tail, out, 0xFFFFFFFFu);
-                done = true;
-            }
+            cmax = (have && c > cmax) ? c : cmax;
+            o_key = o;
+            o_p = pn_pre;
         }
-        if (++iter > cap) {
-            if (!done) atomicOr(err, 2);
-            done = true;
-        }
-        __asm__ volatile("" ::: "memory");
+        const uint32_t q = key[0] & jmask;
+        pn_pre = (uint32_t)prow_next[q < un ? q : 0u];
     }
     return cmax;
+}
+
+// AP[t] = (p[A[t]][0] << 16) | A[t], built by the group's lanes.
+template <typename PT>
+__device__ __forceinline__ void build_ap(uint32_t* AP, const uint16_t* A, const PT* prow0, int n, int k, int S,
+                                         bool active)
+{
+    if (active)
+        for (int t = k; t < n; t += S) {
+            const uint32_t j = A[t];
+            AP[t] = ((uint32_t)prow0[j] << 16) | j;
+        }
+    wave_sync();
 }
 
 // ---- order crossover on a group -------------------------------------------
@@ -251,7 +265,6 @@ __global__ void __launch_bounds__(512) k_generation(const InstDesc* __restrict__
                                                     const WorkItem* __restrict__ work, Control* ctl, int n_inst,
                                                     int mode)
 {
-    constexpr int R = Fifo<MMAX>::R;
     const WorkItem wi = work[blockIdx.x];
     const InstDesc* I = insts + wi.inst;
     const IslandDesc* L = isls + wi.island;
@@ -269,9 +282,8 @@ __global__ void __launch_bounds__(512) k_generation(const InstDesc* __restrict__
     __syncthreads();
 
     const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
-    unsigned char* wbase = ffs_smem + align16((size_t)S * n_pad * sizeof(PT)) + wave * wave_lds_bytes(G, n_pad, R);
-    uint2* fifo = reinterpret_cast<uint2*>(wbase);
-    uint16_t* gbase = reinterpret_cast<uint16_t*>(wbase + (size_t)kWave * R * 8);
+    uint16_t* gbase = reinterpret_cast<uint16_t*>(ffs_smem + align16((size_t)S * n_pad * sizeof(PT)) +
+                                                  wave * wave_lds_bytes(G, n_pad));
     const int g = lane / S, k = lane - g * S;
     const int local = wave * G + g;
     const bool active = (g < G) && (local < wi.count);
@@ -279,8 +291,7 @@ __global__ void __launch_bounds__(512) k_generation(const InstDesc* __restrict__
     uint16_t* B = A + n_pad;
     uint16_t* V = B + n_pad;
     const int slot = wi.slot0 + (active ? local : 0);
-    const int mstage = I->mach[k];
-    const PT* prow = pT + (size_t)k * n_pad;
+    const PT* prow_next = pT + (size_t)(k + 1 < S ? k + 1 : S - 1) * n_pad;
     const uint64_t seed = I->seed, iid = (uint64_t)I->inst_id;
     const uint32_t isl_local = (uint32_t)L->local;
 
@@ -392,10 +403,13 @@ __global__ void __launch_bounds__(512) k_generation(const InstDesc* __restrict__
         swap_genes(A, mx && active && k == 0, mi, mj);
     }
 
-    const uint32_t cm = decode_pipelined<MMAX, PT>(A, prow, fifo, lane, k, S, n, mstage, jb, active, &ctl->err);
+    uint32_t* AP = reinterpret_cast<uint32_t*>(B);   // B..V: n_pad words
+    build_ap<PT>(AP, A, pT, n, k, S, active);
+    const uint32_t cm = decode_pipelined<MMAX, PT>(AP, prow_next, I->mach, k, S, n, jb, active);
     const int src = active ? (g * S + S - 1) : lane;
     const int cmg = __shfl((int)cm, src, 64);
 
+    unsigned long long wkey = ~0ull;
     if (active) {
         uint16_t* dstrow = L->genes[nxt] + (size_t)slot * n_pad;
         int mk_new;
@@ -414,16 +428,25 @@ __global__ void __launch_bounds__(512) k_generation(const InstDesc* __restrict__
                 for (int v = k; v < (n_pad >> 3); v += S) d4[v] = s4[v];
             }
         }
-        if (k == 0) {
-            L->mk[nxt][slot] = mk_new;
-            atomicMin(L->genkey, ((unsigned long long)(unsigned)mk_new << 32) | (unsigned)slot);
-        }
+        if (k == 0) L->mk[nxt][slot] = mk_new;
+        wkey = (k == 0) ? (((unsigned long long)(unsigned)mk_new << 32) | (unsigned)slot) : ~0ull;
     }
+    // island minimum of (makespan, slot): wave reduction, then one atomic per workgroup
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) {
+        const unsigned long long o = __shfl_xor(wkey, off, 64);
+        wkey = o < wkey ? o : wkey;
+    }
+    __shared__ unsigned long long s_wmin[8];
+    if (lane == 0) s_wmin[wave] = wkey;
 
     // ---- the last workgroup to finish updates the best-ever records --------
     __shared__ int s_last;
     __syncthreads();
     if (threadIdx.x == 0) {
+        unsigned long long mn = ~0ull;
+        for (int x = 0; x < (int)(blockDim.x >> 6); ++x) mn = s_wmin[x] < mn ? s_wmin[x] : mn;
+        if (mn != ~0ull) atomicMin(L->genkey, mn);
         __threadfence();
         const unsigned prev = atomicAdd(&ctl->done, 1u);
         s_last = (prev == gridDim.x - 1) ? 1 : 0;
@@ -488,7 +511,6 @@ template <int MMAX, typename PT>
 __global__ void __launch_bounds__(512) k_evaluate(const InstDesc* __restrict__ I, const int* __restrict__ perms,
                                                   int count, int* __restrict__ out, Control* ctl)
 {
-    constexpr int R = Fifo<MMAX>::R;
     const int n = I->n, S = I->S, n_pad = I->n_pad, jb = I->jb, G = I->G;
     PT* pT = reinterpret_cast<PT*>(ffs_smem);
     {
@@ -500,9 +522,8 @@ __global__ void __launch_bounds__(512) k_evaluate(const InstDesc* __restrict__ I
     __syncthreads();
     const int wpb = blockDim.x >> 6;
     const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
-    unsigned char* wbase = ffs_smem + align16((size_t)S * n_pad * sizeof(PT)) + wave * wave_lds_bytes(G, n_pad, R);
-    uint2* fifo = reinterpret_cast<uint2*>(wbase);
-    uint16_t* gbase = reinterpret_cast<uint16_t*>(wbase + (size_t)kWave * R * 8);
+    uint16_t* gbase = reinterpret_cast<uint16_t*>(ffs_smem + align16((size_t)S * n_pad * sizeof(PT)) +
+                                                  wave * wave_lds_bytes(G, n_pad));
     const int g = lane / S, k = lane - g * S;
     const long long idx = ((long long)blockIdx.x * wpb + wave) * G + g;
     const bool active = (g < G) && (idx < count);
@@ -526,8 +547,10 @@ __global__ void __launch_bounds__(512) k_evaluate(const InstDesc* __restrict__ I
     const uint64_t bb = __ballot(bad && active);
     const int shift = g * S;
     const bool gbad = ((shift < 64 ? (bb >> shift) : 0ull) & gmask) != 0ull;
-    const uint32_t cm = decode_pipelined<MMAX, PT>(A, pT + (size_t)k * n_pad, fifo, lane, k, S, n, I->mach[k], jb,
-                                                   active, &ctl->err);
+    uint32_t* AP = reinterpret_cast<uint32_t*>(A + n_pad);   // B..V: n_pad words
+    build_ap<PT>(AP, A, pT, n, k, S, active);
+    const uint32_t cm = decode_pipelined<MMAX, PT>(AP, pT + (size_t)(k + 1 < S ? k + 1 : S - 1) * n_pad, I->mach,
+                                                   k, S, n, jb, active);
     if (active && k == S - 1) out[idx] = gbad ? -1 : (int)cm;
     if (active && k == 0 && gbad) atomicOr(&ctl->err, 1);
 }
