@@ -188,12 +188,17 @@ __device__ __forceinline__ uint32_t decode_pipelined(const uint32_t* AP, const P
             }
 #pragma unroll
             for (int i = 0; i < MMAX; ++i) key[i] = nkey[i];
-            cmax = (have && c > cmax) ? c : cmax;
             o_key = o;
             o_p = pn_pre;
         }
         const uint32_t q = key[0] & jmask;
         pn_pre = (uint32_t)prow_next[q < un ? q : 0u];
+    }
+    // the last stage's list now holds every machine's final completion time
+#pragma unroll
+    for (int i = 0; i < MMAX; ++i) {
+        const uint32_t c = (key[i] == PAD) ? 0u : (key[i] >> jb);
+        cmax = c > cmax ? c : cmax;
     }
     return cmax;
 }
@@ -203,10 +208,22 @@ template <typename PT>
 __device__ __forceinline__ void build_ap(uint32_t* AP, const uint16_t* A, const PT* prow0, int n, int k, int S,
                                          bool active)
 {
+    constexpr int U = 4;
     if (active)
-        for (int t = k; t < n; t += S) {
-            const uint32_t j = A[t];
-            AP[t] = ((uint32_t)prow0[j] << 16) | j;
+        for (int t0 = k; t0 < n; t0 += U * S) {
+            uint32_t j[U], pj[U];
+#pragma unroll
+            for (int u = 0; u < U; ++u) {
+                const int t = t0 + u * S;
+                j[u] = A[t < n ? t : 0];
+            }
+#pragma unroll
+            for (int u = 0; u < U; ++u) pj[u] = prow0[j[u]];
+#pragma unroll
+            for (int u = 0; u < U; ++u) {
+                const int t = t0 + u * S;
+                if (t < n) AP[t] = (pj[u] << 16) | j[u];
+            }
         }
     wave_sync();
 }
@@ -214,36 +231,60 @@ __device__ __forceinline__ void build_ap(uint32_t* AP, const uint16_t* A, const 
 // ---- order crossover on a group -------------------------------------------
 // A = parent 1 (becomes the child), B = parent 2, V = scratch for the inverse
 // of parent 1.  child[a..b] = P1[a..b]; P2 read cyclically from b+1 fills
-// b+1, ..., n-1, 0, ..., a-1 with the genes not in the segment.
+// b+1, ..., n-1, 0, ..., a-1 with the genes not in the segment.  Loops are
+// unrolled four chunks deep so that independent LDS reads overlap.
 __device__ __forceinline__ void ox_group(uint16_t* A, const uint16_t* B, uint16_t* V, int n, int a, int b,
                                          bool doit, int k, int S, int g)
 {
-    if (doit)
-        for (int t = k; t < n; t += S) V[A[t]] = (uint16_t)t;
+    constexpr int U = 4;
+    if (doit) {
+        for (int t0 = k; t0 < n; t0 += U * S) {
+            uint32_t x[U];
+#pragma unroll
+            for (int u = 0; u < U; ++u) {
+                const int t = t0 + u * S;
+                x[u] = A[t < n ? t : 0];
+            }
+#pragma unroll
+            for (int u = 0; u < U; ++u) {
+                const int t = t0 + u * S;
+                if (t < n) V[x[u]] = (uint16_t)t;
+            }
+        }
+    }
     wave_sync();
     const uint64_t gmask = (S >= 64) ? ~0ull : ((1ull << S) - 1ull);
     const int shift = g * S;
     const uint64_t below_me = (1ull << k) - 1ull;
     int base = 0;
-    for (int c0 = 0; c0 < n; c0 += S) {
-        const int t = c0 + k;
-        bool keep = false;
-        uint32_t gene = 0;
-        if (doit && t < n) {
+    for (int c0 = 0; c0 < n; c0 += U * S) {
+        uint32_t gene[U];
+        bool ok[U];
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            const int t = c0 + u * S + k;
+            ok[u] = doit && t < n;
             int pos = b + 1 + t;
             if (pos >= n) pos -= n;
-            gene = B[pos];
-            const int iv = V[gene];
-            keep = (iv < a) || (iv > b);
+            gene[u] = B[ok[u] ? pos : 0];
         }
-        const uint64_t bal = __ballot(keep);
-        const uint64_t gm = (shift < 64 ? (bal >> shift) : 0ull) & gmask;
-        if (keep) {
-            int dst = b + 1 + base + __popcll(gm & below_me);
-            if (dst >= n) dst -= n;
-            A[dst] = (uint16_t)gene;
+        bool keep[U];
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            const int iv = V[gene[u]];
+            keep[u] = ok[u] && ((iv < a) || (iv > b));
         }
-        base += __popcll(gm);
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            const uint64_t bal = __ballot(keep[u]);
+            const uint64_t gm = (shift < 64 ? (bal >> shift) : 0ull) & gmask;
+            if (keep[u]) {
+                int dst = b + 1 + base + __popcll(gm & below_me);
+                if (dst >= n) dst -= n;
+                A[dst] = (uint16_t)gene[u];
+            }
+            base += __popcll(gm);
+        }
     }
     wave_sync();
 }
