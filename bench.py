@@ -34,7 +34,59 @@ def parse():
     ap.add_argument("--waves-per-block", type=int, default=None)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=12.0)
+    ap.add_argument("--calibrate-copy-mib", type=int, default=0,
+                    help="only run a plain device copy of this many MiB (5 times), to calibrate HBM counters")
     return ap.parse_args()
+
+
+KERNEL_SOURCES = ("ffs_kernels.h", "philox.h")
+
+
+def source_digest(read=None) -> str:
+    """SHA-256 of the device-code sources: traffic counters are only reported
+    for the kernels they were taken on."""
+    import hashlib
+    h = hashlib.sha256()
+    csrc = os.path.join(ROOT, "paper_1903_10722_amd", "csrc")
+    for f in KERNEL_SOURCES:
+        if read is None:
+            with open(os.path.join(csrc, f), "rb") as fh:
+                data = fh.read()
+        else:
+            data = read(f)
+        h.update(f.encode() + b"\0" + data)
+    return h.hexdigest()
+
+
+def recorded_traffic(kernel: str, workload: str):
+    """HBM bytes per launch from the committed rocprofv3 counter summary, or
+    None when the summary is missing or was taken on different sources."""
+    path = os.path.join(ROOT, "profiles", f"{kernel}_{workload}_traffic.txt")
+    if not os.path.exists(path):
+        return None
+    vals = {}
+    with open(path) as fh:
+        for line in fh:
+            if ":" in line:
+                k, v = line.split(":", 1)
+                vals[k.strip()] = v.strip()
+    if vals.get("source_sha256") != source_digest():
+        return None
+    try:
+        return float(vals["hbm_bytes_per_launch"])
+    except (KeyError, ValueError):
+        return None
+
+
+def calibrate_copy(mib: int):
+    import torch
+    src = torch.ones(mib * 1024 * 1024 // 4, dtype=torch.int32, device="cuda")
+    dst = torch.empty_like(src)
+    for _ in range(5):
+        dst.copy_(src)
+    torch.cuda.synchronize()
+    print(json.dumps({"calibration": "device copy", "bytes_read": mib * 1024 * 1024,
+                      "bytes_written": mib * 1024 * 1024, "launches": 5}), flush=True)
 
 
 def cpu_baseline(w, seconds: float) -> dict:
@@ -64,7 +116,9 @@ def main():
         print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}); the island GA of this "
               f"build keeps every island on a single MI355X.", file=sys.stderr)
         sys.exit(2)
-    import numpy as np
+    if args.calibrate_copy_mib:
+        calibrate_copy(args.calibrate_copy_mib)
+        return
     import torch
 
     from paper_1903_10722_amd import Context, inputs
@@ -138,7 +192,7 @@ def main():
         "wall_s_timed": wall,
         "bind_and_generation0_s": t_bind,
         "roofline": {"bound": "alu", "achieved": achieved, "peak": PEAK_INT_TOPS, "unit": "TOP/s",
-                     "frac": achieved / PEAK_INT_TOPS, "traffic": None,
+                     "frac": achieved / PEAK_INT_TOPS, "traffic": recorded_traffic("k_generation", "medium"),
                      "kernel": "k_generation", "avg_launch_us": avg_s * 1e6, "launches": launches,
                      "ops_per_launch": ops_per_launch},
     }

@@ -106,8 +106,16 @@ int ffs_create_instance(ffs_ctx *ctx, int32_t n_jobs, int32_t n_stages,
                         int32_t *out_instance_id);
 
 /* Tile shape of the generation kernels: waves per workgroup (1, 2, 4 or 8).
- * Results never depend on it.  Before ffs_bind_workspace only.              */
+ * Results never depend on it.  May be called before or after
+ * ffs_bind_workspace (after: waits for the stream, then re-plans the
+ * workgroups; FFS_EUNSUPPORTED if the tile does not fit in LDS).            */
 int ffs_set_waves_per_block(ffs_ctx *ctx, int32_t waves);
+
+/* ffs_evolve replays whole migration epochs (or chunks of 16 generations
+ * when nothing migrates) from one captured HIP graph when enable != 0 (the
+ * default), the stream is not the null stream, timing is off, and every
+ * migrating instance has the same interval.  Results are identical.        */
+int ffs_set_graphs(ffs_ctx *ctx, int32_t enable);
 
 /* Device bytes needed by all instances created so far.                      */
 int ffs_workspace_size(const ffs_ctx *ctx, size_t *bytes);

@@ -22,7 +22,7 @@ EXPORTS = [
     "ffs_ctx_create", "ffs_ctx_destroy", "ffs_last_error", "ffs_create_instance",
     "ffs_set_waves_per_block", "ffs_workspace_size", "ffs_bind_workspace", "ffs_evaluate",
     "ffs_evolve", "ffs_migrate", "ffs_best", "ffs_get_population", "ffs_generation",
-    "ffs_migration_counters", "ffs_set_timing", "ffs_kernel_time",
+    "ffs_migration_counters", "ffs_set_graphs", "ffs_set_timing", "ffs_kernel_time",
 ]
 
 
@@ -77,6 +77,7 @@ def load_library():
     lib.ffs_get_population.argtypes = [P, i32, i32, pi32, pi32]
     lib.ffs_generation.argtypes = [P, pi32]
     lib.ffs_migration_counters.argtypes = [P, i32, ctypes.POINTER(i64), ctypes.POINTER(i64)]
+    lib.ffs_set_graphs.argtypes = [P, i32]
     lib.ffs_set_timing.argtypes = [P, i32]
     lib.ffs_kernel_time.argtypes = [P, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(i64)]
     for name in EXPORTS:
@@ -106,7 +107,8 @@ class Context:
         self.lib = load_library()
         self.device = torch.device("cuda", device)
         torch.cuda.set_device(self.device)
-        self.stream = stream if stream is not None else torch.cuda.current_stream(self.device)
+        # a dedicated stream (default priority) so that epochs can be captured as graphs
+        self.stream = stream if stream is not None else torch.cuda.Stream(device=self.device)
         h = ctypes.c_void_p()
         self._check(self.lib.ffs_ctx_create(ctypes.c_void_p(self.stream.cuda_stream), ctypes.byref(h)), None)
         self._h = h
@@ -146,7 +148,9 @@ class Context:
         self._check(self.lib.ffs_create_instance(self._h, n, S, _p32(m), _p32(p), specs, len(islands),
                                                  ctypes.byref(cfg), ctypes.c_uint64(seed), ctypes.byref(out)))
         sizes = [int(x["rows"]) * int(x["cols"]) if int(x["kind"]) == 0 else int(x["size"]) for x in islands]
-        self.instances.append(dict(n=n, S=S, sizes=sizes))
+        self.instances.append(dict(n=n, S=S, sizes=sizes, args=dict(m=m, p=p, islands=[dict(x) for x in islands],
+                                                                     interval=interval, theta=theta,
+                                                                     topology=topology, seed=seed)))
         return out.value
 
     def workspace_size(self) -> int:
@@ -170,6 +174,8 @@ class Context:
         t = t.to(device=self.device, dtype=torch.int32).contiguous()
         count = t.shape[0]
         out = torch.empty(count, dtype=torch.int32, device=self.device)
+        # the input was produced on the caller's stream
+        self.stream.wait_stream(torch.cuda.current_stream(self.device))
         rc = self.lib.ffs_evaluate(self._h, inst, ctypes.c_void_p(t.data_ptr()), count,
                                    ctypes.c_void_p(out.data_ptr()))
         if check:
@@ -209,6 +215,12 @@ class Context:
         b = ctypes.c_int64()
         self._check(self.lib.ffs_migration_counters(self._h, inst, ctypes.byref(a), ctypes.byref(b)))
         return a.value, b.value
+
+    def set_waves_per_block(self, waves: int):
+        self._check(self.lib.ffs_set_waves_per_block(self._h, int(waves)))
+
+    def set_graphs(self, enable: bool):
+        self._check(self.lib.ffs_set_graphs(self._h, 1 if enable else 0))
 
     def set_timing(self, enable: bool):
         self._check(self.lib.ffs_set_timing(self._h, 1 if enable else 0))

@@ -105,6 +105,10 @@ struct ffs_ctx {
     void* keval = nullptr;
     std::vector<WorkItem> work;
     std::vector<PairDesc> pairs;
+    // graph of one migration epoch (or a fixed chunk when nothing migrates)
+    bool use_graphs = true;
+    hipGraphExec_t epoch_exec = nullptr;
+    int epoch_len = 0;
     // timing
     bool timing = false;
     std::vector<hipEvent_t> ev_pool;
@@ -292,6 +296,43 @@ int launch_migration(ffs_ctx* c, int force_inst)
     return FFS_OK;
 }
 
+void drop_graph(ffs_ctx* c)
+{
+    if (c->epoch_exec) (void)hipGraphExecDestroy(c->epoch_exec);
+    c->epoch_exec = nullptr;
+    c->epoch_len = 0;
+}
+
+// Common migration interval of every instance that migrates: >0 the
+// interval, 0 when no instance migrates, -1 when the intervals differ.
+int common_interval(const ffs_ctx* c)
+{
+    int I = 0;
+    for (auto& x : c->inst) {
+        if (x.isl.size() < 2 || x.cfg.migration_interval == 0) continue;
+        if (I == 0) I = x.cfg.migration_interval;
+        else if (I != x.cfg.migration_interval) return -1;
+    }
+    return I;
+}
+
+// Upload the work list of the current tile shape and size the LDS of the
+// generation kernel for it.
+int apply_tile(ffs_ctx* c)
+{
+    int max_lds = 0;
+    HIP_TRY(c, hipDeviceGetAttribute(&max_lds, hipDeviceAttributeMaxSharedMemoryPerBlock, c->device));
+    layout(c);
+    if (c->lds_gen > (size_t)max_lds)
+        return fail(c, FFS_EUNSUPPORTED, "tile of %d waves needs %zu bytes of LDS (limit %d)", c->wpb, c->lds_gen, max_lds);
+    HIP_TRY(c, hipFuncSetAttribute(c->kgen, hipFuncAttributeMaxDynamicSharedMemorySize, (int)c->lds_gen));
+    if (c->n_work)
+        HIP_TRY(c, hipMemcpy(c->ws + c->off_work, c->work.data(), sizeof(WorkItem) * c->work.size(),
+                             hipMemcpyHostToDevice));
+    drop_graph(c);
+    return FFS_OK;
+}
+
 bool migration_due(const ffs_ctx* c, int g)
 {
     for (auto& I : c->inst)
@@ -321,6 +362,7 @@ void ffs_ctx_destroy(ffs_ctx* c)
 {
     if (!c) return;
     if (c->bound) (void)hipStreamSynchronize(c->stream);
+    drop_graph(c);
     for (auto e : c->ev_pool) (void)hipEventDestroy(e);
     for (auto& pr : c->ev_used) {
         (void)hipEventDestroy(pr.first);
@@ -408,9 +450,22 @@ int ffs_create_instance(ffs_ctx* c, int32_t n, int32_t S, const int32_t* machine
 int ffs_set_waves_per_block(ffs_ctx* c, int32_t waves)
 {
     if (!c) return FFS_EINVAL;
-    if (c->bound) return fail(c, FFS_ESTATE, "tile shape is fixed once the workspace is bound");
     if (waves != 1 && waves != 2 && waves != 4 && waves != 8) return fail(c, FFS_EINVAL, "waves must be 1, 2, 4 or 8");
+    if (!c->bound) {
+        c->wpb = waves;
+        return FFS_OK;
+    }
+    // bound: only the work list and the LDS size change; the workspace
+    // layout reserves room for the finest tile
+    HIP_TRY(c, hipStreamSynchronize(c->stream));
+    const int old = c->wpb;
     c->wpb = waves;
+    int rc = apply_tile(c);
+    if (rc) {
+        c->wpb = old;
+        (void)apply_tile(c);
+        return rc;
+    }
     return FFS_OK;
 }
 
@@ -578,7 +633,40 @@ int ffs_evolve(ffs_ctx* c, int32_t generations)
     int rc = check_bound(c);
     if (rc) return rc;
     if (generations < 0) return fail(c, FFS_EINVAL, "generations must be >= 0");
-    for (int it = 0; it < generations; ++it) {
+    const int I = common_interval(c);
+    // whole epochs replay one captured graph: the kernels read the generation
+    // from the control block, so the same graph serves every epoch
+    const bool graphs = c->use_graphs && !c->timing && c->stream != nullptr && I >= 0;
+    const int L = (I > 0) ? I : 16;
+    int left = generations;
+    while (left > 0) {
+        if (graphs && c->gen % L == 0 && left >= L) {
+            if (!c->epoch_exec || c->epoch_len != L) {
+                drop_graph(c);
+                hipGraph_t graph = nullptr;
+                HIP_TRY(c, hipStreamBeginCapture(c->stream, hipStreamCaptureModeRelaxed));
+                int crc = FFS_OK;
+                for (int t = 0; t < L && crc == FFS_OK; ++t) crc = launch_generation(c, 0);
+                if (crc == FFS_OK && I > 0) crc = launch_migration(c, -1);
+                hipError_t ec = hipStreamEndCapture(c->stream, &graph);
+                if (crc) {
+                    if (graph) (void)hipGraphDestroy(graph);
+                    return crc;
+                }
+                if (ec != hipSuccess) return fail(c, FFS_EDEVICE, "hipStreamEndCapture: %s", hipGetErrorString(ec));
+                hipError_t ei = hipGraphInstantiate(&c->epoch_exec, graph, nullptr, nullptr, 0);
+                (void)hipGraphDestroy(graph);
+                if (ei != hipSuccess) {
+                    c->epoch_exec = nullptr;
+                    return fail(c, FFS_EDEVICE, "hipGraphInstantiate: %s", hipGetErrorString(ei));
+                }
+                c->epoch_len = L;
+            }
+            HIP_TRY(c, hipGraphLaunch(c->epoch_exec, c->stream));
+            c->gen += L;
+            left -= L;
+            continue;
+        }
         const int g = c->gen + 1;
         rc = launch_generation(c, 0);
         if (rc) return rc;
@@ -587,6 +675,7 @@ int ffs_evolve(ffs_ctx* c, int32_t generations)
             rc = launch_migration(c, -1);
             if (rc) return rc;
         }
+        --left;
     }
     HIP_TRY(c, hipGetLastError());
     return FFS_OK;
@@ -660,6 +749,14 @@ int ffs_migration_counters(ffs_ctx* c, int32_t inst, int64_t* migrations, int64_
     HIP_TRY(c, hipStreamSynchronize(c->stream));
     if (migrations) *migrations = v[0];
     if (migrants) *migrants = v[1];
+    return FFS_OK;
+}
+
+int ffs_set_graphs(ffs_ctx* c, int32_t enable)
+{
+    if (!c) return FFS_EINVAL;
+    c->use_graphs = enable != 0;
+    if (!c->use_graphs) drop_graph(c);
     return FFS_OK;
 }
 

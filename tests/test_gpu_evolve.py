@@ -204,3 +204,42 @@ def test_stored_makespans_match_redecode():
             assert sorted(genes[r].tolist()) == list(range(w["p"].shape[0]))
         assert np.array_equal(mk[rows], oracle.decode_many(w["m"], w["p"], genes[rows]))
     ctx.close()
+
+
+def test_graph_replay_and_eager_agree():
+    """Epoch graphs (default) and eager launches give the oracle's trajectory;
+    replays are checked after every epoch, with host work in between."""
+    ensure_built()
+    w = inputs.workload("tiny", seed=4)
+    for graphs in (True, False):
+        say(f"[evolve] tiny graphs={graphs}")
+        ctx = make_ctx([w])
+        ctx.set_graphs(graphs)
+        ga = oracle_ga(w)
+        for _ in range(5):
+            ctx.evolve(10)
+            ga.evolve(10)
+            assert_same_state(ctx, ga, 0, 2, f"graphs={graphs} generation {ctx.generation}")
+        ctx.close()
+
+
+def test_tile_change_after_bind_and_autotuner():
+    """Changing the tile shape mid-run (also through the autotuner) keeps the
+    trajectory."""
+    ensure_built()
+    from paper_1903_10722_amd.autotune import autotune
+    w = inputs.workload("medium", seed=3, scale=4)
+    say("[evolve] tile change after bind")
+    ctx = make_ctx([w])
+    ga = oracle_ga(w)
+    for wpb in (2, 8, 1):
+        ctx.set_waves_per_block(wpb)
+        ctx.evolve(7)
+        ga.evolve(7)
+        assert_same_state(ctx, ga, 0, 2, f"waves_per_block={wpb}")
+    res = autotune(ctx, generations=10, use_cache=False)
+    assert res["waves_per_block"] in (1, 2, 4, 8)
+    ctx.evolve(13)
+    ga.evolve(13)
+    assert_same_state(ctx, ga, 0, 2, "after autotune")
+    ctx.close()
