@@ -86,6 +86,8 @@ def _load():
     lib.or_ga_counters.argtypes = [ctypes.c_void_p, _i64p, _i64p]
     lib.or_ga_set_generation.argtypes = [ctypes.c_void_p, ctypes.c_int]
     lib.or_ga_step_island.argtypes = [ctypes.c_void_p, ctypes.c_int]
+    lib.or_ga_cell_candidate.argtypes = [ctypes.c_void_p, ctypes.c_int, ctypes.c_int, ctypes.c_int, _i32p, _i32p]
+    lib.or_ga_set_cell_choices.argtypes = [ctypes.c_void_p, ctypes.c_int, _i32p]
     _lib = lib
     return lib
 
@@ -225,6 +227,23 @@ class GA:
     def step_island(self, island: int):
         """Next generation of one island only (no migration, counters kept)."""
         self._lib.or_ga_step_island(self._h, island)
+
+    def cell_candidate(self, island: int, slot: int, sub: int):
+        """(child, meta) of a cell at the next generation from candidate stream
+        `sub`; meta = (p1, p2, crossover, a, b, mutation, i, j)."""
+        child = np.zeros(self.n, dtype=np.int32)
+        meta = np.zeros(8, dtype=np.int32)
+        self._lib.or_ga_cell_candidate(self._h, island, slot, sub, _ptr(child, _i32p), _ptr(meta, _i32p))
+        return child, meta
+
+    def set_cell_choices(self, island: int, choices):
+        """Candidate stream per cell for the next generation only."""
+        if choices is None:
+            self._lib.or_ga_set_cell_choices(self._h, island, None)
+        else:
+            c = _i32(choices)
+            assert c.shape == (self.sizes[island],)
+            self._lib.or_ga_set_cell_choices(self._h, island, _ptr(c, _i32p))
 
     def best(self):
         mk = ctypes.c_int64()

@@ -260,6 +260,7 @@ typedef struct {
     int best_gen, best_island, best_slot;
     int *best_perm;
     int64_t migrations, migrants;  /* counters, for tests */
+    int **choice;                  /* per island: candidate stream of each cell for the next step, or NULL */
 } or_ga_t;
 
 static int64_t dec(or_ga_t *g, const int *perm)
@@ -301,6 +302,7 @@ void *or_ga_create(int n, int S, const int *m, const int *p, int n_islands,
     g->seed = seed; g->inst = inst;
     g->best_perm = (int *)malloc(sizeof(int) * (size_t)n);
     g->best_island = -1;
+    g->choice = (int **)calloc((size_t)n_islands, sizeof(int *));
     for (int i = 0; i < n_islands; ++i) {
         or_island_t *I = &g->isl[i];
         I->kind = kinds[i];
@@ -332,7 +334,8 @@ void *or_ga_create(int n, int S, const int *m, const int *p, int n_islands,
 void or_ga_destroy(void *h)
 {
     or_ga_t *g = (or_ga_t *)h;
-    for (int i = 0; i < g->n_islands; ++i) { free(g->isl[i].genes); free(g->isl[i].mk); }
+    for (int i = 0; i < g->n_islands; ++i) { free(g->isl[i].genes); free(g->isl[i].mk); free(g->choice[i]); }
+    free(g->choice);
     free(g->isl); free(g->m); free(g->p); free(g->best_perm); free(g);
 }
 
@@ -342,6 +345,58 @@ static void swap_mutation(int n, int *x, uint32_t dflag, uint32_t di, uint32_t d
     int i = (int)uniform_below(di, (uint32_t)n);
     int j = (i + 1 + (int)uniform_below(dj, (uint32_t)(n > 1 ? n - 1 : 0))) % n;
     int t = x[i]; x[i] = x[j]; x[j] = t;
+}
+
+/* Offspring of cell s at generation g->gen from candidate stream `sub` of
+ * the CELL purpose (sub 0 is the plain GA's only stream).  meta (may be NULL)
+ * receives p1, p2, crossover flag, a, b, mutation flag, i, j.              */
+static void cell_offspring(or_ga_t *g, int island, int s, int sub, int *child, int *meta)
+{
+    or_island_t *I = &g->isl[island];
+    int n = g->n;
+    int p1, p2;
+    or_cell_parents(I->rows, I->cols, I->mk, s, &p1, &p2);
+    uint32_t d[6];
+    for (int t = 0; t < 6; ++t)
+        d[t] = or_draw(g->seed, g->inst, (uint32_t)island, (uint32_t)s, (uint32_t)sub, (uint32_t)g->gen, OR_CELL,
+                       (uint32_t)t);
+    const int *P1 = I->genes + (size_t)p1 * n, *P2 = I->genes + (size_t)p2 * n;
+    int cx = (uint64_t)d[0] < I->tc;
+    int u = (int)uniform_below(d[1], (uint32_t)n), v = (int)uniform_below(d[2], (uint32_t)n);
+    int a = u < v ? u : v, b = u < v ? v : u;
+    if (cx) or_ox(n, P1, P2, a, b, child);
+    else memcpy(child, P1, sizeof(int) * (size_t)n);
+    swap_mutation(n, child, d[3], d[4], d[5], I->tm);
+    if (meta) {
+        int mx = (uint64_t)d[3] < I->tm;
+        int mi = (int)uniform_below(d[4], (uint32_t)n);
+        int mj = (mi + 1 + (int)uniform_below(d[5], (uint32_t)(n > 1 ? n - 1 : 0))) % n;
+        meta[0] = p1; meta[1] = p2; meta[2] = cx; meta[3] = a; meta[4] = b;
+        meta[5] = mx; meta[6] = mi; meta[7] = mj;
+    }
+}
+
+/* Test access: the offspring a cell would get at the next generation from
+ * candidate stream `sub`, with its meta data (see cell_offspring).          */
+void or_ga_cell_candidate(void *h, int island, int slot, int sub, int *child, int *meta)
+{
+    or_ga_t *g = (or_ga_t *)h;
+    g->gen += 1;
+    cell_offspring(g, island, slot, sub, child, meta);
+    g->gen -= 1;
+}
+
+/* Candidate stream of every cell of `island` for the next generation only
+ * (the choice of a learned pre-screen, replayed); NULL restores stream 0.  */
+void or_ga_set_cell_choices(void *h, int island, const int *choices)
+{
+    or_ga_t *g = (or_ga_t *)h;
+    free(g->choice[island]);
+    g->choice[island] = NULL;
+    if (choices) {
+        g->choice[island] = (int *)malloc(sizeof(int) * (size_t)g->isl[island].size);
+        memcpy(g->choice[island], choices, sizeof(int) * (size_t)g->isl[island].size);
+    }
 }
 
 /* one generation of a cellular island, synchronous (reads generation g-1
@@ -354,20 +409,8 @@ static void cellular_step(or_ga_t *g, int island)
     int *nm = (int *)malloc(sizeof(int) * (size_t)I->size);
     int *child = (int *)malloc(sizeof(int) * (size_t)n);
     for (int s = 0; s < I->size; ++s) {
-        int p1, p2;
-        or_cell_parents(I->rows, I->cols, I->mk, s, &p1, &p2);
-        uint32_t d[6];
-        for (int t = 0; t < 6; ++t)
-            d[t] = or_draw(g->seed, g->inst, (uint32_t)island, (uint32_t)s, 0, (uint32_t)g->gen, OR_CELL, (uint32_t)t);
-        const int *P1 = I->genes + (size_t)p1 * n, *P2 = I->genes + (size_t)p2 * n;
-        if ((uint64_t)d[0] < I->tc) {
-            int u = (int)uniform_below(d[1], (uint32_t)n), v = (int)uniform_below(d[2], (uint32_t)n);
-            int a = u < v ? u : v, b = u < v ? v : u;
-            or_ox(n, P1, P2, a, b, child);
-        } else {
-            memcpy(child, P1, sizeof(int) * (size_t)n);
-        }
-        swap_mutation(n, child, d[3], d[4], d[5], I->tm);
+        int sub = g->choice[island] ? g->choice[island][s] : 0;
+        cell_offspring(g, island, s, sub, child, NULL);
         int cm = (int)dec(g, child);
         if (cm < I->mk[s]) {
             memcpy(ng + (size_t)s * n, child, sizeof(int) * (size_t)n);
@@ -379,6 +422,8 @@ static void cellular_step(or_ga_t *g, int island)
     }
     free(I->genes); free(I->mk); free(child);
     I->genes = ng; I->mk = nm;
+    free(g->choice[island]);
+    g->choice[island] = NULL;
 }
 
 /* one generation of a pseudo island: per pair, the better parent X and its

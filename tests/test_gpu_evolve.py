@@ -243,3 +243,33 @@ def test_tile_change_after_bind_and_autotuner():
     ga.evolve(13)
     assert_same_state(ctx, ga, 0, 2, "after autotune")
     ctx.close()
+
+
+def test_batched_full_size_256_instances():
+    """The uneven batch at full size: 256 instances (n in {20..500}, S in
+    {5,10,20}, grids 32x32 .. 128x128) in one context, migration every 10.
+    After 10 generations (one epoch, graph-replayed) the 12 cheapest instances
+    match their oracle runs exactly; for 8 others, sampled individuals are
+    valid permutations whose stored makespans equal the oracle's decode."""
+    ensure_built()
+    ws = inputs.batched_workloads(count=256, batch_seed=7)
+    say("[evolve] batched full size, 256 instances")
+    ctx = make_ctx(ws)
+    ctx.evolve(10)
+    cost = [w["p"].shape[0] * w["p"].shape[1] * w["islands"][0]["size"] for w in ws]
+    order = np.argsort(cost)
+    for i in order[:12]:
+        ga = oracle_ga(ws[i], inst=int(i))
+        ga.evolve(10)
+        assert_same_state(ctx, ga, int(i), 2, f"instance {i} n={ws[i]['p'].shape}")
+        assert ctx.best(int(i))["makespan"] == ga.best()["makespan"]
+    rng = np.random.default_rng(0)
+    for i in order[-8:]:
+        w = ws[int(i)]
+        for isl in range(2):
+            genes, mk = ctx.population(int(i), isl)
+            rows = rng.choice(len(mk), 6, replace=False)
+            for r in rows:
+                assert sorted(genes[r].tolist()) == list(range(w["p"].shape[0]))
+            assert np.array_equal(mk[rows], oracle.decode_many(w["m"], w["p"], genes[rows]))
+    ctx.close()
