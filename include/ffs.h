@@ -80,6 +80,18 @@ typedef struct {
     int32_t migration_interval;
     int32_t topology;
     double theta;         /* in [0, 1]; the paper's experiments use 1.0       */
+    /* Learned pre-screen of the cellular island (0 or 1 = off, 2..64 = on; at
+     * most one instance per context).  Each cell builds `surrogate_k`
+     * candidate children from candidate streams 0..k-1 (stream 0 is the
+     * plain GA's), a 256-512-512-1 BF16 MLP ranks them, and only the best
+     * ranked one is decoded exactly and replaces the cell if strictly
+     * better.  The first `surrogate_warmup` generations use stream 0 only.
+     * After every generation each decoded cellular child (features, exact
+     * (C - LB) / LB) enters a replay ring of 65536 rows and the network
+     * takes one Adam step (lr 1e-3) on 4096 rows sampled from it.  Makespans
+     * always come from exact decodes.                                       */
+    int32_t surrogate_k;
+    int32_t surrogate_warmup;
 } ffs_ga_config;
 
 /* Create / destroy a context bound to a HIP stream (hipStream_t as void*;
@@ -168,6 +180,58 @@ int ffs_migration_counters(ffs_ctx *ctx, int32_t inst, int64_t *migrations, int6
  * the summed milliseconds and the launch count since enabling.  (syncs)     */
 int ffs_set_timing(ffs_ctx *ctx, int32_t enable);
 int ffs_kernel_time(ffs_ctx *ctx, double *total_ms, int64_t *launches);
+
+/* ---- learned pre-screen (instances with surrogate_k > 1) ------------------
+ * Parameters: one FP32 vector of 394753 values, W1 [512][256] (row = output
+ * unit), b1 [512], W2 [512][512], b2 [512], w3 [512], b3 [1]; the products
+ * use BF16 copies of W1, W2, w3 with FP32 accumulation (MFMA).  Features:
+ * BF16 rows of 256 (uint16 bit patterns): for B = floor(240 / S) position
+ * buckets (position t in bucket floor(t B / n)) and stage k, entry b*S + k =
+ * B * (processing time at stage k of the jobs in bucket b) / (stage k's total
+ * processing time); entries 240..251: parents' makespans / LB, cut points /
+ * n, crossover and mutation flags, swap positions / n, LB / sum(p), n / 1000,
+ * S / 20, sum(m) / (6 S); the rest 0.  LB = max(max_k ceil(P_k / m_k),
+ * max_j sum_k p_jk).  Every ratio is one correctly rounded FP32 division.   */
+
+/* Copy the FP32 parameters out / in (in: the BF16 copies are refreshed, the
+ * Adam moments kept).  host: float [394753].  (syncs)                       */
+int ffs_surrogate_params(ffs_ctx *ctx, int32_t inst, float *host);
+int ffs_surrogate_set_params(ffs_ctx *ctx, int32_t inst, const float *host);
+
+/* Forward pass of `rows` rows (positive multiple of 128).  X: device BF16
+ * [rows][256]; y: device float [rows]; H1, H2: device BF16 [rows][512]
+ * receiving the hidden activations (may be NULL when rows <= 4096).  (syncs) */
+int ffs_mlp_forward(ffs_ctx *ctx, int32_t inst, const uint16_t *X, int32_t rows, float *y, uint16_t *H1,
+                    uint16_t *H2);
+
+/* Gradients of mean((y - t)^2) over rows (multiple of 128, <= 4096) without
+ * an update.  X: device BF16 [rows][256]; t: device float [rows]; grad:
+ * device float [394753] in the parameter layout; dZ2, dZ1: device BF16
+ * [rows][512] receiving the back-propagated pre-activation gradients of
+ * layers 2 and 1 (may be NULL).  (syncs)                                    */
+int ffs_mlp_gradients(ffs_ctx *ctx, int32_t inst, const uint16_t *X, const float *t, int32_t rows, float *grad,
+                      uint16_t *dZ2, uint16_t *dZ1);
+
+/* One training step (gradients as above, then Adam) on caller data.  (syncs) */
+int ffs_mlp_train_step(ffs_ctx *ctx, int32_t inst, const uint16_t *X, const float *t, int32_t rows);
+
+/* Score the candidates the next generation would consider: X_host BF16
+ * [cells * k][256] (row cell * k + c), pred_host float [cells * k],
+ * exact_host float [cells * k] (exact (C - LB) / LB of every candidate, only
+ * when exact != 0), choice_host int32 [cells].  Cells are numbered over the
+ * instance's cellular islands in island order, row-major within a grid.
+ * Any output may be NULL.  The population is not changed.  (syncs)          */
+int ffs_surrogate_candidates(ffs_ctx *ctx, int32_t inst, int32_t exact, uint16_t *X_host, float *pred_host,
+                             float *exact_host, int32_t *choice_host);
+
+/* Candidate stream each cell used in the last screened generation (int32
+ * [cells]).  (syncs)                                                        */
+int ffs_surrogate_choices(ffs_ctx *ctx, int32_t inst, int32_t *host);
+
+/* Rows [first, first + count) of the replay ring (features BF16 [count][256],
+ * targets float [count]); row ((g - 1) * cells + cell) mod 65536 holds the
+ * child decoded for `cell` in generation g.  (syncs)                        */
+int ffs_surrogate_ring(ffs_ctx *ctx, int32_t inst, int32_t first, int32_t count, uint16_t *X_host, float *t_host);
 
 #ifdef __cplusplus
 }

@@ -23,7 +23,13 @@ EXPORTS = [
     "ffs_set_waves_per_block", "ffs_workspace_size", "ffs_bind_workspace", "ffs_evaluate",
     "ffs_evolve", "ffs_migrate", "ffs_best", "ffs_get_population", "ffs_generation",
     "ffs_migration_counters", "ffs_set_graphs", "ffs_set_timing", "ffs_kernel_time",
+    "ffs_surrogate_params", "ffs_surrogate_set_params", "ffs_mlp_forward", "ffs_mlp_gradients",
+    "ffs_mlp_train_step", "ffs_surrogate_candidates", "ffs_surrogate_choices", "ffs_surrogate_ring",
 ]
+
+N_PARAMS = 394753
+PARAM_SLICES = {"W1": (0, (512, 256)), "b1": (131072, (512,)), "W2": (131584, (512, 512)),
+                "b2": (393728, (512,)), "w3": (394240, (512,)), "b3": (394752, (1,))}
 
 
 class FFSError(RuntimeError):
@@ -39,7 +45,8 @@ class IslandSpec(ctypes.Structure):
 
 class GAConfig(ctypes.Structure):
     _fields_ = [("migration_interval", ctypes.c_int32), ("topology", ctypes.c_int32),
-                ("theta", ctypes.c_double)]
+                ("theta", ctypes.c_double), ("surrogate_k", ctypes.c_int32),
+                ("surrogate_warmup", ctypes.c_int32)]
 
 
 _lib = None
@@ -80,6 +87,16 @@ def load_library():
     lib.ffs_set_graphs.argtypes = [P, i32]
     lib.ffs_set_timing.argtypes = [P, i32]
     lib.ffs_kernel_time.argtypes = [P, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(i64)]
+    pf32 = ctypes.POINTER(ctypes.c_float)
+    pu16 = ctypes.POINTER(ctypes.c_uint16)
+    lib.ffs_surrogate_params.argtypes = [P, i32, pf32]
+    lib.ffs_surrogate_set_params.argtypes = [P, i32, pf32]
+    lib.ffs_mlp_forward.argtypes = [P, i32, P, i32, P, P, P]
+    lib.ffs_mlp_gradients.argtypes = [P, i32, P, P, i32, P, P, P]
+    lib.ffs_mlp_train_step.argtypes = [P, i32, P, P, i32]
+    lib.ffs_surrogate_candidates.argtypes = [P, i32, i32, pu16, pf32, pf32, pi32]
+    lib.ffs_surrogate_choices.argtypes = [P, i32, pi32]
+    lib.ffs_surrogate_ring.argtypes = [P, i32, i32, i32, pu16, pf32]
     for name in EXPORTS:
         if name not in ("ffs_ctx_destroy", "ffs_last_error"):
             getattr(lib, name).restype = ctypes.c_int
@@ -135,7 +152,7 @@ class Context:
             pass
 
     def add_instance(self, m, p, islands, interval: int, theta: float = 1.0, topology: int = 0,
-                     seed: int = 1) -> int:
+                     seed: int = 1, surrogate_k: int = 0, surrogate_warmup: int = 5) -> int:
         m = _i32(m)
         p = _i32(p)
         n, S = p.shape
@@ -143,14 +160,16 @@ class Context:
         for i, x in enumerate(islands):
             specs[i] = IslandSpec(int(x["kind"]), int(x.get("rows", 0)), int(x.get("cols", 0)),
                                   int(x.get("size", 0)), float(x["pc"]), float(x["pm"]))
-        cfg = GAConfig(int(interval), int(topology), float(theta))
+        cfg = GAConfig(int(interval), int(topology), float(theta), int(surrogate_k), int(surrogate_warmup))
         out = ctypes.c_int32()
         self._check(self.lib.ffs_create_instance(self._h, n, S, _p32(m), _p32(p), specs, len(islands),
                                                  ctypes.byref(cfg), ctypes.c_uint64(seed), ctypes.byref(out)))
         sizes = [int(x["rows"]) * int(x["cols"]) if int(x["kind"]) == 0 else int(x["size"]) for x in islands]
         self.instances.append(dict(n=n, S=S, sizes=sizes, args=dict(m=m, p=p, islands=[dict(x) for x in islands],
                                                                      interval=interval, theta=theta,
-                                                                     topology=topology, seed=seed)))
+                                                                     topology=topology, seed=seed,
+                                                                     surrogate_k=surrogate_k,
+                                                                     surrogate_warmup=surrogate_warmup)))
         return out.value
 
     def workspace_size(self) -> int:
@@ -230,3 +249,75 @@ class Context:
         n = ctypes.c_int64()
         self._check(self.lib.ffs_kernel_time(self._h, ctypes.byref(ms), ctypes.byref(n)))
         return ms.value, n.value
+
+    # ---- learned pre-screen -------------------------------------------------
+    def _ptr(self, t):
+        return ctypes.c_void_p(t.data_ptr()) if t is not None else None
+
+    def surrogate_params(self, inst: int = 0) -> np.ndarray:
+        out = np.zeros(N_PARAMS, dtype=np.float32)
+        self._check(self.lib.ffs_surrogate_params(self._h, inst, out.ctypes.data_as(ctypes.POINTER(ctypes.c_float))))
+        return out
+
+    def set_surrogate_params(self, params, inst: int = 0):
+        a = np.ascontiguousarray(np.asarray(params, dtype=np.float32))
+        assert a.shape == (N_PARAMS,)
+        self._check(self.lib.ffs_surrogate_set_params(self._h, inst, a.ctypes.data_as(ctypes.POINTER(ctypes.c_float))))
+
+    def mlp_forward(self, X, inst: int = 0):
+        """X: torch uint16-as-int16 BF16 bits [rows][256] on the device -> (y, H1, H2)."""
+        torch = self._torch
+        rows = X.shape[0]
+        y = torch.empty(rows, dtype=torch.float32, device=self.device)
+        H1 = torch.empty((rows, 512), dtype=torch.int16, device=self.device)
+        H2 = torch.empty((rows, 512), dtype=torch.int16, device=self.device)
+        self.stream.wait_stream(torch.cuda.current_stream(self.device))
+        self._check(self.lib.ffs_mlp_forward(self._h, inst, self._ptr(X), rows, self._ptr(y), self._ptr(H1), self._ptr(H2)))
+        return y, H1, H2
+
+    def mlp_gradients(self, X, t, inst: int = 0):
+        torch = self._torch
+        rows = X.shape[0]
+        g = torch.empty(N_PARAMS, dtype=torch.float32, device=self.device)
+        dZ2 = torch.empty((rows, 512), dtype=torch.int16, device=self.device)
+        dZ1 = torch.empty((rows, 512), dtype=torch.int16, device=self.device)
+        self.stream.wait_stream(torch.cuda.current_stream(self.device))
+        self._check(self.lib.ffs_mlp_gradients(self._h, inst, self._ptr(X), self._ptr(t), rows, self._ptr(g),
+                                               self._ptr(dZ2), self._ptr(dZ1)))
+        return g, dZ2, dZ1
+
+    def mlp_train_step(self, X, t, inst: int = 0):
+        torch = self._torch
+        self.stream.wait_stream(torch.cuda.current_stream(self.device))
+        self._check(self.lib.ffs_mlp_train_step(self._h, inst, self._ptr(X), self._ptr(t), X.shape[0]))
+
+    def surrogate_candidates(self, inst: int = 0, exact: bool = False, features: bool = False):
+        info = self.instances[inst]
+        k = int(info["args"]["surrogate_k"])
+        cells = sum(s for s, x in zip(info["sizes"], info["args"]["islands"]) if int(x["kind"]) == 0)
+        pred = np.zeros(cells * k, dtype=np.float32)
+        ex = np.zeros(cells * k, dtype=np.float32) if exact else None
+        X = np.zeros((cells * k, 256), dtype=np.uint16) if features else None
+        ch = np.zeros(cells, dtype=np.int32)
+        pf = ctypes.POINTER(ctypes.c_float)
+        self._check(self.lib.ffs_surrogate_candidates(
+            self._h, inst, 1 if exact else 0,
+            X.ctypes.data_as(ctypes.POINTER(ctypes.c_uint16)) if X is not None else None,
+            pred.ctypes.data_as(pf), ex.ctypes.data_as(pf) if ex is not None else None, _p32(ch)))
+        return dict(pred=pred.reshape(cells, k), exact=None if ex is None else ex.reshape(cells, k),
+                    features=None if X is None else X.reshape(cells, k, 256), choice=ch)
+
+    def surrogate_choices(self, inst: int = 0) -> np.ndarray:
+        info = self.instances[inst]
+        cells = sum(s for s, x in zip(info["sizes"], info["args"]["islands"]) if int(x["kind"]) == 0)
+        ch = np.zeros(cells, dtype=np.int32)
+        self._check(self.lib.ffs_surrogate_choices(self._h, inst, _p32(ch)))
+        return ch
+
+    def surrogate_ring(self, first: int, count: int, inst: int = 0):
+        X = np.zeros((count, 256), dtype=np.uint16)
+        t = np.zeros(count, dtype=np.float32)
+        self._check(self.lib.ffs_surrogate_ring(self._h, inst, first, count,
+                                                X.ctypes.data_as(ctypes.POINTER(ctypes.c_uint16)),
+                                                t.ctypes.data_as(ctypes.POINTER(ctypes.c_float))))
+        return X, t

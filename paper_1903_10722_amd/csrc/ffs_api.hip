@@ -25,6 +25,7 @@ namespace {
 struct HostIsland {
     ffs_island_spec spec;
     int size;
+    int cell_base;
     size_t off_genes[2], off_mk[2], off_genkey, off_minmax, off_sorted;
 };
 
@@ -36,6 +37,9 @@ struct HostInstance {
     std::vector<HostIsland> isl;
     ffs_ga_config cfg;
     uint64_t seed;
+    long long LB;
+    int msum, n_cells;
+    std::vector<long long> Pk;
     size_t off_pT, off_best_perm, off_best_rec, off_counters;
 };
 
@@ -46,6 +50,8 @@ template <int M, typename PT>
 void* gen_ptr() { return reinterpret_cast<void*>(&k_generation<M, PT>); }
 template <int M, typename PT>
 void* eval_ptr() { return reinterpret_cast<void*>(&k_evaluate<M, PT>); }
+template <int M, typename PT>
+void* cand_ptr() { return reinterpret_cast<void*>(&k_candidates<M, PT>); }
 
 const int kMmaxList[] = {2, 3, 4, 5, 6, 8, 16};
 
@@ -53,6 +59,15 @@ void* pick_gen(int mm, int ptb)
 {
 #define FFS_CASE(M)                                                          \
     if (mm == M) return ptb == 1 ? gen_ptr<M, uint8_t>() : gen_ptr<M, uint16_t>();
+    FFS_CASE(2) FFS_CASE(3) FFS_CASE(4) FFS_CASE(5) FFS_CASE(6) FFS_CASE(8) FFS_CASE(16)
+#undef FFS_CASE
+    return nullptr;
+}
+
+void* pick_cand(int mm, int ptb)
+{
+#define FFS_CASE(M)                                                          \
+    if (mm == M) return ptb == 1 ? cand_ptr<M, uint8_t>() : cand_ptr<M, uint16_t>();
     FFS_CASE(2) FFS_CASE(3) FFS_CASE(4) FFS_CASE(5) FFS_CASE(6) FFS_CASE(8) FFS_CASE(16)
 #undef FFS_CASE
     return nullptr;
@@ -75,6 +90,10 @@ int round_mmax(int m)
 }
 
 size_t al256(size_t x) { return (x + 255) & ~(size_t)255; }
+
+constexpr int kBatch = 4096;    // training minibatch of the pre-screen
+constexpr int kRing = 65536;    // replay ring entries
+constexpr float kLr = 1e-3f, kBeta1 = 0.9f, kBeta2 = 0.999f, kEps = 1e-8f;
 
 uint64_t rate_threshold(double p)
 {
@@ -105,6 +124,15 @@ struct ffs_ctx {
     void* keval = nullptr;
     std::vector<WorkItem> work;
     std::vector<PairDesc> pairs;
+    // learned pre-screen (at most one instance per context)
+    int surr = -1;                 // instance with the pre-screen, or -1
+    int surr_K = 0, surr_warmup = 0, surr_cells = 0, surr_Nc = 0, surr_Ncp = 0;
+    long long adam_steps = 0;
+    void* kcand = nullptr;
+    size_t o_w = 0, o_wb = 0, o_m = 0, o_v = 0, o_g = 0;
+    size_t o_Xall = 0, o_H1all = 0, o_H2all = 0, o_yall = 0, o_Tall = 0, o_choice = 0;
+    size_t o_idx = 0, o_Xb = 0, o_tb = 0, o_H1b = 0, o_H2b = 0, o_yb = 0, o_dy = 0, o_dZ2 = 0, o_dZ1 = 0;
+    size_t o_part = 0, o_cpart = 0, o_dpart = 0, o_ringX = 0, o_ringT = 0;
     // graph of one migration epoch (or a fixed chunk when nothing migrates)
     bool use_graphs = true;
     hipGraphExec_t epoch_exec = nullptr;
@@ -221,6 +249,44 @@ void layout(ffs_ctx* c)
     int P = 1;
     while (P < c->max_size) P <<= 1;
     c->lds_sort = (size_t)P * 8;
+    // learned pre-screen: parameters, scoring and training buffers, replay ring
+    c->surr = -1;
+    for (size_t ii = 0; ii < c->inst.size(); ++ii)
+        if (c->inst[ii].cfg.surrogate_k > 1) c->surr = (int)ii;
+    if (c->surr >= 0) {
+        const auto& I = c->inst[c->surr];
+        c->surr_K = I.cfg.surrogate_k;
+        c->surr_warmup = I.cfg.surrogate_warmup;
+        c->surr_cells = I.n_cells;
+        c->surr_Nc = I.n_cells * c->surr_K;
+        c->surr_Ncp = (c->surr_Nc + 127) / 128 * 128;
+        const size_t Pn = kParams, Ncp = c->surr_Ncp, Bt = kBatch;
+        c->o_w = take(Pn * 4);
+        c->o_wb = take(Pn * 2);
+        c->o_m = take(Pn * 4);
+        c->o_v = take(Pn * 4);
+        c->o_g = take(Pn * 4);
+        c->o_Xall = take(Ncp * kFeat * 2);
+        c->o_H1all = take(Ncp * kHidden * 2);
+        c->o_H2all = take(Ncp * kHidden * 2);
+        c->o_yall = take(Ncp * 4);
+        c->o_Tall = take(Ncp * 4);
+        c->o_choice = take((size_t)I.n_cells * 4);
+        c->o_idx = take(Bt * 4);
+        c->o_Xb = take(Bt * kFeat * 2);
+        c->o_tb = take(Bt * 4);
+        c->o_H1b = take(Bt * kHidden * 2);
+        c->o_H2b = take(Bt * kHidden * 2);
+        c->o_yb = take(Bt * 4);
+        c->o_dy = take(Bt * 4);
+        c->o_dZ2 = take(Bt * kHidden * 2);
+        c->o_dZ1 = take(Bt * kHidden * 2);
+        c->o_part = take((size_t)(kBatch / 128) * kHidden * kHidden * 4);
+        c->o_cpart = take((size_t)(kBatch / 64) * kHidden * 4);
+        c->o_dpart = take((size_t)(kBatch / 64) * 4);
+        c->o_ringX = take((size_t)kRing * kFeat * 2);
+        c->o_ringT = take((size_t)kRing * 4);
+    }
     c->total = off;
 }
 
@@ -333,6 +399,143 @@ int apply_tile(ffs_ctx* c)
     return FFS_OK;
 }
 
+template <bool TA, bool TB, int EPI>
+int gemm(ffs_ctx* c, const uint16_t* A, const uint16_t* B, int M, int N, int K, int lda, int ldb, float* Cf,
+         uint16_t* Cb, int ldc, const float* bias, const uint16_t* mask, int splits)
+{
+    if (M % GBM || N % GBN || K % (GBK * splits))
+        return fail(c, FFS_EINVAL, "gemm shape %dx%dx%d (splits %d) not tiled", M, N, K, splits);
+    hipLaunchKernelGGL((k_gemm<TA, TB, EPI>), dim3(N / GBN, M / GBM, splits), dim3(256), 0, c->stream, A, B, M, N, K,
+                       lda, ldb, Cf, Cb, ldc, bias, mask);
+    return FFS_OK;
+}
+
+template <typename T>
+T* at(ffs_ctx* c, size_t off) { return reinterpret_cast<T*>(c->ws + off); }
+
+// y = MLP(X) for `rows` rows (multiple of 128; the output layer covers the
+// first out_rows); H1, H2 receive the hidden activations; with K > 0 also
+// choice[cell] = argmin over each cell's K consecutive rows.
+int mlp_forward(ffs_ctx* c, const uint16_t* X, int rows, uint16_t* H1, uint16_t* H2, float* y, int K, int* choice,
+                int out_rows)
+{
+    const float* w = at<float>(c, c->o_w);
+    const uint16_t* wb = at<uint16_t>(c, c->o_wb);
+    int rc = gemm<false, true, EPI_BIAS_RELU_BF16>(c, X, wb + kP_W1, rows, kHidden, kFeat, kFeat, kFeat, nullptr, H1,
+                                                   kHidden, w + kP_b1, nullptr, 1);
+    if (rc) return rc;
+    rc = gemm<false, true, EPI_BIAS_RELU_BF16>(c, H1, wb + kP_W2, rows, kHidden, kHidden, kHidden, kHidden, nullptr, H2,
+                                               kHidden, w + kP_b2, nullptr, 1);
+    if (rc) return rc;
+    const int waves = (K > 0) ? out_rows / K : out_rows;
+    hipLaunchKernelGGL(k_mlp_out, dim3((waves + 3) / 4), dim3(256), 0, c->stream, H2, wb + kP_w3, w + kP_b3,
+                       K > 0 ? waves * K : out_rows, K, y, choice);
+    return FFS_OK;
+}
+
+// column sums of a [rows][cols] BF16 matrix (optionally weighted by dy) into
+// out[cols] (and sum(dy) into *dsum), deterministic two-stage order
+int colsum(ffs_ctx* c, const uint16_t* X, const float* dy, int rows, int cols, float* out, float* dsum)
+{
+    const int chunks = rows / 64;
+    float* part = at<float>(c, c->o_cpart);
+    float* dpart = at<float>(c, c->o_dpart);
+    hipLaunchKernelGGL(k_colsum, dim3((cols + 255) / 256, chunks), dim3(256), 0, c->stream, X, dy, rows, cols, part,
+                       dsum ? dpart : nullptr);
+    hipLaunchKernelGGL(k_sum_splits, dim3((cols + 255) / 256), dim3(256), 0, c->stream, part, chunks, (size_t)cols,
+                       out);
+    if (dsum)
+        hipLaunchKernelGGL(k_sum_splits, dim3(1), dim3(256), 0, c->stream, dpart, chunks, (size_t)1, dsum);
+    return FFS_OK;
+}
+
+// Gradients of mean((y - t)^2) for `rows` rows of X into grad (parameter
+// layout).  H1, H2, y, dZ2, dZ1 are the batch buffers unless given.
+int mlp_gradients(ffs_ctx* c, const uint16_t* X, const float* t, int rows, float* grad, uint16_t* dZ2o,
+                  uint16_t* dZ1o)
+{
+    if (rows < 128 || rows > kBatch || rows % 128) return fail(c, FFS_EINVAL, "rows must be a multiple of 128 in [128, %d]", kBatch);
+    uint16_t* H1 = at<uint16_t>(c, c->o_H1b);
+    uint16_t* H2 = at<uint16_t>(c, c->o_H2b);
+    float* y = at<float>(c, c->o_yb);
+    float* dy = at<float>(c, c->o_dy);
+    uint16_t* dZ2 = dZ2o ? dZ2o : at<uint16_t>(c, c->o_dZ2);
+    uint16_t* dZ1 = dZ1o ? dZ1o : at<uint16_t>(c, c->o_dZ1);
+    const uint16_t* wb = at<uint16_t>(c, c->o_wb);
+    float* part = at<float>(c, c->o_part);
+    int rc = mlp_forward(c, X, rows, H1, H2, y, 0, nullptr, rows);
+    if (rc) return rc;
+    hipLaunchKernelGGL(k_mlp_dz2, dim3(rows * kHidden / 256), dim3(256), 0, c->stream, y, t, H2, wb + kP_w3, rows, dy,
+                       dZ2);
+    colsum(c, H2, dy, rows, kHidden, grad + kP_w3, grad + kP_b3);
+    colsum(c, dZ2, nullptr, rows, kHidden, grad + kP_b2, nullptr);
+    const int splits = rows / 128;
+    rc = gemm<true, false, EPI_F32>(c, dZ2, H1, kHidden, kHidden, rows, kHidden, kHidden, part, nullptr, kHidden,
+                                    nullptr, nullptr, splits);
+    if (rc) return rc;
+    hipLaunchKernelGGL(k_sum_splits, dim3(kHidden * kHidden / 256), dim3(256), 0, c->stream, part, splits,
+                       (size_t)kHidden * kHidden, grad + kP_W2);
+    rc = gemm<false, false, EPI_MASK_BF16>(c, dZ2, wb + kP_W2, rows, kHidden, kHidden, kHidden, kHidden, nullptr, dZ1,
+                                           kHidden, nullptr, H1, 1);
+    if (rc) return rc;
+    colsum(c, dZ1, nullptr, rows, kHidden, grad + kP_b1, nullptr);
+    rc = gemm<true, false, EPI_F32>(c, dZ1, X, kHidden, kFeat, rows, kHidden, kFeat, part, nullptr, kFeat, nullptr,
+                                    nullptr, splits);
+    if (rc) return rc;
+    hipLaunchKernelGGL(k_sum_splits, dim3(kHidden * kFeat / 256), dim3(256), 0, c->stream, part, splits,
+                       (size_t)kHidden * kFeat, grad + kP_W1);
+    HIP_TRY(c, hipGetLastError());
+    return FFS_OK;
+}
+
+int mlp_adam(ffs_ctx* c)
+{
+    c->adam_steps += 1;
+    const double st = (double)c->adam_steps;
+    const float bc1 = (float)(1.0 - std::pow((double)kBeta1, st));
+    const float bc2 = (float)(1.0 - std::pow((double)kBeta2, st));
+    hipLaunchKernelGGL(k_adam, dim3((kParams + 255) / 256), dim3(256), 0, c->stream, at<float>(c, c->o_w),
+                       at<float>(c, c->o_m), at<float>(c, c->o_v), at<const float>(c, c->o_g),
+                       at<uint16_t>(c, c->o_wb), kParams, kLr, kBeta1, kBeta2, kEps, bc1, bc2);
+    HIP_TRY(c, hipGetLastError());
+    return FFS_OK;
+}
+
+// One training step after generation g: a minibatch from the replay ring,
+// gradients, Adam.
+int surrogate_train(ffs_ctx* c, int g)
+{
+    const auto& I = c->inst[c->surr];
+    const long long filled = std::min<long long>((long long)g * c->surr_cells, kRing);
+    int* idx = at<int>(c, c->o_idx);
+    hipLaunchKernelGGL(k_batch_idx, dim3((kBatch / 8 + 255) / 256), dim3(256), 0, c->stream, (uint64_t)I.seed,
+                       (uint64_t)c->surr, g, (int)filled, kBatch, idx);
+    hipLaunchKernelGGL(k_gather_batch, dim3(kBatch / 8), dim3(256), 0, c->stream, at<const uint16_t>(c, c->o_ringX),
+                       at<const float>(c, c->o_ringT), idx, kBatch, at<uint16_t>(c, c->o_Xb), at<float>(c, c->o_tb));
+    int rc = mlp_gradients(c, at<const uint16_t>(c, c->o_Xb), at<const float>(c, c->o_tb), kBatch,
+                           at<float>(c, c->o_g), nullptr, nullptr);
+    if (rc) return rc;
+    return mlp_adam(c);
+}
+
+// Candidates of every cell for the next generation: features (and exact
+// targets when Tout), predictions, and the chosen stream per cell.
+int surrogate_score(ffs_ctx* c, float* Tout)
+{
+    const auto& I = c->inst[c->surr];
+    const InstDesc* di = reinterpret_cast<const InstDesc*>(c->ws + c->off_insts);
+    const IslandDesc* dl = reinterpret_cast<const IslandDesc*>(c->ws + c->off_isls);
+    const Control* ctl = reinterpret_cast<const Control*>(c->ws + c->off_ctl);
+    const int per_block = c->wpb * I.G;
+    const int blocks = (c->surr_Nc + per_block - 1) / per_block;
+    int inst = c->surr, Nc = c->surr_Nc;
+    uint16_t* X = at<uint16_t>(c, c->o_Xall);
+    void* args[] = {(void*)&di, (void*)&dl, (void*)&inst, (void*)&ctl, (void*)&Nc, (void*)&X, (void*)&Tout};
+    HIP_TRY(c, hipLaunchKernel(c->kcand, dim3(blocks), dim3(64 * c->wpb), args, c->lds_gen, c->stream));
+    return mlp_forward(c, X, c->surr_Ncp, at<uint16_t>(c, c->o_H1all), at<uint16_t>(c, c->o_H2all),
+                       at<float>(c, c->o_yall), c->surr_K, at<int>(c, c->o_choice), c->surr_Nc);
+}
+
 bool migration_due(const ffs_ctx* c, int g)
 {
     for (auto& I : c->inst)
@@ -442,6 +645,36 @@ int ffs_create_instance(ffs_ctx* c, int32_t n, int32_t S, const int32_t* machine
     }
     I.cfg = *cfg;
     I.seed = seed;
+    // lower bound max(max_k ceil(P_k / m_k), max_j sum_k p_jk), stage totals
+    I.Pk.assign(S, 0);
+    long long jobmax = 0;
+    for (int j = 0; j < n; ++j) {
+        long long sj = 0;
+        for (int k = 0; k < S; ++k) {
+            I.Pk[k] += I.p[(size_t)j * S + k];
+            sj += I.p[(size_t)j * S + k];
+        }
+        jobmax = std::max(jobmax, sj);
+    }
+    I.LB = jobmax;
+    I.msum = 0;
+    for (int k = 0; k < S; ++k) {
+        I.LB = std::max(I.LB, (I.Pk[k] + I.m[k] - 1) / I.m[k]);
+        I.msum += I.m[k];
+    }
+    I.n_cells = 0;
+    for (auto& L : I.isl) {
+        L.cell_base = (L.spec.kind == 0) ? I.n_cells : -1;
+        if (L.spec.kind == 0) I.n_cells += L.size;
+    }
+    if (cfg->surrogate_k < 0 || cfg->surrogate_k > 64) return fail(c, FFS_EINVAL, "surrogate_k must be in [0, 64]");
+    if (cfg->surrogate_warmup < 0) return fail(c, FFS_EINVAL, "surrogate_warmup must be >= 0");
+    if (cfg->surrogate_k > 1) {
+        if (I.n_cells == 0) return fail(c, FFS_EINVAL, "the pre-screen needs a cellular island");
+        if (!c->inst.empty()) return fail(c, FFS_EUNSUPPORTED, "the pre-screen needs a context with a single instance");
+    }
+    for (auto& x : c->inst)
+        if (x.cfg.surrogate_k > 1) return fail(c, FFS_EUNSUPPORTED, "the pre-screen needs a context with a single instance");
     c->inst.push_back(I);
     *out_id = (int32_t)(c->inst.size() - 1);
     return FFS_OK;
@@ -533,7 +766,21 @@ int ffs_bind_workspace(ffs_ctx* c, void* dptr, size_t bytes)
         d.n_islands = (int)I.isl.size();
         d.interval = (I.isl.size() >= 2) ? I.cfg.migration_interval : 0;
         d.topology = I.cfg.topology;
-        for (int k = 0; k < I.S; ++k) d.mach[k] = I.m[k];
+        for (int k = 0; k < I.S; ++k) {
+            d.mach[k] = I.m[k];
+            d.Pk[k] = (int)I.Pk[k];
+        }
+        d.LB = (int)I.LB;
+        d.msum = I.msum;
+        d.n_cells = I.n_cells;
+        d.surr_k = (c->surr == (int)ii) ? c->surr_K : 0;
+        d.surr_warmup = I.cfg.surrogate_warmup;
+        d.ring_size = kRing;
+        if (c->surr == (int)ii) {
+            d.surr_choice = reinterpret_cast<int*>(c->ws + c->o_choice);
+            d.ring_X = reinterpret_cast<uint16_t*>(c->ws + c->o_ringX);
+            d.ring_T = reinterpret_cast<float*>(c->ws + c->o_ringT);
+        }
         hi[ii] = d;
         for (size_t x = 0; x < I.isl.size(); ++x) {
             auto& L = I.isl[x];
@@ -554,6 +801,7 @@ int ffs_bind_workspace(ffs_ctx* c, void* dptr, size_t bytes)
             e.size = L.size;
             e.inst = (int)ii;
             e.local = (int)x;
+            e.cell_base = L.cell_base;
             hl.push_back(e);
         }
         isl_base += (int)I.isl.size();
@@ -587,6 +835,21 @@ int ffs_bind_workspace(ffs_ctx* c, void* dptr, size_t bytes)
             const unsigned long long gk = ~0ull;
             HIP_TRY(c, hipMemcpy(c->ws + L.off_genkey, &gk, 8, hipMemcpyHostToDevice));
         }
+    }
+    if (c->surr >= 0) {
+        c->kcand = pick_cand(c->mm, c->ptb);
+        if (!c->kcand) return fail(c, FFS_EUNSUPPORTED, "no candidate kernel for %d machines", c->mm);
+        HIP_TRY(c, hipFuncSetAttribute(c->kcand, hipFuncAttributeMaxDynamicSharedMemorySize, (int)c->lds_gen));
+        hipLaunchKernelGGL(k_mlp_init, dim3((kParams + 255) / 256), dim3(256), 0, c->stream, (uint64_t)c->inst[c->surr].seed,
+                           (uint64_t)c->surr, at<float>(c, c->o_w), at<uint16_t>(c, c->o_wb), at<float>(c, c->o_m),
+                           at<float>(c, c->o_v));
+        const size_t xw = (size_t)c->surr_Ncp * kFeat / 2;
+        hipLaunchKernelGGL(k_zero_u32, dim3((unsigned)((xw + 255) / 256)), dim3(256), 0, c->stream,
+                           at<uint32_t>(c, c->o_Xall), xw);
+        hipLaunchKernelGGL(k_zero_u32, dim3((c->surr_cells + 255) / 256), dim3(256), 0, c->stream,
+                           at<uint32_t>(c, c->o_choice), (size_t)c->surr_cells);
+        c->adam_steps = 0;
+        HIP_TRY(c, hipGetLastError());
     }
     c->bound = true;
     c->gen = 0;
@@ -636,7 +899,7 @@ int ffs_evolve(ffs_ctx* c, int32_t generations)
     const int I = common_interval(c);
     // whole epochs replay one captured graph: the kernels read the generation
     // from the control block, so the same graph serves every epoch
-    const bool graphs = c->use_graphs && !c->timing && c->stream != nullptr && I >= 0;
+    const bool graphs = c->use_graphs && !c->timing && c->stream != nullptr && I >= 0 && c->surr < 0;
     const int L = (I > 0) ? I : 16;
     int left = generations;
     while (left > 0) {
@@ -668,9 +931,17 @@ int ffs_evolve(ffs_ctx* c, int32_t generations)
             continue;
         }
         const int g = c->gen + 1;
+        if (c->surr >= 0 && g > c->surr_warmup) {
+            rc = surrogate_score(c, nullptr);     // choose the candidate each cell decodes
+            if (rc) return rc;
+        }
         rc = launch_generation(c, 0);
         if (rc) return rc;
         c->gen = g;
+        if (c->surr >= 0) {
+            rc = surrogate_train(c, g);
+            if (rc) return rc;
+        }
         if (migration_due(c, g)) {
             rc = launch_migration(c, -1);
             if (rc) return rc;
@@ -790,6 +1061,122 @@ int ffs_kernel_time(ffs_ctx* c, double* total_ms, int64_t* launches)
     c->ev_used.clear();
     if (total_ms) *total_ms = c->timed_ms;
     if (launches) *launches = c->timed_launches;
+    return FFS_OK;
+}
+
+static int check_surr(ffs_ctx* c, int32_t inst)
+{
+    int rc = check_bound(c);
+    if (rc) return rc;
+    if (inst < 0 || inst >= (int)c->inst.size()) return fail(c, FFS_EINVAL, "no instance %d", inst);
+    if (c->surr != inst) return fail(c, FFS_EINVAL, "instance %d has no pre-screen", inst);
+    return FFS_OK;
+}
+
+int ffs_surrogate_params(ffs_ctx* c, int32_t inst, float* host)
+{
+    int rc = check_surr(c, inst);
+    if (rc) return rc;
+    if (!host) return fail(c, FFS_EINVAL, "null buffer");
+    HIP_TRY(c, hipMemcpyAsync(host, c->ws + c->o_w, (size_t)kParams * 4, hipMemcpyDeviceToHost, c->stream));
+    HIP_TRY(c, hipStreamSynchronize(c->stream));
+    return FFS_OK;
+}
+
+int ffs_surrogate_set_params(ffs_ctx* c, int32_t inst, const float* host)
+{
+    int rc = check_surr(c, inst);
+    if (rc) return rc;
+    if (!host) return fail(c, FFS_EINVAL, "null buffer");
+    HIP_TRY(c, hipMemcpyAsync(c->ws + c->o_w, host, (size_t)kParams * 4, hipMemcpyHostToDevice, c->stream));
+    hipLaunchKernelGGL(k_to_bf16, dim3((kParams + 255) / 256), dim3(256), 0, c->stream, at<const float>(c, c->o_w),
+                       at<uint16_t>(c, c->o_wb), kParams);
+    HIP_TRY(c, hipGetLastError());
+    HIP_TRY(c, hipStreamSynchronize(c->stream));
+    return FFS_OK;
+}
+
+int ffs_mlp_forward(ffs_ctx* c, int32_t inst, const uint16_t* X, int32_t rows, float* y, uint16_t* H1, uint16_t* H2)
+{
+    int rc = check_surr(c, inst);
+    if (rc) return rc;
+    if (!X || !y) return fail(c, FFS_EINVAL, "null buffer");
+    if (rows < 128 || rows % 128) return fail(c, FFS_EINVAL, "rows must be a positive multiple of 128");
+    if ((!H1 || !H2) && rows > kBatch) return fail(c, FFS_EINVAL, "give H1 and H2 for more than %d rows", kBatch);
+    rc = mlp_forward(c, X, rows, H1 ? H1 : at<uint16_t>(c, c->o_H1b), H2 ? H2 : at<uint16_t>(c, c->o_H2b), y, 0,
+                     nullptr, rows);
+    if (rc) return rc;
+    HIP_TRY(c, hipGetLastError());
+    HIP_TRY(c, hipStreamSynchronize(c->stream));
+    return FFS_OK;
+}
+
+int ffs_mlp_gradients(ffs_ctx* c, int32_t inst, const uint16_t* X, const float* t, int32_t rows, float* grad,
+                      uint16_t* dZ2, uint16_t* dZ1)
+{
+    int rc = check_surr(c, inst);
+    if (rc) return rc;
+    if (!X || !t || !grad) return fail(c, FFS_EINVAL, "null buffer");
+    rc = mlp_gradients(c, X, t, rows, grad, dZ2, dZ1);
+    if (rc) return rc;
+    HIP_TRY(c, hipStreamSynchronize(c->stream));
+    return FFS_OK;
+}
+
+int ffs_mlp_train_step(ffs_ctx* c, int32_t inst, const uint16_t* X, const float* t, int32_t rows)
+{
+    int rc = check_surr(c, inst);
+    if (rc) return rc;
+    if (!X || !t) return fail(c, FFS_EINVAL, "null buffer");
+    rc = mlp_gradients(c, X, t, rows, at<float>(c, c->o_g), nullptr, nullptr);
+    if (rc) return rc;
+    rc = mlp_adam(c);
+    if (rc) return rc;
+    HIP_TRY(c, hipStreamSynchronize(c->stream));
+    return FFS_OK;
+}
+
+int ffs_surrogate_candidates(ffs_ctx* c, int32_t inst, int32_t exact, uint16_t* X_host, float* pred_host,
+                             float* exact_host, int32_t* choice_host)
+{
+    int rc = check_surr(c, inst);
+    if (rc) return rc;
+    rc = surrogate_score(c, exact ? at<float>(c, c->o_Tall) : nullptr);
+    if (rc) return rc;
+    const size_t Nc = (size_t)c->surr_Nc;
+    if (X_host) HIP_TRY(c, hipMemcpyAsync(X_host, c->ws + c->o_Xall, Nc * kFeat * 2, hipMemcpyDeviceToHost, c->stream));
+    if (pred_host) HIP_TRY(c, hipMemcpyAsync(pred_host, c->ws + c->o_yall, Nc * 4, hipMemcpyDeviceToHost, c->stream));
+    if (exact_host && exact)
+        HIP_TRY(c, hipMemcpyAsync(exact_host, c->ws + c->o_Tall, Nc * 4, hipMemcpyDeviceToHost, c->stream));
+    if (choice_host)
+        HIP_TRY(c, hipMemcpyAsync(choice_host, c->ws + c->o_choice, (size_t)c->surr_cells * 4, hipMemcpyDeviceToHost,
+                                  c->stream));
+    HIP_TRY(c, hipStreamSynchronize(c->stream));
+    return FFS_OK;
+}
+
+int ffs_surrogate_choices(ffs_ctx* c, int32_t inst, int32_t* host)
+{
+    int rc = check_surr(c, inst);
+    if (rc) return rc;
+    if (!host) return fail(c, FFS_EINVAL, "null buffer");
+    HIP_TRY(c, hipMemcpyAsync(host, c->ws + c->o_choice, (size_t)c->surr_cells * 4, hipMemcpyDeviceToHost, c->stream));
+    HIP_TRY(c, hipStreamSynchronize(c->stream));
+    return FFS_OK;
+}
+
+int ffs_surrogate_ring(ffs_ctx* c, int32_t inst, int32_t first, int32_t count, uint16_t* X_host, float* t_host)
+{
+    int rc = check_surr(c, inst);
+    if (rc) return rc;
+    if (first < 0 || count < 0 || first + count > kRing) return fail(c, FFS_EINVAL, "ring rows out of range");
+    if (X_host)
+        HIP_TRY(c, hipMemcpyAsync(X_host, c->ws + c->o_ringX + (size_t)first * kFeat * 2, (size_t)count * kFeat * 2,
+                                  hipMemcpyDeviceToHost, c->stream));
+    if (t_host)
+        HIP_TRY(c, hipMemcpyAsync(t_host, c->ws + c->o_ringT + (size_t)first * 4, (size_t)count * 4,
+                                  hipMemcpyDeviceToHost, c->stream));
+    HIP_TRY(c, hipStreamSynchronize(c->stream));
     return FFS_OK;
 }
 

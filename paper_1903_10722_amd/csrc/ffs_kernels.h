@@ -21,6 +21,7 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include "ffs_mlp.h"
 #include "philox.h"
 
 namespace flowshop {
@@ -41,7 +42,14 @@ struct InstDesc {
     int n, S, n_pad, jb, G;
     int island0, n_islands;
     int interval, topology;
+    // learned pre-screen (surr_k > 1): candidate streams per cell, replay ring
+    int surr_k, surr_warmup, n_cells, ring_size;
+    int* surr_choice;            // [n_cells] candidate chosen for the next generation
+    uint16_t* ring_X;            // [ring_size][256] features of decoded children
+    float* ring_T;               // [ring_size] (C - LB) / LB
+    int LB, msum;
     int mach[kMaxStages];
+    int Pk[kMaxStages];          // sum over jobs of p[j][k]
 };
 
 struct IslandDesc {
@@ -54,6 +62,8 @@ struct IslandDesc {
     int kind, rows, cols, size;
     int inst;
     int local;                   // island index inside its instance
+    int cell_base;               // index of slot 0 among the instance's cellular cells
+    int pad;
 };
 
 struct WorkItem {
@@ -299,6 +309,118 @@ __device__ __forceinline__ void swap_genes(uint16_t* A, bool doit, int i, int j)
     wave_sync();
 }
 
+// ---- cellular offspring ----------------------------------------------------
+struct CellMeta {
+    int mk1, mk2, a, b, mi, mj;
+    bool cx, mx;
+};
+
+// The child of cell `slot` at generation `gen` from candidate stream `sub`
+// (sub 0 is the plain GA's stream): parents = the two best of (self, N, E,
+// S, W) by (makespan, that order) in generation gen-1, then order crossover
+// and swap mutation on the group's LDS rows.  A receives the child.
+__device__ __forceinline__ CellMeta cellular_offspring(const InstDesc* I, const IslandDesc* L, int slot, uint32_t sub,
+                                                   int gen, int cur, uint16_t* A, uint16_t* B, uint16_t* V, int k,
+                                                   int S, int g, bool active)
+{
+    const int n = I->n, n_pad = I->n_pad;
+    const int* mkp = L->mk[cur];
+    const int rows = L->rows, cols = L->cols;
+    const int r = slot / cols, c = slot - r * cols;
+    const int nb0 = slot;
+    const int nb1 = ((r == 0) ? rows - 1 : r - 1) * cols + c;
+    const int nb2 = r * cols + ((c == cols - 1) ? 0 : c + 1);
+    const int nb3 = ((r == rows - 1) ? 0 : r + 1) * cols + c;
+    const int nb4 = r * cols + ((c == 0) ? cols - 1 : c - 1);
+    const int v0 = mkp[nb0], v1 = mkp[nb1], v2 = mkp[nb2], v3 = mkp[nb3], v4 = mkp[nb4];
+    int bv = v0, bs = nb0, bo = 0;
+    if (v1 < bv) { bv = v1; bs = nb1; bo = 1; }
+    if (v2 < bv) { bv = v2; bs = nb2; bo = 2; }
+    if (v3 < bv) { bv = v3; bs = nb3; bo = 3; }
+    if (v4 < bv) { bv = v4; bs = nb4; bo = 4; }
+    int sv = 0x7FFFFFFF, ss = -1;
+    if (bo != 0 && v0 < sv) { sv = v0; ss = nb0; }
+    if (bo != 1 && v1 < sv) { sv = v1; ss = nb1; }
+    if (bo != 2 && v2 < sv) { sv = v2; ss = nb2; }
+    if (bo != 3 && v3 < sv) { sv = v3; ss = nb3; }
+    if (bo != 4 && v4 < sv) { sv = v4; ss = nb4; }
+    if (ss < 0) ss = nb1;   // only when every makespan is INT_MAX (never)
+    const Block4 bk = stream_block(I->seed, (uint64_t)I->inst_id, (uint32_t)L->local, (uint32_t)slot, sub,
+                                   (uint32_t)gen, kCell, 0);
+    const bool cx = (uint64_t)draw32(bk, 0) < L->tc;
+    const int u = (int)below(draw32(bk, 1), (uint32_t)n), w = (int)below(draw32(bk, 2), (uint32_t)n);
+    const int a = u < w ? u : w, b = u < w ? w : u;
+    const bool mx = (uint64_t)draw32(bk, 3) < L->tm;
+    const int mi = (int)below(draw32(bk, 4), (uint32_t)n);
+    int mj = mi + 1 + (int)below(draw32(bk, 5), (uint32_t)(n - 1));
+    if (mj >= n) mj -= n;
+    const uint16_t* gp = L->genes[cur];
+    if (active) {
+        row_g2l(A, gp + (size_t)bs * n_pad, n_pad, k, S);
+        row_g2l(B, gp + (size_t)ss * n_pad, n_pad, k, S);
+    }
+    wave_sync();
+    ox_group(A, B, V, n, a, b, cx && active, k, S, g);
+    swap_genes(A, mx && active && k == 0, mi, mj);
+    CellMeta meta;
+    meta.mk1 = bv;
+    meta.mk2 = sv;
+    meta.a = a;
+    meta.b = b;
+    meta.mi = mi;
+    meta.mj = mj;
+    meta.cx = cx;
+    meta.mx = mx;
+    return meta;
+}
+
+// Pre-screen input of the chromosome in A (the group's S lanes): lane k sums
+// stage k's processing times over each of B = floor(240 / S) position
+// buckets (position t is in bucket floor(t B / n)) and writes
+// bf16(fp32(load * B) / fp32(P_k)) at index b * S + k; indices B*S .. 239 and
+// 252 .. 255 are 0; 240 .. 251 hold the scalars (parents' makespans / LB,
+// cut points / n, crossover flag, mutation flag, swap positions / n, LB / E,
+// n / 1000, S / 20, sum m / (6 S)).  Every ratio is one correctly rounded
+// FP32 division.
+template <typename PT>
+__device__ __forceinline__ void features_group(const uint16_t* A, const PT* pT, const InstDesc* I, int k, bool active,
+                                               const CellMeta& cm, uint16_t* out)
+{
+    if (!active) return;
+    const int n = I->n, S = I->S, n_pad = I->n_pad;
+    const int B = 240 / S;
+    const PT* prow = pT + (size_t)k * n_pad;
+    const float Pk = (float)I->Pk[k];
+    int t = 0;
+    for (int bb = 0; bb < B; ++bb) {
+        const int tend = ((bb + 1) * n + B - 1) / B;
+        long long load = 0;
+#pragma unroll 8
+        for (; t < tend; ++t) load += prow[A[t]];
+        out[bb * S + k] = f32_to_bf16(__fdiv_rn((float)(load * B), Pk));
+    }
+    const float fn = (float)n, fLB = (float)I->LB;
+    for (int e = B * S + k; e < kFeat; e += S) {
+        float v = 0.f;
+        switch (e - 240) {
+            case 0: v = __fdiv_rn((float)cm.mk1, fLB); break;
+            case 1: v = __fdiv_rn((float)cm.mk2, fLB); break;
+            case 2: v = __fdiv_rn((float)cm.a, fn); break;
+            case 3: v = __fdiv_rn((float)cm.b, fn); break;
+            case 4: v = cm.cx ? 1.f : 0.f; break;
+            case 5: v = cm.mx ? 1.f : 0.f; break;
+            case 6: v = __fdiv_rn((float)cm.mi, fn); break;
+            case 7: v = __fdiv_rn((float)cm.mj, fn); break;
+            case 8: v = __fdiv_rn(fLB, (float)I->E); break;
+            case 9: v = __fdiv_rn(fn, 1000.f); break;
+            case 10: v = __fdiv_rn((float)S, 20.f); break;
+            case 11: v = __fdiv_rn((float)I->msum, (float)(6 * S)); break;
+            default: break;
+        }
+        out[e] = f32_to_bf16(v);
+    }
+}
+
 // ---- one generation (mode 0) or generation 0 (mode 1) of every island -----
 template <int MMAX, typename PT>
 __global__ void __launch_bounds__(512) k_generation(const InstDesc* __restrict__ insts,
@@ -336,6 +458,7 @@ __global__ void __launch_bounds__(512) k_generation(const InstDesc* __restrict__
     const uint64_t seed = I->seed, iid = (uint64_t)I->inst_id;
     const uint32_t isl_local = (uint32_t)L->local;
 
+    CellMeta meta{};
     if (mode == 1) {
         // generation 0: Fisher-Yates from the INIT stream; a pseudo pair is a
         // permutation (even slot) and its reversal (odd slot).
@@ -373,44 +496,9 @@ __global__ void __launch_bounds__(512) k_generation(const InstDesc* __restrict__
         }
         wave_sync();
     } else if (L->kind == 0) {
-        // cellular: two best of (self, N, E, S, W) by (makespan, that order)
-        const int* mkp = L->mk[cur];
-        const int rows = L->rows, cols = L->cols;
-        const int r = slot / cols, c = slot - r * cols;
-        const int nb0 = slot;
-        const int nb1 = ((r == 0) ? rows - 1 : r - 1) * cols + c;
-        const int nb2 = r * cols + ((c == cols - 1) ? 0 : c + 1);
-        const int nb3 = ((r == rows - 1) ? 0 : r + 1) * cols + c;
-        const int nb4 = r * cols + ((c == 0) ? cols - 1 : c - 1);
-        const int v0 = mkp[nb0], v1 = mkp[nb1], v2 = mkp[nb2], v3 = mkp[nb3], v4 = mkp[nb4];
-        int bv = v0, bs = nb0, bo = 0;
-        if (v1 < bv) { bv = v1; bs = nb1; bo = 1; }
-        if (v2 < bv) { bv = v2; bs = nb2; bo = 2; }
-        if (v3 < bv) { bv = v3; bs = nb3; bo = 3; }
-        if (v4 < bv) { bv = v4; bs = nb4; bo = 4; }
-        int sv = 0x7FFFFFFF, ss = -1;
-        if (bo != 0 && v0 < sv) { sv = v0; ss = nb0; }
-        if (bo != 1 && v1 < sv) { sv = v1; ss = nb1; }
-        if (bo != 2 && v2 < sv) { sv = v2; ss = nb2; }
-        if (bo != 3 && v3 < sv) { sv = v3; ss = nb3; }
-        if (bo != 4 && v4 < sv) { sv = v4; ss = nb4; }
-        if (ss < 0) ss = nb1;   // only when every makespan is INT_MAX (never)
-        const Block4 bk = stream_block(seed, iid, isl_local, (uint32_t)slot, 0, (uint32_t)gen, kCell, 0);
-        const bool cx = (uint64_t)draw32(bk, 0) < L->tc;
-        const int u = (int)below(draw32(bk, 1), (uint32_t)n), w = (int)below(draw32(bk, 2), (uint32_t)n);
-        const int a = u < w ? u : w, b = u < w ? w : u;
-        const bool mx = (uint64_t)draw32(bk, 3) < L->tm;
-        const int mi = (int)below(draw32(bk, 4), (uint32_t)n);
-        int mj = mi + 1 + (int)below(draw32(bk, 5), (uint32_t)(n - 1));
-        if (mj >= n) mj -= n;
-        const uint16_t* gp = L->genes[cur];
-        if (active) {
-            row_g2l(A, gp + (size_t)bs * n_pad, n_pad, k, S);
-            row_g2l(B, gp + (size_t)ss * n_pad, n_pad, k, S);
-        }
-        wave_sync();
-        ox_group(A, B, V, n, a, b, cx && active, k, S, g);
-        swap_genes(A, mx && active && k == 0, mi, mj);
+        const bool screened = I->surr_k > 1 && gen > I->surr_warmup;
+        const uint32_t sub = screened ? (uint32_t)I->surr_choice[L->cell_base + slot] : 0u;
+        meta = cellular_offspring(I, L, slot, sub, gen, cur, A, B, V, k, S, g, active);
     } else {
         // pseudo: X = better of the pair, Y = reverse(X); even slot gets
         // OX(X, Y), odd slot OX(Y, X), with shared cut points.
@@ -471,6 +559,12 @@ __global__ void __launch_bounds__(512) k_generation(const InstDesc* __restrict__
         }
         if (k == 0) L->mk[nxt][slot] = mk_new;
         wkey = (k == 0) ? (((unsigned long long)(unsigned)mk_new << 32) | (unsigned)slot) : ~0ull;
+    }
+    if (mode == 0 && L->kind == 0 && I->surr_k > 1) {
+        // training data of the pre-screen: the decoded child and its exact makespan
+        const long long ri = ((long long)(gen - 1) * I->n_cells + L->cell_base + slot) % I->ring_size;
+        features_group<PT>(A, pT, I, k, active, meta, I->ring_X + ri * kFeat);
+        if (active && k == 0) I->ring_T[ri] = __fdiv_rn((float)(cmg - I->LB), (float)I->LB);
     }
     // island minimum of (makespan, slot): wave reduction, then one atomic per workgroup
 #pragma unroll
@@ -594,6 +688,115 @@ __global__ void __launch_bounds__(512) k_evaluate(const InstDesc* __restrict__ I
                                                    k, S, n, jb, active);
     if (active && k == S - 1) out[idx] = gbad ? -1 : (int)cm;
     if (active && k == 0 && gbad) atomicOr(&ctl->err, 1);
+}
+
+// ---- candidates of the learned pre-screen ----------------------------------
+// Row q = cell * K + c: the child cell `cell` would get at the next
+// generation from candidate stream c, as features (Xout[q]) and, when Tout
+// is given, its exact (C - LB) / LB (the judge of the pre-screen's ranking).
+template <int MMAX, typename PT>
+__global__ void __launch_bounds__(512) k_candidates(const InstDesc* __restrict__ insts,
+                                                    const IslandDesc* __restrict__ isls, int inst,
+                                                    const Control* ctl, int Nc, uint16_t* __restrict__ Xout,
+                                                    float* __restrict__ Tout)
+{
+    const InstDesc* I = insts + inst;
+    const int n = I->n, S = I->S, n_pad = I->n_pad, jb = I->jb, G = I->G, K = I->surr_k;
+    const int gen = ctl->gen + 1, cur = ctl->gen & 1;
+    PT* pT = reinterpret_cast<PT*>(ffs_smem);
+    {
+        const uint4* src = reinterpret_cast<const uint4*>(I->pT);
+        uint4* dst = reinterpret_cast<uint4*>(pT);
+        const int nv = (int)((size_t)S * n_pad * sizeof(PT) / 16);
+        for (int v = threadIdx.x; v < nv; v += blockDim.x) dst[v] = src[v];
+    }
+    __syncthreads();
+    const int wpb = blockDim.x >> 6;
+    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    uint16_t* gbase = reinterpret_cast<uint16_t*>(ffs_smem + align16((size_t)S * n_pad * sizeof(PT)) +
+                                                  wave * wave_lds_bytes(G, n_pad));
+    const int g = lane / S, k = lane - g * S;
+    const int q = (blockIdx.x * wpb + wave) * G + g;
+    const bool active = (g < G) && (q < Nc);
+    const int qq = active ? q : 0;
+    const int cell = qq / K, c = qq - cell * K;
+    const IslandDesc* L = isls + I->island0;
+    int slot = 0;
+    for (int x = 0; x < I->n_islands; ++x) {
+        const IslandDesc* X = isls + I->island0 + x;
+        if (X->kind == 0 && cell >= X->cell_base && cell < X->cell_base + X->size) {
+            L = X;
+            slot = cell - X->cell_base;
+        }
+    }
+    uint16_t* A = gbase + (size_t)(active ? g : 0) * 3 * n_pad;
+    uint16_t* B = A + n_pad;
+    uint16_t* V = B + n_pad;
+    const CellMeta meta = cellular_offspring(I, L, slot, (uint32_t)c, gen, cur, A, B, V, k, S, g, active);
+    features_group<PT>(A, pT, I, k, active, meta, Xout + (size_t)qq * kFeat);
+    if (Tout) {
+        uint32_t* AP = reinterpret_cast<uint32_t*>(B);
+        build_ap<PT>(AP, A, pT, n, k, S, active);
+        const uint32_t cm = decode_pipelined<MMAX, PT>(AP, pT + (size_t)(k + 1 < S ? k + 1 : S - 1) * n_pad,
+                                                       I->mach, k, S, n, jb, active);
+        const int cmg = __shfl((int)cm, active ? (g * S + S - 1) : lane, 64);
+        if (active && k == 0) Tout[q] = __fdiv_rn((float)(cmg - I->LB), (float)I->LB);
+    }
+}
+
+// Parameters of the 256-512-512-1 network, one FP32 vector: W1 [512][256],
+// b1 [512], W2 [512][512], b2 [512], w3 [512], b3.  Weights uniform in
+// +-sqrt(6 / fan_in) from the MLP_INIT stream (slot = tensor index, draw =
+// element index), biases 0; Adam moments 0.
+constexpr int kP_W1 = 0, kP_b1 = 131072, kP_W2 = 131584, kP_b2 = 393728, kP_w3 = 394240, kP_b3 = 394752;
+constexpr int kParams = 394753;
+
+__global__ void __launch_bounds__(256) k_mlp_init(uint64_t seed, uint64_t inst, float* __restrict__ w,
+                                                  uint16_t* __restrict__ wb, float* __restrict__ m,
+                                                  float* __restrict__ v)
+{
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= kParams) return;
+    int tensor, elem, fan_in;
+    if (i < kP_b1) { tensor = 0; elem = i; fan_in = 256; }
+    else if (i < kP_W2) { tensor = 1; elem = i - kP_b1; fan_in = 0; }
+    else if (i < kP_b2) { tensor = 2; elem = i - kP_W2; fan_in = 512; }
+    else if (i < kP_w3) { tensor = 3; elem = i - kP_b2; fan_in = 0; }
+    else if (i < kP_b3) { tensor = 4; elem = i - kP_w3; fan_in = 512; }
+    else { tensor = 5; elem = 0; fan_in = 0; }
+    float x = 0.f;
+    if (fan_in > 0) {
+        const Block4 b = stream_block(seed, inst, 0, (uint32_t)tensor, 0, 0, kMlpInit, (uint32_t)(elem >> 3));
+        const uint64_t word = b.w[(elem & 7) >> 1];
+        const uint32_t u = (elem & 1) ? (uint32_t)(word >> 32) : (uint32_t)word;
+        const float f = ((float)(u >> 8) + 0.5f) * 5.9604644775390625e-08f;   // (0, 1), 2^-24 steps
+        x = (2.f * f - 1.f) * sqrtf(6.f / (float)fan_in);
+    }
+    w[i] = x;
+    wb[i] = f32_to_bf16(x);
+    m[i] = 0.f;
+    v[i] = 0.f;
+}
+
+// Minibatch rows of training step `gen`: uniform over the filled part of the
+// replay ring, from the MLP_BATCH stream (draw r -> row r).
+__global__ void __launch_bounds__(256) k_batch_idx(uint64_t seed, uint64_t inst, int gen, int filled, int rows,
+                                                   int* __restrict__ idx)
+{
+    const int blk = blockIdx.x * blockDim.x + threadIdx.x;
+    if (blk * 8 >= rows) return;
+    const Block4 b = stream_block(seed, inst, 0, 0, 0, (uint32_t)gen, kMlpBatch, (uint32_t)blk);
+#pragma unroll
+    for (int d = 0; d < 8; ++d) {
+        const int r = blk * 8 + d;
+        if (r < rows) idx[r] = (int)below(draw32(b, d), (uint32_t)filled);
+    }
+}
+
+__global__ void __launch_bounds__(256) k_zero_u32(uint32_t* __restrict__ p, size_t count)
+{
+    const size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < count) p[i] = 0u;
 }
 
 // ---- migration (paper Section 4.3) -----------------------------------------

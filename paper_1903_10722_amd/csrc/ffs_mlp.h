@@ -1,0 +1,254 @@
+// ffs_mlp.h -- the learned pre-screen on gfx950: BF16 MLP 256-512-512-1 on
+// MFMA with FP32 accumulation (forward, backward, Adam), its input features,
+// and candidate selection.
+//
+// Storage: weights row-major [out][in] (W1 512x256, W2 512x512, w3 512) in
+// BF16 for the products plus FP32 master copies; biases FP32; activations
+// BF16 row-major [rows][512]; features BF16 [rows][256].
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace flowshop {
+
+typedef __bf16 bf16x8_t __attribute__((ext_vector_type(8)));
+typedef float f32x16_t __attribute__((ext_vector_type(16)));
+
+constexpr int kFeat = 256;
+constexpr int kHidden = 512;
+
+// FP32 -> BF16 bits, round to nearest even (finite values).
+__device__ __forceinline__ uint16_t f32_to_bf16(float x)
+{
+    const uint32_t u = __float_as_uint(x);
+    return (uint16_t)((u + 0x7FFFu + ((u >> 16) & 1u)) >> 16);
+}
+
+__device__ __forceinline__ float bf16_to_f32(uint16_t h) { return __uint_as_float((uint32_t)h << 16); }
+
+// ---- tiled GEMM on MFMA ------------------------------------------------------
+// C[M x N] = opA[M x K] * opB[K x N], BF16 operands, FP32 accumulation.
+//   TA = false: A stored [M][K] (row stride lda);  true: stored [K][M].
+//   TB = false: B stored [K][N] (row stride ldb);  true: stored [N][K].
+// Block tile 128 x 128, K step 32, four waves of 64 x 64 (2 x 2 MFMA 32x32x16).
+// v_mfma_f32_32x32x16_bf16 lane layout: lane l supplies row (l % 32) of A and
+// column (l % 32) of B for k = 8 (l / 32) .. + 7; it receives column (l % 32)
+// of D at rows 8 (r / 4) + 4 (l / 32) + r % 4, r = 0..15.
+// blockIdx.z splits K into gridDim.z equal ranges (EPI_F32 writes each
+// split's partial product to its own M x N slice).
+enum GemmEpi { EPI_F32 = 0, EPI_BIAS_RELU_BF16 = 1, EPI_MASK_BF16 = 2 };
+constexpr int GBM = 128, GBN = 128, GBK = 32, GLD = GBK + 8;
+
+template <bool TA, bool TB, int EPI>
+__global__ void __launch_bounds__(256) k_gemm(const uint16_t* __restrict__ A, const uint16_t* __restrict__ B,
+                                              int M, int N, int K, int lda, int ldb, float* __restrict__ Cf,
+                                              uint16_t* __restrict__ Cb, int ldc, const float* __restrict__ bias,
+                                              const uint16_t* __restrict__ mask)
+{
+    __shared__ __align__(16) uint16_t As[GBM * GLD];
+    __shared__ __align__(16) uint16_t Bs[GBN * GLD];
+    const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
+    const int bm = blockIdx.y * GBM, bn = blockIdx.x * GBN;
+    const int wm = (wave >> 1) * 64, wn = (wave & 1) * 64;
+    const int ks = K / gridDim.z, kbeg = blockIdx.z * ks, kend = kbeg + ks;
+    f32x16_t acc[2][2];
+#pragma unroll
+    for (int a = 0; a < 2; ++a)
+#pragma unroll
+        for (int b = 0; b < 2; ++b)
+#pragma unroll
+            for (int r = 0; r < 16; ++r) acc[a][b][r] = 0.f;
+
+    for (int k0 = kbeg; k0 < kend; k0 += GBK) {
+        // stage A as As[i][k]
+        if (!TA) {
+            for (int v = tid; v < GBM * GBK / 8; v += 256) {
+                const int i = v >> 2, kk = (v & 3) * 8;
+                *reinterpret_cast<uint4*>(&As[i * GLD + kk]) =
+                    *reinterpret_cast<const uint4*>(&A[(size_t)(bm + i) * lda + k0 + kk]);
+            }
+        } else {
+            for (int v = tid; v < GBK * GBM / 8; v += 256) {
+                const int kk = v >> 4, i = (v & 15) * 8;
+                const uint4 x = *reinterpret_cast<const uint4*>(&A[(size_t)(k0 + kk) * lda + bm + i]);
+                const uint16_t* e = reinterpret_cast<const uint16_t*>(&x);
+#pragma unroll
+                for (int t = 0; t < 8; ++t) As[(i + t) * GLD + kk] = e[t];
+            }
+        }
+        // stage B as Bs[j][k]
+        if (TB) {
+            for (int v = tid; v < GBN * GBK / 8; v += 256) {
+                const int j = v >> 2, kk = (v & 3) * 8;
+                *reinterpret_cast<uint4*>(&Bs[j * GLD + kk]) =
+                    *reinterpret_cast<const uint4*>(&B[(size_t)(bn + j) * ldb + k0 + kk]);
+            }
+        } else {
+            for (int v = tid; v < GBK * GBN / 8; v += 256) {
+                const int kk = v >> 4, j = (v & 15) * 8;
+                const uint4 x = *reinterpret_cast<const uint4*>(&B[(size_t)(k0 + kk) * ldb + bn + j]);
+                const uint16_t* e = reinterpret_cast<const uint16_t*>(&x);
+#pragma unroll
+                for (int t = 0; t < 8; ++t) Bs[(j + t) * GLD + kk] = e[t];
+            }
+        }
+        __syncthreads();
+#pragma unroll
+        for (int kk = 0; kk < GBK; kk += 16) {
+            bf16x8_t a[2], b[2];
+#pragma unroll
+            for (int t = 0; t < 2; ++t) {
+                a[t] = *reinterpret_cast<const bf16x8_t*>(&As[(wm + t * 32 + (lane & 31)) * GLD + kk + 8 * (lane >> 5)]);
+                b[t] = *reinterpret_cast<const bf16x8_t*>(&Bs[(wn + t * 32 + (lane & 31)) * GLD + kk + 8 * (lane >> 5)]);
+            }
+#pragma unroll
+            for (int ti = 0; ti < 2; ++ti)
+#pragma unroll
+                for (int tj = 0; tj < 2; ++tj)
+                    acc[ti][tj] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a[ti], b[tj], acc[ti][tj], 0, 0, 0);
+        }
+        __syncthreads();
+    }
+    float* Cz = (EPI == EPI_F32) ? Cf + (size_t)blockIdx.z * M * ldc : nullptr;
+#pragma unroll
+    for (int ti = 0; ti < 2; ++ti)
+#pragma unroll
+        for (int tj = 0; tj < 2; ++tj)
+#pragma unroll
+            for (int r = 0; r < 16; ++r) {
+                const int i = bm + wm + ti * 32 + 8 * (r >> 2) + 4 * (lane >> 5) + (r & 3);
+                const int j = bn + wn + tj * 32 + (lane & 31);
+                const float v = acc[ti][tj][r];
+                const size_t o = (size_t)i * ldc + j;
+                if (EPI == EPI_F32) {
+                    Cz[o] = v;
+                } else if (EPI == EPI_BIAS_RELU_BF16) {
+                    const float z = v + bias[j];
+                    Cb[o] = f32_to_bf16(z > 0.f ? z : 0.f);
+                } else {
+                    Cb[o] = (bf16_to_f32(mask[o]) > 0.f) ? f32_to_bf16(v) : (uint16_t)0;
+                }
+            }
+}
+
+// out[i] = sum over splits s of part[s][i]  (fixed order: deterministic)
+__global__ void __launch_bounds__(256) k_sum_splits(const float* __restrict__ part, int splits, size_t count,
+                                                    float* __restrict__ out)
+{
+    const size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= count) return;
+    float s = 0.f;
+    for (int z = 0; z < splits; ++z) s += part[(size_t)z * count + i];
+    out[i] = s;
+}
+
+// ---- output layer --------------------------------------------------------
+// y[i] = H2[i] . w3 + b3, one wave per row (64 lanes x 8 columns).  With
+// K > 0 (scoring) the wave then handles the K candidates of one cell and
+// writes the index of the smallest prediction (ties: lowest index).
+__global__ void __launch_bounds__(256) k_mlp_out(const uint16_t* __restrict__ H2, const uint16_t* __restrict__ w3,
+                                                 const float* __restrict__ b3, int rows, int K,
+                                                 float* __restrict__ y, int* __restrict__ choice)
+{
+    const int wave = (blockIdx.x * blockDim.x + threadIdx.x) >> 6, lane = threadIdx.x & 63;
+    const int per = K > 0 ? K : 1;
+    const int r0 = wave * per;
+    if (r0 >= rows) return;
+    const uint4 wv = *reinterpret_cast<const uint4*>(&w3[lane * 8]);
+    const uint16_t* we = reinterpret_cast<const uint16_t*>(&wv);
+    float best = 0.f;
+    int bi = 0;
+    for (int c = 0; c < per; ++c) {
+        const uint4 hv = *reinterpret_cast<const uint4*>(&H2[(size_t)(r0 + c) * kHidden + lane * 8]);
+        const uint16_t* he = reinterpret_cast<const uint16_t*>(&hv);
+        float s = 0.f;
+#pragma unroll
+        for (int t = 0; t < 8; ++t) s += bf16_to_f32(he[t]) * bf16_to_f32(we[t]);
+#pragma unroll
+        for (int off = 32; off > 0; off >>= 1) s += __shfl_xor(s, off, 64);
+        s += b3[0];
+        if (lane == 0) y[r0 + c] = s;
+        if (c == 0 || s < best) {
+            best = s;
+            bi = c;
+        }
+    }
+    if (K > 0 && lane == 0) choice[wave] = bi;
+}
+
+// ---- backward pieces -------------------------------------------------------
+// dy = 2 (y - t) / rows; dZ2[i][j] = bf16(dy[i] * w3[j]) where H2[i][j] > 0.
+__global__ void __launch_bounds__(256) k_mlp_dz2(const float* __restrict__ y, const float* __restrict__ t,
+                                                 const uint16_t* __restrict__ H2, const uint16_t* __restrict__ w3,
+                                                 int rows, float* __restrict__ dy, uint16_t* __restrict__ dZ2)
+{
+    const size_t e = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (e >= (size_t)rows * kHidden) return;
+    const int i = (int)(e / kHidden), j = (int)(e % kHidden);
+    const float d = 2.f * (y[i] - t[i]) / (float)rows;
+    if (j == 0) dy[i] = d;
+    dZ2[e] = (bf16_to_f32(H2[e]) > 0.f) ? f32_to_bf16(d * bf16_to_f32(w3[j])) : (uint16_t)0;
+}
+
+// Column sums over rows in two fixed-order stages (deterministic): block
+// (x, z) sums rows [z * rows / gridDim.z, (z+1) * rows / gridDim.z) of 256
+// columns into part[z][j]; k_sum_splits adds the slices.  part[z][j] =
+// sum_i X[i][j] (BF16 X), or sum_i X[i][j] * dy[i] when dy != nullptr; with
+// dsum != nullptr the thread of column 0 also writes dsum[z] = sum_i dy[i].
+__global__ void __launch_bounds__(256) k_colsum(const uint16_t* __restrict__ X, const float* __restrict__ dy,
+                                                int rows, int cols, float* __restrict__ part,
+                                                float* __restrict__ dsum)
+{
+    const int j = blockIdx.x * blockDim.x + threadIdx.x;
+    if (j >= cols) return;
+    const int per = rows / gridDim.y;
+    const int r0 = blockIdx.y * per, r1 = r0 + per;
+    float s = 0.f, sd = 0.f;
+#pragma unroll 8
+    for (int i = r0; i < r1; ++i) {
+        const float x = bf16_to_f32(X[(size_t)i * cols + j]);
+        s += dy ? x * dy[i] : x;
+        if (dsum && j == 0) sd += dy[i];
+    }
+    part[(size_t)blockIdx.y * cols + j] = s;
+    if (dsum && j == 0) dsum[blockIdx.y] = sd;
+}
+
+// Adam (Kingma & Ba) on FP32 master weights; writes the BF16 copy when given.
+__global__ void __launch_bounds__(256) k_adam(float* __restrict__ w, float* __restrict__ m, float* __restrict__ v,
+                                              const float* __restrict__ g, uint16_t* __restrict__ wb, int count,
+                                              float lr, float beta1, float beta2, float eps, float bc1, float bc2)
+{
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= count) return;
+    const float gi = g[i];
+    const float mi = beta1 * m[i] + (1.f - beta1) * gi;
+    const float vi = beta2 * v[i] + (1.f - beta2) * gi * gi;
+    m[i] = mi;
+    v[i] = vi;
+    const float wi = w[i] - lr * (mi / bc1) / (sqrtf(vi / bc2) + eps);
+    w[i] = wi;
+    if (wb) wb[i] = f32_to_bf16(wi);
+}
+
+__global__ void __launch_bounds__(256) k_to_bf16(const float* __restrict__ x, uint16_t* __restrict__ y, int count)
+{
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < count) y[i] = f32_to_bf16(x[i]);
+}
+
+// Minibatch gather: rows idx_b (Philox stream of the training step) of the
+// replay ring into contiguous X / t.
+__global__ void __launch_bounds__(256) k_gather_batch(const uint16_t* __restrict__ ringX,
+                                                      const float* __restrict__ ringT, const int* __restrict__ idx,
+                                                      int rows, uint16_t* __restrict__ X, float* __restrict__ t)
+{
+    const int r = blockIdx.x * 8 + (threadIdx.x >> 5), lane = threadIdx.x & 31;   // 32 lanes x 8 features
+    if (r >= rows) return;
+    const int src = idx[r];
+    *reinterpret_cast<uint4*>(&X[(size_t)r * kFeat + lane * 8]) =
+        *reinterpret_cast<const uint4*>(&ringX[(size_t)src * kFeat + lane * 8]);
+    if (lane == 0) t[r] = ringT[src];
+}
+
+}  // namespace flowshop

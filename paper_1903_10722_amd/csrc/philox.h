@@ -17,7 +17,7 @@
 
 namespace flowshop {
 
-enum Purpose : uint32_t { kInit = 3, kCell = 4, kPair = 5 };
+enum Purpose : uint32_t { kInit = 3, kCell = 4, kPair = 5, kMlpInit = 7, kMlpBatch = 8 };
 
 struct Block4 {
     uint64_t w[4];
