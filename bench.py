@@ -34,6 +34,8 @@ def parse():
     ap.add_argument("--waves-per-block", type=int, default=None)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=12.0)
+    ap.add_argument("--surrogate-seconds", type=float, default=8.0,
+                    help="wall-clock budget of each side of the plain vs pre-screen comparison (0 = skip)")
     ap.add_argument("--calibrate-copy-mib", type=int, default=0,
                     help="only run a plain device copy of this many MiB (5 times), to calibrate HBM counters")
     return ap.parse_args()
@@ -108,6 +110,48 @@ def cpu_baseline(w, seconds: float) -> dict:
             "sample": f"oracle GA on the same medium workload: generation 0 ({t_init:.2f} s) then "
                       f"{gens} generations ({per_gen} decodes each) in {dt:.1f} s, one thread",
             "generations_per_s": gens / dt}
+
+
+def surrogate_compare(seconds: float) -> dict:
+    """Best makespan at equal wall-clock: the plain GA and the GA with the
+    learned pre-screen (k = 8 candidates per cell) on the surrogate workload
+    (n=1000 jobs, 20 stages, machines U[2,6], p U[1,99]; cellular 64x64 +
+    pseudo 4096; migration every 20).  Both start from the same generation 0."""
+    import numpy as np
+    import torch
+    from scipy.stats import spearmanr
+
+    from paper_1903_10722_amd import Context, inputs
+    w = inputs.workload("surrogate", seed=1)
+    p64, m64 = w["p"].astype(np.int64), w["m"].astype(np.int64)
+    lb = max(int(p64.sum(axis=1).max()), max(int(-(-p64[:, k].sum() // m64[k])) for k in range(p64.shape[1])))
+    out = {"workload": "surrogate: n=1000 jobs, 20 stages, machines U[2,6], p U[1,99]; cellular 64x64 + "
+                       "pseudo 4096; migration every 20; k=8 candidates per cell, warm-up 5",
+           "budget_s": seconds, "lower_bound": lb}
+    for name, k in (("plain", 0), ("prescreen", 8)):
+        ctx = Context(device=0)
+        ctx.add_instance(w["m"], w["p"], w["islands"], interval=w["interval"], theta=w["theta"],
+                         topology=w["topology"], seed=101, surrogate_k=k, surrogate_warmup=5)
+        ctx.bind()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        while time.perf_counter() - t0 < seconds:
+            ctx.evolve(5)
+            torch.cuda.synchronize()
+        dt = time.perf_counter() - t0
+        res = {"best_makespan": ctx.best(0)["makespan"], "generations": ctx.generation, "seconds": dt}
+        if k:
+            cand = ctx.surrogate_candidates(exact=True)
+            ex, pred = cand["exact"].astype(np.float64), cand["pred"].astype(np.float64)
+            chosen = ex[np.arange(ex.shape[0]), cand["choice"]]
+            res.update({"spearman": float(spearmanr(pred.reshape(-1), ex.reshape(-1)).correlation),
+                        "spearman_within_cell": float(np.mean([spearmanr(pred[i], ex[i]).correlation
+                                                               for i in range(ex.shape[0]) if np.ptp(ex[i]) > 0])),
+                        "mae": float(np.abs(pred - ex).mean()),
+                        "chosen_minus_candidate0": float(chosen.mean() - ex[:, 0].mean())})
+        out[name] = res
+        ctx.close()
+    return out
 
 
 def main():
@@ -198,6 +242,8 @@ def main():
     }
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(w, args.cpu_seconds)
+    if args.surrogate_seconds > 0:
+        out["best_makespan_at_fixed_budget"] = surrogate_compare(args.surrogate_seconds)
     ctx.close()
     print(json.dumps(out), flush=True)
 
