@@ -24,6 +24,18 @@ sys.path.insert(0, ROOT)
 
 PEAK_INT_TOPS = 256 * 64 * 2.4e9 / 1e12   # 256 CUs x 64 lanes/clk x 2.4 GHz (32-bit integer VALU)
 
+WORKLOADS = {
+    "medium": "medium: n=100 jobs, 5 stages, machines U[1,5], p U[1,99]; cellular 64x64 (pc 0.9, pm 0.1) + "
+              "pseudo 4096 (pc 0.75); adaptive migration every 20 generations; step = one 20-generation epoch",
+    "tiny": "tiny: n=20 jobs, 3 stages, machines [2,2,2], p U[1,99]; cellular 8x8 + pseudo 64; migration every 10",
+    "large": "large: n=500 jobs, 10 stages, machines U[3,5], p U[1,99]; 8 cellular 128x128 + 8 pseudo 16384; "
+             "ring-then-adaptive migration every 20",
+    "surrogate": "surrogate: n=1000 jobs, 20 stages, machines U[2,6], p U[1,99]; cellular 64x64 + pseudo 4096; "
+                 "migration every 20",
+    "batched": "batched: 256 instances, n in {20,50,100,200,500}, S in {5,10,20}, machines U[1,5], grids 32..128; "
+               "migration every 10",
+}
+
 
 def parse():
     ap = argparse.ArgumentParser()
@@ -31,6 +43,10 @@ def parse():
     ap.add_argument("--steps", type=int, default=100)
     ap.add_argument("--warmup", type=int, default=5)
     ap.add_argument("--seed", type=int, default=1)
+    ap.add_argument("--workload", default="medium", choices=["medium", "tiny", "large", "surrogate", "batched"],
+                    help="workload of the timed steps (the reported metric is quoted on medium)")
+    ap.add_argument("--prescreen-k", type=int, default=0,
+                    help="run the timed steps with the learned pre-screen (k candidates per cell)")
     ap.add_argument("--waves-per-block", type=int, default=None)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=12.0)
@@ -171,13 +187,19 @@ def main():
         from paper_1903_10722_amd.build import build_library
         build_library()
 
-    w = inputs.workload("medium", seed=args.seed)
+    if args.workload == "batched":
+        ws = inputs.batched_workloads(count=256, batch_seed=7)
+    else:
+        ws = [inputs.workload(args.workload, seed=args.seed)]
+    w = ws[0]
     n, S = w["p"].shape
     m = w["m"]
     I = w["interval"]
-    decodes_per_gen = sum(x["size"] for x in w["islands"])
+    decodes_per_gen = sum(sum(x["size"] for x in v["islands"]) for v in ws)
     ctx = Context(device=0, waves_per_block=args.waves_per_block)
-    ctx.add_instance(w["m"], w["p"], w["islands"], interval=I, theta=w["theta"], topology=w["topology"], seed=101)
+    for v in ws:
+        ctx.add_instance(v["m"], v["p"], v["islands"], interval=I, theta=v["theta"], topology=v["topology"], seed=101,
+                         surrogate_k=args.prescreen_k, surrogate_warmup=5)
     t_bind = time.perf_counter()
     ctx.bind()
     t_bind = time.perf_counter() - t_bind
@@ -207,8 +229,8 @@ def main():
     k_ms, launches = ctx.kernel_time()
     ctx.set_timing(False)
     avg_s = k_ms / max(1, launches) / 1e3
-    ops_per_decode = n * int(sum(int(x) + 6 for x in m))
-    ops_per_launch = ops_per_decode * decodes_per_gen
+    ops_per_launch = sum(int(v["p"].shape[0]) * int(sum(int(x) + 6 for x in v["m"])) *
+                         sum(x["size"] for x in v["islands"]) for v in ws)
     achieved = ops_per_launch / avg_s / 1e12
 
     out = {
@@ -224,11 +246,10 @@ def main():
         "vs_baseline": None,
         "dtype": "int32",
         "data": "synthetic",
-        "config": {"workload": "medium: n=100 jobs, 5 stages, machines U[1,5], p U[1,99]; cellular 64x64 "
-                               "(pc 0.9, pm 0.1) + pseudo 4096 (pc 0.75); adaptive migration every 20 "
-                               "generations; step = one 20-generation epoch",
-                   "machines": [int(x) for x in m], "decodes_per_generation": decodes_per_gen,
-                   "generations_per_step": I},
+        "config": {"workload": WORKLOADS[args.workload] + ("" if not args.prescreen_k else
+                                                          f"; learned pre-screen k={args.prescreen_k}"),
+                   "machines": [int(x) for x in m] if len(ws) == 1 else "per instance",
+                   "decodes_per_generation": decodes_per_gen, "generations_per_step": I},
         "generations_per_s": gens / (ms / 1e3),
         "best_makespan": best["makespan"],
         "best_found_generation": best["generation"],
@@ -236,7 +257,7 @@ def main():
         "wall_s_timed": wall,
         "bind_and_generation0_s": t_bind,
         "roofline": {"bound": "alu", "achieved": achieved, "peak": PEAK_INT_TOPS, "unit": "TOP/s",
-                     "frac": achieved / PEAK_INT_TOPS, "traffic": recorded_traffic("k_generation", "medium"),
+                     "frac": achieved / PEAK_INT_TOPS, "traffic": recorded_traffic("k_generation", args.workload),
                      "kernel": "k_generation", "avg_launch_us": avg_s * 1e6, "launches": launches,
                      "ops_per_launch": ops_per_launch},
     }
