@@ -242,7 +242,7 @@ void layout(ffs_ctx* c)
             L.off_minmax = take(16);
             L.off_sorted = take((size_t)L.size * sizeof(int));
         }
-        const size_t lds = align16((size_t)I.S * I.n_pad * c->ptb) +
+        const size_t lds = align16((size_t)I.S * ((size_t)I.n_pad * c->ptb + 4)) +
                            (size_t)c->wpb * wave_lds_bytes(I.G, I.n_pad);
         c->lds_gen = std::max(c->lds_gen, lds);
     }
@@ -778,6 +778,7 @@ int ffs_bind_workspace(ffs_ctx* c, void* dptr, size_t bytes)
         d.ring_size = kRing;
         if (c->surr == (int)ii) {
             d.surr_choice = reinterpret_cast<int*>(c->ws + c->o_choice);
+            d.surr_X = reinterpret_cast<const uint16_t*>(c->ws + c->o_Xall);
             d.ring_X = reinterpret_cast<uint16_t*>(c->ws + c->o_ringX);
             d.ring_T = reinterpret_cast<float*>(c->ws + c->o_ringT);
         }
@@ -873,7 +874,7 @@ int ffs_evaluate(ffs_ctx* c, int32_t inst, const int32_t* perms, int32_t count, 
     Control* ctl = reinterpret_cast<Control*>(c->ws + c->off_ctl);
     const int per_block = c->wpb * I.G;
     const int blocks = (count + per_block - 1) / per_block;
-    const size_t lds = align16((size_t)I.S * I.n_pad * c->ptb) + (size_t)c->wpb * wave_lds_bytes(I.G, I.n_pad);
+    const size_t lds = align16((size_t)I.S * ((size_t)I.n_pad * c->ptb + 4)) + (size_t)c->wpb * wave_lds_bytes(I.G, I.n_pad);
     void* args[] = {(void*)&di, (void*)&perms, (void*)&count, (void*)&out, (void*)&ctl};
     HIP_TRY(c, hipLaunchKernel(c->keval, dim3(blocks), dim3(64 * c->wpb), args, lds, c->stream));
     Control h;

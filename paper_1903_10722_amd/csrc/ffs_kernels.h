@@ -45,6 +45,7 @@ struct InstDesc {
     // learned pre-screen (surr_k > 1): candidate streams per cell, replay ring
     int surr_k, surr_warmup, n_cells, ring_size;
     int* surr_choice;            // [n_cells] candidate chosen for the next generation
+    const uint16_t* surr_X;      // [n_cells * surr_k][256] features of the scored candidates
     uint16_t* ring_X;            // [ring_size][256] features of decoded children
     float* ring_T;               // [ring_size] (C - LB) / LB
     int LB, msum;
@@ -96,6 +97,31 @@ __host__ __device__ inline size_t align16(size_t x) { return (x + 15) & ~(size_t
 __host__ __device__ inline size_t wave_lds_bytes(int G, int n_pad)
 {
     return (size_t)G * 3 * n_pad * 2;
+}
+
+// The processing-time table is staged into LDS stage-major with each row
+// padded by 4 bytes, so that the S rows start on different LDS banks (the S
+// lanes of a group read the same job in S different rows).
+template <typename PT>
+__host__ __device__ inline int pt_stride(int n_pad) { return n_pad + 4 / (int)sizeof(PT); }
+
+template <typename PT>
+__host__ __device__ inline size_t pt_lds_bytes(int S, int n_pad)
+{
+    return align16((size_t)S * pt_stride<PT>(n_pad) * sizeof(PT));
+}
+
+// HBM rows of n_pad elements -> LDS rows of pt_stride elements (32-bit words).
+template <typename PT>
+__device__ __forceinline__ void stage_pt(PT* dst, const void* src, int S, int n_pad)
+{
+    const int wpr = (int)(n_pad * sizeof(PT) / 4), ld = wpr + 1;
+    const uint32_t* s = reinterpret_cast<const uint32_t*>(src);
+    uint32_t* d = reinterpret_cast<uint32_t*>(dst);
+    for (int w = threadIdx.x; w < S * wpr; w += blockDim.x) {
+        const int r = w / wpr, c = w - r * wpr;
+        d[r * ld + c] = s[w];
+    }
 }
 
 // ---- row copies by the S lanes of a group (16-byte vectors) ---------------
@@ -389,15 +415,15 @@ __device__ __forceinline__ void features_group(const uint16_t* A, const PT* pT, 
     if (!active) return;
     const int n = I->n, S = I->S, n_pad = I->n_pad;
     const int B = 240 / S;
-    const PT* prow = pT + (size_t)k * n_pad;
+    const PT* prow = pT + (size_t)k * pt_stride<PT>(n_pad);
     const float Pk = (float)I->Pk[k];
     int t = 0;
     for (int bb = 0; bb < B; ++bb) {
         const int tend = ((bb + 1) * n + B - 1) / B;
-        long long load = 0;
+        uint32_t load = 0;
 #pragma unroll 8
         for (; t < tend; ++t) load += prow[A[t]];
-        out[bb * S + k] = f32_to_bf16(__fdiv_rn((float)(load * B), Pk));
+        out[bb * S + k] = f32_to_bf16(__fdiv_rn((float)((uint64_t)load * (uint64_t)B), Pk));
     }
     const float fn = (float)n, fLB = (float)I->LB;
     for (int e = B * S + k; e < kFeat; e += S) {
@@ -436,16 +462,11 @@ __global__ void __launch_bounds__(512) k_generation(const InstDesc* __restrict__
     const int cur = (gen + 1) & 1, nxt = gen & 1;
 
     PT* pT = reinterpret_cast<PT*>(ffs_smem);
-    {
-        const uint4* src = reinterpret_cast<const uint4*>(I->pT);
-        uint4* dst = reinterpret_cast<uint4*>(pT);
-        const int nv = (int)((size_t)S * n_pad * sizeof(PT) / 16);
-        for (int v = threadIdx.x; v < nv; v += blockDim.x) dst[v] = src[v];
-    }
+    stage_pt<PT>(pT, I->pT, S, n_pad);
     __syncthreads();
 
     const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
-    uint16_t* gbase = reinterpret_cast<uint16_t*>(ffs_smem + align16((size_t)S * n_pad * sizeof(PT)) +
+    uint16_t* gbase = reinterpret_cast<uint16_t*>(ffs_smem + pt_lds_bytes<PT>(S, n_pad) +
                                                   wave * wave_lds_bytes(G, n_pad));
     const int g = lane / S, k = lane - g * S;
     const int local = wave * G + g;
@@ -454,7 +475,7 @@ __global__ void __launch_bounds__(512) k_generation(const InstDesc* __restrict__
     uint16_t* B = A + n_pad;
     uint16_t* V = B + n_pad;
     const int slot = wi.slot0 + (active ? local : 0);
-    const PT* prow_next = pT + (size_t)(k + 1 < S ? k + 1 : S - 1) * n_pad;
+    const PT* prow_next = pT + (size_t)(k + 1 < S ? k + 1 : S - 1) * pt_stride<PT>(n_pad);
     const uint64_t seed = I->seed, iid = (uint64_t)I->inst_id;
     const uint32_t isl_local = (uint32_t)L->local;
 
@@ -561,9 +582,21 @@ __global__ void __launch_bounds__(512) k_generation(const InstDesc* __restrict__
         wkey = (k == 0) ? (((unsigned long long)(unsigned)mk_new << 32) | (unsigned)slot) : ~0ull;
     }
     if (mode == 0 && L->kind == 0 && I->surr_k > 1) {
-        // training data of the pre-screen: the decoded child and its exact makespan
-        const long long ri = ((long long)(gen - 1) * I->n_cells + L->cell_base + slot) % I->ring_size;
-        features_group<PT>(A, pT, I, k, active, meta, I->ring_X + ri * kFeat);
+        // training data of the pre-screen: the decoded child and its exact
+        // makespan; a screened child's features were computed when it was scored
+        const int cell = L->cell_base + slot;
+        const long long ri = ((long long)(gen - 1) * I->n_cells + cell) % I->ring_size;
+        uint16_t* dst = I->ring_X + ri * kFeat;
+        if (gen > I->surr_warmup) {
+            if (active) {
+                const uint4* s4 = reinterpret_cast<const uint4*>(
+                    I->surr_X + ((size_t)cell * I->surr_k + (size_t)I->surr_choice[cell]) * kFeat);
+                uint4* d4 = reinterpret_cast<uint4*>(dst);
+                for (int v = k; v < kFeat / 8; v += S) d4[v] = s4[v];
+            }
+        } else {
+            features_group<PT>(A, pT, I, k, active, meta, dst);
+        }
         if (active && k == 0) I->ring_T[ri] = __fdiv_rn((float)(cmg - I->LB), (float)I->LB);
     }
     // island minimum of (makespan, slot): wave reduction, then one atomic per workgroup
@@ -648,16 +681,11 @@ __global__ void __launch_bounds__(512) k_evaluate(const InstDesc* __restrict__ I
 {
     const int n = I->n, S = I->S, n_pad = I->n_pad, jb = I->jb, G = I->G;
     PT* pT = reinterpret_cast<PT*>(ffs_smem);
-    {
-        const uint4* src = reinterpret_cast<const uint4*>(I->pT);
-        uint4* dst = reinterpret_cast<uint4*>(pT);
-        const int nv = (int)((size_t)S * n_pad * sizeof(PT) / 16);
-        for (int v = threadIdx.x; v < nv; v += blockDim.x) dst[v] = src[v];
-    }
+    stage_pt<PT>(pT, I->pT, S, n_pad);
     __syncthreads();
     const int wpb = blockDim.x >> 6;
     const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
-    uint16_t* gbase = reinterpret_cast<uint16_t*>(ffs_smem + align16((size_t)S * n_pad * sizeof(PT)) +
+    uint16_t* gbase = reinterpret_cast<uint16_t*>(ffs_smem + pt_lds_bytes<PT>(S, n_pad) +
                                                   wave * wave_lds_bytes(G, n_pad));
     const int g = lane / S, k = lane - g * S;
     const long long idx = ((long long)blockIdx.x * wpb + wave) * G + g;
@@ -684,7 +712,7 @@ __global__ void __launch_bounds__(512) k_evaluate(const InstDesc* __restrict__ I
     const bool gbad = ((shift < 64 ? (bb >> shift) : 0ull) & gmask) != 0ull;
     uint32_t* AP = reinterpret_cast<uint32_t*>(A + n_pad);   // B..V: n_pad words
     build_ap<PT>(AP, A, pT, n, k, S, active);
-    const uint32_t cm = decode_pipelined<MMAX, PT>(AP, pT + (size_t)(k + 1 < S ? k + 1 : S - 1) * n_pad, I->mach,
+    const uint32_t cm = decode_pipelined<MMAX, PT>(AP, pT + (size_t)(k + 1 < S ? k + 1 : S - 1) * pt_stride<PT>(n_pad), I->mach,
                                                    k, S, n, jb, active);
     if (active && k == S - 1) out[idx] = gbad ? -1 : (int)cm;
     if (active && k == 0 && gbad) atomicOr(&ctl->err, 1);
@@ -704,16 +732,11 @@ __global__ void __launch_bounds__(512) k_candidates(const InstDesc* __restrict__
     const int n = I->n, S = I->S, n_pad = I->n_pad, jb = I->jb, G = I->G, K = I->surr_k;
     const int gen = ctl->gen + 1, cur = ctl->gen & 1;
     PT* pT = reinterpret_cast<PT*>(ffs_smem);
-    {
-        const uint4* src = reinterpret_cast<const uint4*>(I->pT);
-        uint4* dst = reinterpret_cast<uint4*>(pT);
-        const int nv = (int)((size_t)S * n_pad * sizeof(PT) / 16);
-        for (int v = threadIdx.x; v < nv; v += blockDim.x) dst[v] = src[v];
-    }
+    stage_pt<PT>(pT, I->pT, S, n_pad);
     __syncthreads();
     const int wpb = blockDim.x >> 6;
     const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
-    uint16_t* gbase = reinterpret_cast<uint16_t*>(ffs_smem + align16((size_t)S * n_pad * sizeof(PT)) +
+    uint16_t* gbase = reinterpret_cast<uint16_t*>(ffs_smem + pt_lds_bytes<PT>(S, n_pad) +
                                                   wave * wave_lds_bytes(G, n_pad));
     const int g = lane / S, k = lane - g * S;
     const int q = (blockIdx.x * wpb + wave) * G + g;
@@ -737,7 +760,7 @@ __global__ void __launch_bounds__(512) k_candidates(const InstDesc* __restrict__
     if (Tout) {
         uint32_t* AP = reinterpret_cast<uint32_t*>(B);
         build_ap<PT>(AP, A, pT, n, k, S, active);
-        const uint32_t cm = decode_pipelined<MMAX, PT>(AP, pT + (size_t)(k + 1 < S ? k + 1 : S - 1) * n_pad,
+        const uint32_t cm = decode_pipelined<MMAX, PT>(AP, pT + (size_t)(k + 1 < S ? k + 1 : S - 1) * pt_stride<PT>(n_pad),
                                                        I->mach, k, S, n, jb, active);
         const int cmg = __shfl((int)cm, active ? (g * S + S - 1) : lane, 64);
         if (active && k == 0) Tout[q] = __fdiv_rn((float)(cmg - I->LB), (float)I->LB);
