@@ -246,9 +246,9 @@ void layout(ffs_ctx* c)
                            (size_t)c->wpb * wave_lds_bytes(I.G, I.n_pad);
         c->lds_gen = std::max(c->lds_gen, lds);
     }
-    int P = 1;
-    while (P < c->max_size) P <<= 1;
-    c->lds_sort = (size_t)P * 8;
+    int R = 1;
+    while (R * kSortThreads < c->max_size) R <<= 1;
+    c->lds_sort = sort_lds_bytes(R);
     // learned pre-screen: parameters, scoring and training buffers, replay ring
     c->surr = -1;
     for (size_t ii = 0; ii < c->inst.size(); ++ii)
@@ -352,7 +352,7 @@ int launch_migration(ffs_ctx* c, int force_inst)
         hipLaunchKernelGGL(k_mig_minmax, dim3(c->n_isl), dim3(256), 0, c->stream, di, dl, ctl, force_inst);
         hipLaunchKernelGGL(k_mig_ring, dim3(c->n_isl), dim3(256), 0, c->stream, di, dl, ctl, force_inst);
     }
-    hipLaunchKernelGGL(k_mig_sort, dim3(c->n_isl), dim3(1024), c->lds_sort, c->stream, di, dl, ctl, force_inst);
+    hipLaunchKernelGGL(k_mig_sort, dim3(c->n_isl), dim3(kSortThreads), c->lds_sort, c->stream, di, dl, ctl, force_inst);
     if (c->n_pairs > 0) {
         const int chunks = (c->max_size + kMigRows - 1) / kMigRows;
         hipLaunchKernelGGL(k_mig_adapt, dim3(c->n_pairs, chunks), dim3(256), 0, c->stream, di, dl, dp, ctl,
@@ -622,7 +622,7 @@ int ffs_create_instance(ffs_ctx* c, int32_t n, int32_t S, const int32_t* machine
     I.n_pad = (n + 31) & ~31;
     // chromosomes per wave: one lane per stage, capped so that a wave's
     // three LDS rows per chromosome stay within 32 KB
-    I.G = std::min(kWave / S, std::max(1, 32768 / (6 * I.n_pad)));
+    I.G = std::min(kWave / S, std::max(1, 32768 / (2 * group_stride(I.n_pad))));
     for (int x = 0; x < n_islands; ++x) {
         const ffs_island_spec& sp = islands[x];
         HostIsland L;

@@ -84,6 +84,20 @@ struct Control {
 
 extern __shared__ __align__(16) unsigned char ffs_smem[];
 
+// Global-memory views of generic pointers: accesses through them compile to
+// global (not flat) instructions, which the compiler may keep in flight
+// across LDS accesses.
+template <typename T>
+__device__ __forceinline__ const __attribute__((address_space(1))) T* as_global(const T* p)
+{
+    return (const __attribute__((address_space(1))) T*)p;
+}
+template <typename T>
+__device__ __forceinline__ __attribute__((address_space(1))) T* as_global(T* p)
+{
+    return (__attribute__((address_space(1))) T*)p;
+}
+
 __device__ __forceinline__ void wave_sync()
 {
     __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
@@ -93,10 +107,14 @@ __device__ __forceinline__ void wave_sync()
 
 __host__ __device__ inline size_t align16(size_t x) { return (x + 15) & ~(size_t)15; }
 
-// LDS bytes of one wave: three n_pad rows of uint16 per group.
+// LDS of one group: three n_pad rows of uint16 and 16 bytes of padding, so
+// that the groups of a wave start 4 banks apart and same-offset accesses of
+// different groups do not collide.
+__host__ __device__ inline int group_stride(int n_pad) { return 3 * n_pad + 8; }
+
 __host__ __device__ inline size_t wave_lds_bytes(int G, int n_pad)
 {
-    return (size_t)G * 3 * n_pad * 2;
+    return (size_t)G * group_stride(n_pad) * 2;
 }
 
 // The processing-time table is staged into LDS stage-major with each row
@@ -115,39 +133,133 @@ __host__ __device__ inline size_t pt_lds_bytes(int S, int n_pad)
 template <typename PT>
 __device__ __forceinline__ void stage_pt(PT* dst, const void* src, int S, int n_pad)
 {
-    const int wpr = (int)(n_pad * sizeof(PT) / 4), ld = wpr + 1;
-    const uint32_t* s = reinterpret_cast<const uint32_t*>(src);
+    constexpr int U = 4;
+    const int wpr = (int)(n_pad * sizeof(PT) / 4), ld = wpr + 1, nw = S * wpr;
+    const auto* s = as_global(reinterpret_cast<const uint32_t*>(src));
     uint32_t* d = reinterpret_cast<uint32_t*>(dst);
-    for (int w = threadIdx.x; w < S * wpr; w += blockDim.x) {
-        const int r = w / wpr, c = w - r * wpr;
-        d[r * ld + c] = s[w];
+    for (int w0 = threadIdx.x; w0 < nw; w0 += U * blockDim.x) {
+        uint32_t x[U];
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            const int w = w0 + u * blockDim.x;
+            x[u] = s[w < nw ? w : nw - 1];
+        }
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            // past the end: the last word again, with the same value
+            const int w = w0 + u * blockDim.x < nw ? w0 + u * blockDim.x : nw - 1;
+            const int r = w / wpr, c = w - r * wpr;
+            d[r * ld + c] = x[u];
+        }
     }
 }
 
 // ---- row copies by the S lanes of a group (16-byte vectors) ---------------
+// The global reads of a row are all issued before the LDS writes.
+typedef uint32_t u32x4 __attribute__((ext_vector_type(4)));
+
+__device__ __forceinline__ void rows_g2l(uint16_t* dA, const uint16_t* sA, uint16_t* dB, const uint16_t* sB,
+                                         int n_pad, int k, int S)
+{
+    constexpr int U = 4;
+    const auto* a4 = as_global(reinterpret_cast<const u32x4*>(sA));
+    const auto* b4 = as_global(reinterpret_cast<const u32x4*>(sB));
+    u32x4* da = reinterpret_cast<u32x4*>(dA);
+    u32x4* db = reinterpret_cast<u32x4*>(dB);
+    const int nv = n_pad >> 3;
+    for (int v0 = k; v0 < nv; v0 += U * S) {
+        u32x4 xa[U], xb[U];
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            const int v = v0 + u * S < nv ? v0 + u * S : nv - 1;
+            xa[u] = a4[v];
+            xb[u] = b4[v];
+        }
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            // past the end: the last vector again, with the same value
+            const int v = v0 + u * S < nv ? v0 + u * S : nv - 1;
+            da[v] = xa[u];
+            db[v] = xb[u];
+        }
+    }
+}
+
 __device__ __forceinline__ void row_g2l(uint16_t* dst, const uint16_t* src, int n_pad, int k, int S)
 {
-    const uint4* s4 = reinterpret_cast<const uint4*>(src);
-    uint4* d4 = reinterpret_cast<uint4*>(dst);
+    constexpr int U = 4;
+    const auto* s4 = as_global(reinterpret_cast<const u32x4*>(src));
+    u32x4* d4 = reinterpret_cast<u32x4*>(dst);
     const int nv = n_pad >> 3;
-#pragma unroll 4
-    for (int v = k; v < nv; v += S) d4[v] = s4[v];
+    for (int v0 = k; v0 < nv; v0 += U * S) {
+        u32x4 x[U];
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            const int v = v0 + u * S < nv ? v0 + u * S : nv - 1;
+            x[u] = s4[v];
+        }
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            const int v = v0 + u * S < nv ? v0 + u * S : nv - 1;
+            d4[v] = x[u];
+        }
+    }
 }
 
 __device__ __forceinline__ void row_l2g(uint16_t* dst, const uint16_t* src, int n_pad, int k, int S)
 {
-    const uint4* s4 = reinterpret_cast<const uint4*>(src);
-    uint4* d4 = reinterpret_cast<uint4*>(dst);
+    const u32x4* s4 = reinterpret_cast<const u32x4*>(src);
+    auto* d4 = as_global(reinterpret_cast<u32x4*>(dst));
     const int nv = n_pad >> 3;
 #pragma unroll 4
     for (int v = k; v < nv; v += S) d4[v] = s4[v];
 }
 
 // ---- pipelined decode -----------------------------------------------------
-// Value of `x` held by lane - 1 (whole-wave shift right by one lane, DPP).
+// Value of `x` held by lane - 1 (whole-wave shift right by one lane, DPP;
+// lane 0 reads 0).
 __device__ __forceinline__ uint32_t from_prev_lane(uint32_t x)
 {
-    return (uint32_t)__builtin_amdgcn_update_dpp(0, (int)x, 0x138 /* wave_shr:1 */, 0xF, 0xF, false);
+    return (uint32_t)__builtin_amdgcn_mov_dpp((int)x, 0x138 /* wave_shr:1 */, 0xF, 0xF, true);
+}
+
+// One step of stage k (see decode_pipelined).  With PRED the lane acts only
+// while rel < n_act and takes a job only while rel < n; without it the caller
+// guarantees both for every lane that matters.
+template <int MMAX, bool PRED, typename PT>
+__device__ __forceinline__ void pipe_step(uint32_t (&key)[MMAX], uint32_t& o_key, uint32_t& o_p, uint32_t& pn_pre,
+                                          uint32_t ap, uint32_t rel, uint32_t n_act, uint32_t un, bool first,
+                                          uint32_t jb, uint32_t jmask, const PT* prow_next)
+{
+    constexpr uint32_t PAD = 0xFFFFFFFFu;
+    const uint32_t in_key = from_prev_lane(o_key);
+    const uint32_t in_p = from_prev_lane(o_p);
+    if (!PRED || rel < n_act) {
+        const bool have = !PRED || rel < un;
+        const uint32_t j = first ? (ap & 0xFFFFu) : (in_key & jmask);
+        const uint32_t r = first ? 0u : (in_key >> jb);
+        const uint32_t pj = first ? (ap >> 16) : in_p;
+        const uint32_t o = key[0];
+        const uint32_t f = o >> jb;
+        const uint32_t st = f > r ? f : r;
+        const uint32_t c = st + pj;
+        const uint32_t nk = have ? ((c << jb) | j) : PAD;
+        const uint32_t ithr = have ? ((c + 1u) << jb) : PAD;
+        uint32_t nkey[MMAX];
+        bool prev = true;
+#pragma unroll
+        for (int i = 0; i < MMAX; ++i) {
+            const bool lt = (i + 1 < MMAX) ? (key[(i + 1 < MMAX) ? i + 1 : i] < ithr) : false;
+            nkey[i] = lt ? key[(i + 1 < MMAX) ? i + 1 : i] : (prev ? nk : key[i]);
+            prev = lt;
+        }
+#pragma unroll
+        for (int i = 0; i < MMAX; ++i) key[i] = nkey[i];
+        o_key = o;
+        o_p = pn_pre;
+    }
+    const uint32_t q = key[0] & jmask;
+    pn_pre = (uint32_t)prow_next[min(q, un - 1u)];
 }
 
 // One group of S lanes decodes one permutation; lane k runs stage k.
@@ -170,6 +282,9 @@ __device__ __forceinline__ uint32_t from_prev_lane(uint32_t x)
 // The decode therefore runs exactly n + sum_{k<S-1} (m_k + 1) steps, and a
 // job handed on in one step is taken by the next lane in the next step, so
 // one register pair per lane carries it: (key, processing time at k+1).
+// In steps [a_{S-1}, n) every stage is dispatching, so that stretch runs
+// without per-lane predication; lanes of unused groups then compute values
+// nobody reads (their loads stay in bounds).
 //
 // AP[t] = (p[job][0] << 16) | job for the permutation's t-th job.  Returns
 // the makespan on the lane of the last stage.
@@ -184,53 +299,44 @@ __device__ __forceinline__ uint32_t decode_pipelined(const uint32_t* AP, const P
         if (i < k) a_k += step;
         total += step;
     }
+    const int a_last = total - n;
     const int mstage = mach[k];
     uint32_t key[MMAX];
 #pragma unroll
     for (int i = 0; i < MMAX; ++i) key[i] = (i < mstage) ? 0u : PAD;
-    uint32_t cmax = 0;
     uint32_t o_key = 0, o_p = 0;
     const bool first = (k == 0), last = (k == S - 1);
     const uint32_t jmask = (1u << jb) - 1u;
+    const uint32_t ujb = (uint32_t)jb;
     const uint32_t un = (uint32_t)n;
     const uint32_t n_act = active ? (last ? un : un + (uint32_t)mstage) : 0u;
-    uint32_t ap0 = AP[0], ap1 = AP[n > 1 ? 1 : 0];
     uint32_t pn_pre = (uint32_t)prow_next[0];
-    for (int it = 0; it < total; ++it) {
-        const uint32_t in_key = from_prev_lane(o_key);
-        const uint32_t in_p = from_prev_lane(o_p);
-        const uint32_t ap = ap0;
-        ap0 = ap1;
-        ap1 = AP[(it + 2 < n) ? it + 2 : n - 1];
-        const uint32_t rel = (uint32_t)(it - a_k);
-        if (rel < n_act) {
-            const bool have = rel < un;
-            const uint32_t j = first ? (ap & 0xFFFFu) : (in_key & jmask);
-            const uint32_t r = first ? 0u : (in_key >> jb);
-            const uint32_t pj = first ? (ap >> 16) : in_p;
-            const uint32_t o = key[0];
-            const uint32_t f = o >> jb;
-            const uint32_t s = f > r ? f : r;
-            const uint32_t c = s + pj;
-            const uint32_t nk = have ? ((c << jb) | j) : PAD;
-            const uint32_t ithr = have ? ((c + 1u) << jb) : PAD;
-            uint32_t nkey[MMAX];
-            bool prev = true;
-#pragma unroll
-            for (int i = 0; i < MMAX; ++i) {
-                const bool lt = (i + 1 < MMAX) ? (key[(i + 1 < MMAX) ? i + 1 : i] < ithr) : false;
-                nkey[i] = lt ? key[(i + 1 < MMAX) ? i + 1 : i] : (prev ? nk : key[i]);
-                prev = lt;
-            }
-#pragma unroll
-            for (int i = 0; i < MMAX; ++i) key[i] = nkey[i];
-            o_key = o;
-            o_p = pn_pre;
+    // the steady stretch starts on a multiple of 4 so that its job words can
+    // be read four at a time (AP is 16-byte aligned)
+    const int steady0 = (a_last + 3) & ~3;
+    const int fill_end = steady0 < n ? steady0 : n;
+    int it = 0;
+    for (; it < fill_end; ++it)
+        pipe_step<MMAX, true, PT>(key, o_key, o_p, pn_pre, AP[it], (uint32_t)(it - a_k), n_act, un, first, ujb,
+                                  jmask, prow_next);
+    if (it + 3 < n) {
+        uint4 cur = *reinterpret_cast<const uint4*>(AP + it);
+        for (; it + 3 < n; it += 4) {
+            const int nx = (it + 7 < n) ? it + 4 : it;
+            const uint4 nxt = *reinterpret_cast<const uint4*>(AP + nx);
+            asm volatile("" ::: "memory");   // keep the read ahead of the four steps
+            pipe_step<MMAX, false, PT>(key, o_key, o_p, pn_pre, cur.x, 0u, 0u, un, first, ujb, jmask, prow_next);
+            pipe_step<MMAX, false, PT>(key, o_key, o_p, pn_pre, cur.y, 0u, 0u, un, first, ujb, jmask, prow_next);
+            pipe_step<MMAX, false, PT>(key, o_key, o_p, pn_pre, cur.z, 0u, 0u, un, first, ujb, jmask, prow_next);
+            pipe_step<MMAX, false, PT>(key, o_key, o_p, pn_pre, cur.w, 0u, 0u, un, first, ujb, jmask, prow_next);
+            cur = nxt;
         }
-        const uint32_t q = key[0] & jmask;
-        pn_pre = (uint32_t)prow_next[q < un ? q : 0u];
     }
+    for (; it < total; ++it)
+        pipe_step<MMAX, true, PT>(key, o_key, o_p, pn_pre, AP[it < n ? it : n - 1], (uint32_t)(it - a_k), n_act,
+                                  un, first, ujb, jmask, prow_next);
     // the last stage's list now holds every machine's final completion time
+    uint32_t cmax = 0;
 #pragma unroll
     for (int i = 0; i < MMAX; ++i) {
         const uint32_t c = (key[i] == PAD) ? 0u : (key[i] >> jb);
@@ -267,59 +373,121 @@ __device__ __forceinline__ void build_ap(uint32_t* AP, const uint16_t* A, const 
 // ---- order crossover on a group -------------------------------------------
 // A = parent 1 (becomes the child), B = parent 2, V = scratch for the inverse
 // of parent 1.  child[a..b] = P1[a..b]; P2 read cyclically from b+1 fills
-// b+1, ..., n-1, 0, ..., a-1 with the genes not in the segment.  Loops are
-// unrolled four chunks deep so that independent LDS reads overlap.
+// b+1, ..., n-1, 0, ..., a-1 with the genes not in the segment.  Lane k of
+// the group owns the cyclic offsets [kC, kC + C) of P2 (C = ceil(n / S)):
+// it counts the genes it keeps, an exclusive scan over the group's lanes
+// gives its first destination, and a second pass writes them.
+__device__ __forceinline__ uint32_t wrap_sub(uint32_t x, uint32_t n)
+{
+    const uint32_t y = x - n;   // x < 2n: x mod n
+    return y < x ? y : x;
+}
+
+// Register path for C <= kOxReg: each lane reads its parent-1 and parent-2
+// genes once, so the whole crossover costs three LDS round trips plus the
+// group scan.
+constexpr int kOxReg = 24;
+
+__device__ __forceinline__ int group_exclusive_scan(int v, int k, int S)
+{
+    int incl = v;
+    for (int d = 1; d < S; d <<= 1) {
+        const int up = __shfl_up(incl, d, 64);
+        if (k >= d) incl += up;
+    }
+    return incl - v;
+}
+
 __device__ __forceinline__ void ox_group(uint16_t* A, const uint16_t* B, uint16_t* V, int n, int a, int b,
                                          bool doit, int k, int S, int g)
 {
-    constexpr int U = 4;
+    const uint32_t un = (uint32_t)n, ua = (uint32_t)a, ub = (uint32_t)b;
+    const int C = (n + S - 1) / S;
+    const int o0 = k * C, o1 = (o0 + C < n) ? o0 + C : n;
+    if (C <= kOxReg) {
+        // lane k: positions [o0, o1) of parent 1 and cyclic offsets [o0, o1) of parent 2
+        uint32_t x1[kOxReg], x2[kOxReg];
+#pragma unroll
+        for (int u = 0; u < kOxReg; ++u) {
+            const bool ok = o0 + u < o1;
+            x1[u] = A[ok ? o0 + u : 0];
+            x2[u] = B[ok ? wrap_sub(ub + 1u + (uint32_t)(o0 + u), un) : 0u];
+        }
+        if (doit) {
+#pragma unroll
+            for (int u = 0; u < kOxReg; ++u)
+                if (o0 + u < o1) V[x1[u]] = (uint16_t)(o0 + u);
+        }
+        wave_sync();
+        uint32_t keep = 0;
+        int cnt = 0;
+#pragma unroll
+        for (int u = 0; u < kOxReg; ++u) {
+            const uint32_t iv = V[x2[u]];
+            const bool kp = (o0 + u < o1) && (iv < ua || iv > ub);
+            keep |= kp ? (1u << u) : 0u;
+            cnt += kp ? 1 : 0;
+        }
+        const int pre = group_exclusive_scan(cnt, k, S);
+        if (doit) {
+            uint32_t dst = wrap_sub(ub + 1u + (uint32_t)pre, un);
+#pragma unroll
+            for (int u = 0; u < kOxReg; ++u)
+                if (keep & (1u << u)) {
+                    A[dst] = (uint16_t)x2[u];
+                    dst = wrap_sub(dst + 1u, un);
+                }
+        }
+        wave_sync();
+        return;
+    }
+    // long rows: two passes over P2 in chunks of U
+    constexpr int U = 8;
     if (doit) {
-        for (int t0 = k; t0 < n; t0 += U * S) {
+        for (int t0 = o0; t0 < o1; t0 += U) {
             uint32_t x[U];
 #pragma unroll
-            for (int u = 0; u < U; ++u) {
-                const int t = t0 + u * S;
-                x[u] = A[t < n ? t : 0];
-            }
+            for (int u = 0; u < U; ++u) x[u] = A[t0 + u < o1 ? t0 + u : 0];
 #pragma unroll
-            for (int u = 0; u < U; ++u) {
-                const int t = t0 + u * S;
-                if (t < n) V[x[u]] = (uint16_t)t;
-            }
+            for (int u = 0; u < U; ++u)
+                if (t0 + u < o1) V[x[u]] = (uint16_t)(t0 + u);
         }
     }
     wave_sync();
-    const uint64_t gmask = (S >= 64) ? ~0ull : ((1ull << S) - 1ull);
-    const int shift = g * S;
-    const uint64_t below_me = (1ull << k) - 1ull;
-    int base = 0;
-    for (int c0 = 0; c0 < n; c0 += U * S) {
-        uint32_t gene[U];
-        bool ok[U];
+    int cnt = 0;
+    if (doit) {
+        for (int ob = o0; ob < o1; ob += U) {
+            uint32_t x[U];
 #pragma unroll
-        for (int u = 0; u < U; ++u) {
-            const int t = c0 + u * S + k;
-            ok[u] = doit && t < n;
-            int pos = b + 1 + t;
-            if (pos >= n) pos -= n;
-            gene[u] = B[ok[u] ? pos : 0];
-        }
-        bool keep[U];
-#pragma unroll
-        for (int u = 0; u < U; ++u) {
-            const int iv = V[gene[u]];
-            keep[u] = ok[u] && ((iv < a) || (iv > b));
-        }
-#pragma unroll
-        for (int u = 0; u < U; ++u) {
-            const uint64_t bal = __ballot(keep[u]);
-            const uint64_t gm = (shift < 64 ? (bal >> shift) : 0ull) & gmask;
-            if (keep[u]) {
-                int dst = b + 1 + base + __popcll(gm & below_me);
-                if (dst >= n) dst -= n;
-                A[dst] = (uint16_t)gene[u];
+            for (int u = 0; u < U; ++u) {
+                const uint32_t p = wrap_sub(ub + 1u + (uint32_t)(ob + u), un);
+                x[u] = B[(ob + u < o1) ? p : 0u];
             }
-            base += __popcll(gm);
+#pragma unroll
+            for (int u = 0; u < U; ++u) {
+                const uint32_t iv = V[x[u]];
+                cnt += (ob + u < o1 && (iv < ua || iv > ub)) ? 1 : 0;
+            }
+        }
+    }
+    const int pre = group_exclusive_scan(cnt, k, S);
+    if (doit) {
+        uint32_t dst = wrap_sub(ub + 1u + (uint32_t)pre, un);
+        for (int ob = o0; ob < o1; ob += U) {
+            uint32_t x[U];
+#pragma unroll
+            for (int u = 0; u < U; ++u) {
+                const uint32_t p = wrap_sub(ub + 1u + (uint32_t)(ob + u), un);
+                x[u] = B[(ob + u < o1) ? p : 0u];
+            }
+#pragma unroll
+            for (int u = 0; u < U; ++u) {
+                const uint32_t iv = V[x[u]];
+                if (ob + u < o1 && (iv < ua || iv > ub)) {
+                    A[dst] = (uint16_t)x[u];
+                    dst = wrap_sub(dst + 1u, un);
+                }
+            }
         }
     }
     wave_sync();
@@ -350,7 +518,7 @@ __device__ __forceinline__ CellMeta cellular_offspring(const InstDesc* I, const 
                                                    int S, int g, bool active)
 {
     const int n = I->n, n_pad = I->n_pad;
-    const int* mkp = L->mk[cur];
+    const auto* mkp = as_global(L->mk[cur]);
     const int rows = L->rows, cols = L->cols;
     const int r = slot / cols, c = slot - r * cols;
     const int nb0 = slot;
@@ -381,10 +549,7 @@ __device__ __forceinline__ CellMeta cellular_offspring(const InstDesc* I, const 
     int mj = mi + 1 + (int)below(draw32(bk, 5), (uint32_t)(n - 1));
     if (mj >= n) mj -= n;
     const uint16_t* gp = L->genes[cur];
-    if (active) {
-        row_g2l(A, gp + (size_t)bs * n_pad, n_pad, k, S);
-        row_g2l(B, gp + (size_t)ss * n_pad, n_pad, k, S);
-    }
+    if (active) rows_g2l(A, gp + (size_t)bs * n_pad, B, gp + (size_t)ss * n_pad, n_pad, k, S);
     wave_sync();
     ox_group(A, B, V, n, a, b, cx && active, k, S, g);
     swap_genes(A, mx && active && k == 0, mi, mj);
@@ -471,7 +636,7 @@ __global__ void __launch_bounds__(512) k_generation(const InstDesc* __restrict__
     const int g = lane / S, k = lane - g * S;
     const int local = wave * G + g;
     const bool active = (g < G) && (local < wi.count);
-    uint16_t* A = gbase + (size_t)(active ? g : 0) * 3 * n_pad;
+    uint16_t* A = gbase + (size_t)(active ? g : 0) * group_stride(n_pad);
     uint16_t* B = A + n_pad;
     uint16_t* V = B + n_pad;
     const int slot = wi.slot0 + (active ? local : 0);
@@ -523,7 +688,7 @@ __global__ void __launch_bounds__(512) k_generation(const InstDesc* __restrict__
     } else {
         // pseudo: X = better of the pair, Y = reverse(X); even slot gets
         // OX(X, Y), odd slot OX(Y, X), with shared cut points.
-        const int* mkp = L->mk[cur];
+        const auto* mkp = as_global(L->mk[cur]);
         const int q = slot >> 1;
         const bool odd = slot & 1;
         const int xs = (mkp[2 * q] <= mkp[2 * q + 1]) ? 2 * q : 2 * q + 1;
@@ -542,10 +707,21 @@ __global__ void __launch_bounds__(512) k_generation(const InstDesc* __restrict__
         if (active) row_g2l(V, L->genes[cur] + (size_t)xs * n_pad, n_pad, k, S);
         wave_sync();
         if (active) {
-            for (int t = k; t < n; t += S) {
-                const uint16_t x = V[t], xr = V[n - 1 - t];
-                A[t] = odd ? xr : x;
-                B[t] = odd ? x : xr;
+            constexpr int U = 4;
+            for (int t0 = k; t0 < n; t0 += U * S) {
+                uint16_t x[U], xr[U];
+#pragma unroll
+                for (int u = 0; u < U; ++u) {
+                    const int t = t0 + u * S < n ? t0 + u * S : n - 1;
+                    x[u] = V[t];
+                    xr[u] = V[n - 1 - t];
+                }
+#pragma unroll
+                for (int u = 0; u < U; ++u) {
+                    const int t = t0 + u * S < n ? t0 + u * S : n - 1;
+                    A[t] = odd ? xr[u] : x[u];
+                    B[t] = odd ? x[u] : xr[u];
+                }
             }
         }
         wave_sync();
@@ -690,7 +866,7 @@ __global__ void __launch_bounds__(512) k_evaluate(const InstDesc* __restrict__ I
     const int g = lane / S, k = lane - g * S;
     const long long idx = ((long long)blockIdx.x * wpb + wave) * G + g;
     const bool active = (g < G) && (idx < count);
-    uint16_t* A = gbase + (size_t)(active ? g : 0) * 3 * n_pad;
+    uint16_t* A = gbase + (size_t)(active ? g : 0) * group_stride(n_pad);
     uint16_t* V = A + 2 * n_pad;
     bool bad = false;
     if (active) {
@@ -752,7 +928,7 @@ __global__ void __launch_bounds__(512) k_candidates(const InstDesc* __restrict__
             slot = cell - X->cell_base;
         }
     }
-    uint16_t* A = gbase + (size_t)(active ? g : 0) * 3 * n_pad;
+    uint16_t* A = gbase + (size_t)(active ? g : 0) * group_stride(n_pad);
     uint16_t* B = A + n_pad;
     uint16_t* V = B + n_pad;
     const CellMeta meta = cellular_offspring(I, L, slot, (uint32_t)c, gen, cur, A, B, V, k, S, g, active);
@@ -887,40 +1063,141 @@ __global__ void __launch_bounds__(256) k_mig_ring(const InstDesc* __restrict__ i
     if (threadIdx.x == 0) L->mk[par][ds] = P->mk[par][ss];
 }
 
-// bitonic sort of (makespan << 32 | slot) keys of one island in LDS
-__global__ void __launch_bounds__(1024) k_mig_sort(const InstDesc* __restrict__ insts,
-                                                   const IslandDesc* __restrict__ isls, const Control* ctl,
-                                                   int force_inst)
+// Stable sort of one island's slots by makespan (ties keep slot order): a
+// least-significant-bit-first radix sort over the bits of (makespan - island
+// minimum), one bit per pass.  1024 threads hold R = max(1, P/1024) items
+// each in striped order (item i = r * 1024 + thread), so a wave ballot plus
+// per-(r, wave) zero counts give every item's rank among the zeros; a pass is
+// three block barriers, and an island whose makespans span 2^b values needs
+// b passes.  Padding items (i >= size) carry all ones and stay at the end.
+constexpr int kSortThreads = 1024;
+constexpr int kSortWaves = kSortThreads / 64;
+constexpr int kSortRMax = 16;
+
+__host__ __device__ inline size_t sort_lds_bytes(int R)
+{
+    return (size_t)R * kSortThreads * (sizeof(uint32_t) + sizeof(uint16_t)) +
+           (size_t)2 * kSortRMax * kSortWaves * sizeof(uint32_t) + 64;
+}
+
+__global__ void __launch_bounds__(kSortThreads) k_mig_sort(const InstDesc* __restrict__ insts,
+                                                           const IslandDesc* __restrict__ isls,
+                                                           const Control* ctl, int force_inst)
 {
     const IslandDesc* L = isls + blockIdx.x;
     const InstDesc* I = insts + L->inst;
     const int gen = ctl->gen;
     if (!migrating_now(I, L->inst, gen, force_inst)) return;
     const int N = L->size;
-    int P = 1;
-    while (P < N) P <<= 1;
-    unsigned long long* keys = reinterpret_cast<unsigned long long*>(ffs_smem);
+    int R = 1;
+    while (R * kSortThreads < N) R <<= 1;
+    const int P = R * kSortThreads;
+    const int t = threadIdx.x, wave = t >> 6, lane = t & 63;
+    uint32_t* dbuf = reinterpret_cast<uint32_t*>(ffs_smem);
+    uint16_t* sbuf = reinterpret_cast<uint16_t*>(dbuf + P);
+    uint32_t* zcnt = reinterpret_cast<uint32_t*>(sbuf + P);      // [r][wave] zeros, then exclusive prefix
+    uint32_t* zpre = zcnt + kSortRMax * kSortWaves;
+    uint32_t* misc = zpre + kSortRMax * kSortWaves;              // [0..15] wave minima, [16..31] maxima, [32] zeros
     const int* mk = L->mk[gen & 1];
-    for (int i = threadIdx.x; i < P; i += blockDim.x)
-        keys[i] = (i < N) ? (((unsigned long long)(unsigned)mk[i] << 32) | (unsigned)i) : ~0ull;
-    __syncthreads();
-    for (int kk = 2; kk <= P; kk <<= 1) {
-        for (int j = kk >> 1; j > 0; j >>= 1) {
-            for (int i = threadIdx.x; i < P; i += blockDim.x) {
-                const int ixj = i ^ j;
-                if (ixj > i) {
-                    const unsigned long long x = keys[i], y = keys[ixj];
-                    const bool up = (i & kk) == 0;
-                    if ((x > y) == up) {
-                        keys[i] = y;
-                        keys[ixj] = x;
-                    }
-                }
-            }
-            __syncthreads();
+
+    uint32_t d[kSortRMax], sl[kSortRMax];
+    uint32_t mn = 0xFFFFFFFFu, mx = 0u;
+#pragma unroll
+    for (int r = 0; r < kSortRMax; ++r) {
+        const int i = r * kSortThreads + t;
+        d[r] = 0xFFFFFFFFu;
+        sl[r] = (uint32_t)i;
+        if (r < R && i < N) {
+            d[r] = (uint32_t)mk[i];
+            mn = d[r] < mn ? d[r] : mn;
+            mx = d[r] > mx ? d[r] : mx;
         }
     }
-    for (int i = threadIdx.x; i < N; i += blockDim.x) L->sorted[i] = (int)(keys[i] & 0xFFFFFFFFu);
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) {
+        const uint32_t a = (uint32_t)__shfl_xor((int)mn, o, 64), b = (uint32_t)__shfl_xor((int)mx, o, 64);
+        mn = a < mn ? a : mn;
+        mx = b > mx ? b : mx;
+    }
+    if (lane == 0) {
+        misc[wave] = mn;
+        misc[kSortWaves + wave] = mx;
+    }
+    __syncthreads();
+    mn = 0xFFFFFFFFu;
+    mx = 0u;
+    for (int w = 0; w < kSortWaves; ++w) {
+        const uint32_t a = misc[w], b = misc[kSortWaves + w];
+        mn = a < mn ? a : mn;
+        mx = b > mx ? b : mx;
+    }
+    const uint32_t span = mx - mn;   // N >= 1, so mn <= mx
+    const int bits = span == 0u ? 0 : 32 - __clz((int)span);
+#pragma unroll
+    for (int r = 0; r < kSortRMax; ++r)
+        if (r < R && r * kSortThreads + t < N) d[r] -= mn;
+
+    const uint64_t below = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
+    for (int bit = 0; bit < bits; ++bit) {
+        // zeros per (r, wave)
+        uint64_t zm[kSortRMax];
+#pragma unroll
+        for (int r = 0; r < kSortRMax; ++r)
+            if (r < R) {
+                zm[r] = __ballot(((d[r] >> bit) & 1u) == 0u);
+                if (lane == 0) zcnt[r * kSortWaves + wave] = (uint32_t)__popcll(zm[r]);
+            }
+        __syncthreads();
+        // exclusive prefix over (r, wave) order, by wave 0: four entries per lane
+        if (wave == 0) {
+            const int nent = R * kSortWaves;
+            uint32_t v[4], run = 0;
+#pragma unroll
+            for (int e = 0; e < 4; ++e) {
+                const int idx = lane * 4 + e;
+                v[e] = idx < nent ? zcnt[idx] : 0u;
+                run += v[e];
+            }
+            uint32_t incl = run;
+#pragma unroll
+            for (int o = 1; o < 64; o <<= 1) {
+                const uint32_t up = (uint32_t)__shfl_up((int)incl, o, 64);
+                if (lane >= o) incl += up;
+            }
+            uint32_t ex = incl - run;
+#pragma unroll
+            for (int e = 0; e < 4; ++e) {
+                const int idx = lane * 4 + e;
+                if (idx < nent) zpre[idx] = ex;
+                ex += v[e];
+            }
+            if (lane == 63) misc[32] = incl;
+        }
+        __syncthreads();
+        const uint32_t Z = misc[32];
+#pragma unroll
+        for (int r = 0; r < kSortRMax; ++r)
+            if (r < R) {
+                const uint32_t i = (uint32_t)(r * kSortThreads + t);
+                const uint32_t zb = zpre[r * kSortWaves + wave] + (uint32_t)__popcll(zm[r] & below);
+                const uint32_t pos = ((d[r] >> bit) & 1u) ? Z + (i - zb) : zb;
+                dbuf[pos] = d[r];
+                sbuf[pos] = (uint16_t)sl[r];
+            }
+        __syncthreads();
+#pragma unroll
+        for (int r = 0; r < kSortRMax; ++r)
+            if (r < R) {
+                d[r] = dbuf[r * kSortThreads + t];
+                sl[r] = sbuf[r * kSortThreads + t];
+            }
+    }
+    int* out = L->sorted;
+#pragma unroll
+    for (int r = 0; r < kSortRMax; ++r) {
+        const int i = r * kSortThreads + t;
+        if (r < R && i < N) out[i] = (int)sl[r];
+    }
 }
 
 // adaptive penetration rule of equations (1)-(2) on one island pair, and the
