@@ -115,7 +115,8 @@ struct ffs_ctx {
     int gen = 0;
     std::string err;
     // layout
-    size_t off_ctl = 0, off_insts = 0, off_isls = 0, off_work = 0, off_pairs = 0, total = 0;
+    size_t off_ctl = 0, off_insts = 0, off_isls = 0, off_work = 0, off_pairs = 0, off_counts = 0, total = 0;
+    int max_work = 0;
     int n_isl = 0, n_work = 0, n_pairs = 0, max_size = 0;
     int mm = 2, ptb = 1;
     size_t lds_gen = 0, lds_sort = 0;
@@ -226,6 +227,8 @@ void layout(ffs_ctx* c)
     for (auto& I : c->inst)
         for (auto& L : I.isl) max_work += (size_t)((L.size + I.G - 1) / I.G);
     c->off_work = take(sizeof(WorkItem) * std::max<size_t>(1, max_work));
+    c->max_work = (int)max_work;
+    c->off_counts = take(sizeof(int) * (max_work + 1));
     c->off_pairs = take(sizeof(PairDesc) * (size_t)std::max(1, c->n_pairs));
     c->lds_gen = 0;
     for (auto& I : c->inst) {
@@ -238,7 +241,7 @@ void layout(ffs_ctx* c)
                 L.off_genes[b] = take((size_t)L.size * I.n_pad * 2);
                 L.off_mk[b] = take((size_t)L.size * sizeof(int));
             }
-            L.off_genkey = take(8);
+            L.off_genkey = take(16);
             L.off_minmax = take(16);
             L.off_sorted = take((size_t)L.size * sizeof(int));
         }
@@ -334,7 +337,10 @@ int launch_generation(ffs_ctx* c, int mode)
         c->ev_pool.pop_back();
         HIP_TRY(c, hipEventRecord(e0, c->stream));
     }
-    HIP_TRY(c, hipLaunchKernel(c->kgen, dim3(c->n_work), dim3(64 * c->wpb), args, c->lds_gen, c->stream));
+    // a generation launch has one workgroup more than work items: it folds
+    // the previous generation into the best-ever records
+    const unsigned grid = (unsigned)c->n_work + (mode == 0 ? 1u : 0u);
+    HIP_TRY(c, hipLaunchKernel(c->kgen, dim3(grid), dim3(64 * c->wpb), args, c->lds_gen, c->stream));
     if (e0) {
         HIP_TRY(c, hipEventRecord(e1, c->stream));
         c->ev_used.emplace_back(e0, e1);
@@ -342,8 +348,23 @@ int launch_generation(ffs_ctx* c, int mode)
     return FFS_OK;
 }
 
+// Folds the completed generation into the best-ever records if the next
+// generation launch has not done so yet.
+int flush_best(ffs_ctx* c)
+{
+    const InstDesc* di = reinterpret_cast<const InstDesc*>(c->ws + c->off_insts);
+    const IslandDesc* dl = reinterpret_cast<const IslandDesc*>(c->ws + c->off_isls);
+    Control* ctl = reinterpret_cast<Control*>(c->ws + c->off_ctl);
+    hipLaunchKernelGGL(k_best_flush, dim3(1), dim3(256), 0, c->stream, di, dl, ctl, (int)c->inst.size());
+    HIP_TRY(c, hipGetLastError());
+    return FFS_OK;
+}
+
 int launch_migration(ffs_ctx* c, int force_inst)
 {
+    // migration rewrites rows of the completed generation: record its best first
+    int frc = flush_best(c);
+    if (frc) return frc;
     const InstDesc* di = reinterpret_cast<const InstDesc*>(c->ws + c->off_insts);
     const IslandDesc* dl = reinterpret_cast<const IslandDesc*>(c->ws + c->off_isls);
     const PairDesc* dp = reinterpret_cast<const PairDesc*>(c->ws + c->off_pairs);
@@ -395,6 +416,14 @@ int apply_tile(ffs_ctx* c)
     if (c->n_work)
         HIP_TRY(c, hipMemcpy(c->ws + c->off_work, c->work.data(), sizeof(WorkItem) * c->work.size(),
                              hipMemcpyHostToDevice));
+    if (c->bound) {
+        // new launch width: count launches afresh from the current generation
+        HIP_TRY(c, hipStreamSynchronize(c->stream));
+        std::vector<int> zeros(c->max_work + 1, 0);
+        HIP_TRY(c, hipMemcpy(c->ws + c->off_counts, zeros.data(), zeros.size() * sizeof(int), hipMemcpyHostToDevice));
+        const int base = c->gen;
+        HIP_TRY(c, hipMemcpy(c->ws + c->off_ctl + offsetof(Control, base), &base, sizeof base, hipMemcpyHostToDevice));
+    }
     drop_graph(c);
     return FFS_OK;
 }
@@ -809,6 +838,12 @@ int ffs_bind_workspace(ffs_ctx* c, void* dptr, size_t bytes)
     }
     Control ctl;
     memset(&ctl, 0, sizeof ctl);
+    ctl.counts = reinterpret_cast<int*>(c->ws + c->off_counts);
+    ctl.best_gen = -1;
+    {
+        std::vector<int> zeros(c->max_work + 1, 0);
+        HIP_TRY(c, hipMemcpy(c->ws + c->off_counts, zeros.data(), zeros.size() * sizeof(int), hipMemcpyHostToDevice));
+    }
     HIP_TRY(c, hipMemcpy(c->ws + c->off_ctl, &ctl, sizeof ctl, hipMemcpyHostToDevice));
     HIP_TRY(c, hipMemcpy(c->ws + c->off_insts, hi.data(), sizeof(InstDesc) * hi.size(), hipMemcpyHostToDevice));
     HIP_TRY(c, hipMemcpy(c->ws + c->off_isls, hl.data(), sizeof(IslandDesc) * hl.size(), hipMemcpyHostToDevice));
@@ -833,8 +868,8 @@ int ffs_bind_workspace(ffs_ctx* c, void* dptr, size_t bytes)
         const long long cnt[2] = {0, 0};
         HIP_TRY(c, hipMemcpy(c->ws + I.off_counters, cnt, sizeof cnt, hipMemcpyHostToDevice));
         for (auto& L : I.isl) {
-            const unsigned long long gk = ~0ull;
-            HIP_TRY(c, hipMemcpy(c->ws + L.off_genkey, &gk, 8, hipMemcpyHostToDevice));
+            const unsigned long long gk[2] = {~0ull, ~0ull};
+            HIP_TRY(c, hipMemcpy(c->ws + L.off_genkey, gk, sizeof gk, hipMemcpyHostToDevice));
         }
     }
     if (c->surr >= 0) {
@@ -968,6 +1003,8 @@ int ffs_best(ffs_ctx* c, int32_t inst, int32_t* out_mk, int32_t* out_gen, int32_
     if (rc) return rc;
     if (inst < 0 || inst >= (int)c->inst.size()) return fail(c, FFS_EINVAL, "no instance %d", inst);
     const auto& I = c->inst[inst];
+    rc = flush_best(c);
+    if (rc) return rc;
     int rec[4];
     std::vector<uint16_t> perm((size_t)I.n_pad);
     HIP_TRY(c, hipMemcpyAsync(rec, c->ws + I.off_best_rec, sizeof rec, hipMemcpyDeviceToHost, c->stream));

@@ -56,7 +56,7 @@ struct InstDesc {
 struct IslandDesc {
     uint16_t* genes[2];          // [size][n_pad] per generation parity
     int* mk[2];                  // [size]
-    unsigned long long* genkey;  // min of (makespan << 32 | slot) this generation
+    unsigned long long* genkey;  // [2]: min of (makespan << 32 | slot), by generation parity
     unsigned long long* minmax;  // [2] min / max keys (ring migration)
     int* sorted;                 // [size] slots by (makespan, slot) (migration)
     unsigned long long tc, tm;   // crossover / mutation thresholds (< tc, < tm)
@@ -75,12 +75,23 @@ struct PairDesc {
     int a, b, inst, pad;
 };
 
+// Generation bookkeeping without a last-workgroup handshake or a shared
+// counter: workgroup b of every generation launch keeps its own count of the
+// launches it has run, counts[b], so launch number counts[b] after `base`
+// runs generation base + 1 + counts[b]; the counts of all workgroups agree
+// between launches, and kernels that run between launches read counts[0].
 struct Control {
-    int gen;
-    unsigned int done;
+    int* counts;                 // [workgroups per generation launch]
+    int base;                    // completed generation when the counts were zero
+    int best_gen;                // last generation folded into the best-ever records
     int err;                     // bit 0: invalid permutation, bit 1: decode fault
     int pad;
 };
+
+__device__ __forceinline__ int completed_gen(const Control* c)
+{
+    return c->base + c->counts[0];
+}
 
 extern __shared__ __align__(16) unsigned char ffs_smem[];
 
@@ -203,6 +214,21 @@ __device__ __forceinline__ void row_g2l(uint16_t* dst, const uint16_t* src, int 
             const int v = v0 + u * S < nv ? v0 + u * S : nv - 1;
             d4[v] = x[u];
         }
+    }
+}
+
+__device__ __forceinline__ void row_g2g(uint16_t* dst, const uint16_t* src, int n_pad, int k, int S)
+{
+    constexpr int U = 4;
+    const auto* s4 = as_global(reinterpret_cast<const u32x4*>(src));
+    auto* d4 = as_global(reinterpret_cast<u32x4*>(dst));
+    const int nv = n_pad >> 3;
+    for (int v0 = k; v0 < nv; v0 += U * S) {
+        u32x4 x[U];
+#pragma unroll
+        for (int u = 0; u < U; ++u) x[u] = s4[v0 + u * S < nv ? v0 + u * S : nv - 1];
+#pragma unroll
+        for (int u = 0; u < U; ++u) d4[v0 + u * S < nv ? v0 + u * S : nv - 1] = x[u];
     }
 }
 
@@ -612,6 +638,74 @@ __device__ __forceinline__ void features_group(const uint16_t* A, const PT* pT, 
     }
 }
 
+// ---- best-ever records ------------------------------------------------------
+// Folds generation g into the best-ever records of every instance: the
+// minimum (makespan, slot) key of each island, ties on makespan to the lowest
+// island; a strictly better makespan replaces the record and copies the
+// permutation from generation g's population.  Resets the islands' keys of
+// g's parity for generation g + 2.  Run by one workgroup; s_tmp holds
+// 3 * blockDim.x ints.
+__device__ void fold_best(const InstDesc* __restrict__ insts, const IslandDesc* __restrict__ isls, int n_inst,
+                          int g, Control* ctl, int* s_tmp)
+{
+    const int par = g & 1;
+    int* s_imp = s_tmp;
+    int* s_isl = s_imp + blockDim.x;
+    int* s_slot = s_isl + blockDim.x;
+    for (int base = 0; base < n_inst; base += blockDim.x) {
+        const int ii = base + threadIdx.x;
+        int imp = 0, bisl = -1, bslot = -1;
+        if (ii < n_inst) {
+            const InstDesc* J = insts + ii;
+            unsigned long long bkey = ~0ull;
+            for (int x = 0; x < J->n_islands; ++x) {
+                unsigned long long* gk = isls[J->island0 + x].genkey + par;
+                const unsigned long long v = __hip_atomic_load(gk, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                if (bisl < 0 || (v >> 32) < (bkey >> 32)) {
+                    bkey = v;
+                    bisl = x;
+                }
+                __hip_atomic_store(gk, ~0ull, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            }
+            bslot = (int)(bkey & 0xFFFFFFFFu);
+            const int bmk = (int)(bkey >> 32);
+            if (bmk < J->best_rec[0]) {
+                J->best_rec[0] = bmk;
+                J->best_rec[1] = g;
+                J->best_rec[2] = bisl;
+                J->best_rec[3] = bslot;
+                imp = 1;
+            }
+        }
+        s_imp[threadIdx.x] = imp;
+        s_isl[threadIdx.x] = bisl;
+        s_slot[threadIdx.x] = bslot;
+        __syncthreads();
+        const int lim = (n_inst - base) < (int)blockDim.x ? (n_inst - base) : (int)blockDim.x;
+        for (int t = 0; t < lim; ++t) {
+            if (!s_imp[t]) continue;
+            const InstDesc* J = insts + base + t;
+            const IslandDesc* X = isls + J->island0 + s_isl[t];
+            const uint4* s4 = reinterpret_cast<const uint4*>(X->genes[par] + (size_t)s_slot[t] * J->n_pad);
+            uint4* d4 = reinterpret_cast<uint4*>(J->best_perm);
+            for (int v = threadIdx.x; v < (J->n_pad >> 3); v += blockDim.x) d4[v] = s4[v];
+        }
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) ctl->best_gen = g;
+}
+
+// Folds the completed generation into the best-ever records unless that was
+// done already (one workgroup).
+__global__ void __launch_bounds__(256) k_best_flush(const InstDesc* __restrict__ insts,
+                                                    const IslandDesc* __restrict__ isls, Control* ctl, int n_inst)
+{
+    __shared__ int s_tmp[3 * 256];
+    const int g = completed_gen(ctl);
+    if (ctl->best_gen >= g) return;
+    fold_best(insts, isls, n_inst, g, ctl, s_tmp);
+}
+
 // ---- one generation (mode 0) or generation 0 (mode 1) of every island -----
 template <int MMAX, typename PT>
 __global__ void __launch_bounds__(512) k_generation(const InstDesc* __restrict__ insts,
@@ -619,16 +713,36 @@ __global__ void __launch_bounds__(512) k_generation(const InstDesc* __restrict__
                                                     const WorkItem* __restrict__ work, Control* ctl, int n_inst,
                                                     int mode)
 {
+    // generation number from this workgroup's launch count (generation 0 has none)
+    __shared__ int s_gen;
+    if (threadIdx.x == 0) {
+        int gg = 0;
+        if (mode == 0) {
+            int* cnt = ctl->counts + blockIdx.x;
+            const int t = *cnt;
+            *cnt = t + 1;
+            gg = ctl->base + 1 + t;
+        }
+        s_gen = gg;
+    }
+    // the workgroup after the work items folds the previous generation into
+    // the best-ever records while the others run this one
+    if (mode == 0 && blockIdx.x == gridDim.x - 1) {
+        __syncthreads();
+        const int prev = s_gen - 1;
+        if (ctl->best_gen < prev) fold_best(insts, isls, n_inst, prev, ctl, reinterpret_cast<int*>(ffs_smem));
+        return;
+    }
     const WorkItem wi = work[blockIdx.x];
     const InstDesc* I = insts + wi.inst;
     const IslandDesc* L = isls + wi.island;
     const int n = I->n, S = I->S, n_pad = I->n_pad, jb = I->jb, G = I->G;
-    const int gen = (mode == 1) ? 0 : (ctl->gen + 1);
-    const int cur = (gen + 1) & 1, nxt = gen & 1;
 
     PT* pT = reinterpret_cast<PT*>(ffs_smem);
     stage_pt<PT>(pT, I->pT, S, n_pad);
     __syncthreads();
+    const int gen = s_gen;
+    const int cur = (gen + 1) & 1, nxt = gen & 1;
 
     const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
     uint16_t* gbase = reinterpret_cast<uint16_t*>(ffs_smem + pt_lds_bytes<PT>(S, n_pad) +
@@ -743,15 +857,13 @@ __global__ void __launch_bounds__(512) k_generation(const InstDesc* __restrict__
             mk_new = cmg;
             row_l2g(dstrow, A, n_pad, k, S);
         } else {
-            const int mk_old = L->mk[cur][slot];
+            const int mk_old = as_global(L->mk[cur])[slot];
             const bool rep = cmg < mk_old;
             mk_new = rep ? cmg : mk_old;
             if (rep) {
                 row_l2g(dstrow, A, n_pad, k, S);
             } else {
-                const uint4* s4 = reinterpret_cast<const uint4*>(L->genes[cur] + (size_t)slot * n_pad);
-                uint4* d4 = reinterpret_cast<uint4*>(dstrow);
-                for (int v = k; v < (n_pad >> 3); v += S) d4[v] = s4[v];
+                row_g2g(dstrow, L->genes[cur] + (size_t)slot * n_pad, n_pad, k, S);
             }
         }
         if (k == 0) L->mk[nxt][slot] = mk_new;
@@ -784,69 +896,11 @@ __global__ void __launch_bounds__(512) k_generation(const InstDesc* __restrict__
     __shared__ unsigned long long s_wmin[8];
     if (lane == 0) s_wmin[wave] = wkey;
 
-    // ---- the last workgroup to finish updates the best-ever records --------
-    __shared__ int s_last;
     __syncthreads();
     if (threadIdx.x == 0) {
         unsigned long long mn = ~0ull;
         for (int x = 0; x < (int)(blockDim.x >> 6); ++x) mn = s_wmin[x] < mn ? s_wmin[x] : mn;
-        if (mn != ~0ull) atomicMin(L->genkey, mn);
-        __threadfence();
-        const unsigned prev = atomicAdd(&ctl->done, 1u);
-        s_last = (prev == gridDim.x - 1) ? 1 : 0;
-    }
-    __syncthreads();
-    if (!s_last) return;
-    __threadfence();
-    // the staging LDS is free now: reuse it for the per-instance results
-    int* s_imp = reinterpret_cast<int*>(ffs_smem);
-    int* s_isl = s_imp + blockDim.x;
-    int* s_slot = s_isl + blockDim.x;
-    for (int base = 0; base < n_inst; base += blockDim.x) {
-        const int ii = base + threadIdx.x;
-        int imp = 0, bisl = -1, bslot = -1;
-        if (ii < n_inst) {
-            const InstDesc* J = insts + ii;
-            unsigned long long bkey = ~0ull;
-            for (int x = 0; x < J->n_islands; ++x) {
-                unsigned long long* gk = isls[J->island0 + x].genkey;
-                const unsigned long long v = __hip_atomic_load(gk, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-                // (makespan, island, slot): strict on makespan keeps the lowest island
-                if (bisl < 0 || (v >> 32) < (bkey >> 32)) {
-                    bkey = v;
-                    bisl = x;
-                }
-                __hip_atomic_store(gk, ~0ull, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-            }
-            bslot = (int)(bkey & 0xFFFFFFFFu);
-            const int bmk = (int)(bkey >> 32);
-            if (bmk < J->best_rec[0]) {
-                J->best_rec[0] = bmk;
-                J->best_rec[1] = gen;
-                J->best_rec[2] = bisl;
-                J->best_rec[3] = bslot;
-                imp = 1;
-            }
-        }
-        s_imp[threadIdx.x] = imp;
-        s_isl[threadIdx.x] = bisl;
-        s_slot[threadIdx.x] = bslot;
-        __syncthreads();
-        const int lim = (n_inst - base) < (int)blockDim.x ? (n_inst - base) : (int)blockDim.x;
-        for (int t = 0; t < lim; ++t) {
-            if (!s_imp[t]) continue;
-            const InstDesc* J = insts + base + t;
-            const IslandDesc* X = isls + J->island0 + s_isl[t];
-            const uint4* s4 = reinterpret_cast<const uint4*>(X->genes[nxt] + (size_t)s_slot[t] * J->n_pad);
-            uint4* d4 = reinterpret_cast<uint4*>(J->best_perm);
-            for (int v = threadIdx.x; v < (J->n_pad >> 3); v += blockDim.x) d4[v] = s4[v];
-        }
-        __syncthreads();
-    }
-    if (threadIdx.x == 0) {
-        ctl->done = 0;
-        ctl->gen = gen;
-        __threadfence();
+        if (mn != ~0ull) atomicMin(L->genkey + (gen & 1), mn);
     }
 }
 
@@ -906,7 +960,8 @@ __global__ void __launch_bounds__(512) k_candidates(const InstDesc* __restrict__
 {
     const InstDesc* I = insts + inst;
     const int n = I->n, S = I->S, n_pad = I->n_pad, jb = I->jb, G = I->G, K = I->surr_k;
-    const int gen = ctl->gen + 1, cur = ctl->gen & 1;
+    const int done = completed_gen(ctl);
+    const int gen = done + 1, cur = done & 1;
     PT* pT = reinterpret_cast<PT*>(ffs_smem);
     stage_pt<PT>(pT, I->pT, S, n_pad);
     __syncthreads();
@@ -1011,7 +1066,7 @@ __global__ void __launch_bounds__(256) k_mig_minmax(const InstDesc* __restrict__
 {
     const IslandDesc* L = isls + blockIdx.x;
     const InstDesc* I = insts + L->inst;
-    const int gen = ctl->gen;
+    const int gen = completed_gen(ctl);
     if (!migrating_now(I, L->inst, gen, force_inst) || I->topology != 1) return;
     const int* mk = L->mk[gen & 1];
     unsigned long long mn = ~0ull, mx = 0ull;
@@ -1044,7 +1099,7 @@ __global__ void __launch_bounds__(256) k_mig_ring(const InstDesc* __restrict__ i
 {
     const IslandDesc* L = isls + blockIdx.x;
     const InstDesc* I = insts + L->inst;
-    const int gen = ctl->gen;
+    const int gen = completed_gen(ctl);
     if (!migrating_now(I, L->inst, gen, force_inst) || I->topology != 1) return;
     const int H = I->n_islands / 2;
     if (H == 0) return;
@@ -1086,7 +1141,7 @@ __global__ void __launch_bounds__(kSortThreads) k_mig_sort(const InstDesc* __res
 {
     const IslandDesc* L = isls + blockIdx.x;
     const InstDesc* I = insts + L->inst;
-    const int gen = ctl->gen;
+    const int gen = completed_gen(ctl);
     if (!migrating_now(I, L->inst, gen, force_inst)) return;
     const int N = L->size;
     int R = 1;
@@ -1211,7 +1266,7 @@ __global__ void __launch_bounds__(256) k_mig_adapt(const InstDesc* __restrict__ 
 {
     const PairDesc pd = pairs[blockIdx.x];
     const InstDesc* I = insts + pd.inst;
-    const int gen = ctl->gen;
+    const int gen = completed_gen(ctl);
     if (!migrating_now(I, pd.inst, gen, force_inst)) return;
     const IslandDesc* A = isls + pd.a;
     const IslandDesc* B = isls + pd.b;
