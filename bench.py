@@ -52,6 +52,10 @@ def parse():
     ap.add_argument("--cpu-seconds", type=float, default=12.0)
     ap.add_argument("--surrogate-seconds", type=float, default=8.0,
                     help="wall-clock budget of each side of the plain vs pre-screen comparison (0 = skip)")
+    ap.add_argument("--experiment", default="", choices=["", "islands"],
+                    help="islands: island-layout ablation and migration-gap sweep (prints one JSON line)")
+    ap.add_argument("--runs", type=int, default=20, help="seeds per configuration of --experiment")
+    ap.add_argument("--generations", type=int, default=2000, help="generations per run of --experiment")
     ap.add_argument("--calibrate-copy-mib", type=int, default=0,
                     help="only run a plain device copy of this many MiB (5 times), to calibrate HBM counters")
     return ap.parse_args()
@@ -170,12 +174,71 @@ def surrogate_compare(seconds: float) -> dict:
     return out
 
 
+def islands_experiment(runs: int, generations: int) -> dict:
+    """Island-layout ablation and migration-gap sweep in Section 5's setting
+    (300 jobs, 4 stages, 2 machines per stage, p uniform in [1, 5], 512
+    individuals; makespan objective): the dual heterogeneous layout, a single
+    cellular torus, a single pseudo population, two islands of one kind, and
+    the dual layout at migration gaps 10 ... 800.  `runs` GA seeds run as
+    instances of one batched context; best makespans are read at checkpoints."""
+    import numpy as np
+    import torch
+
+    from paper_1903_10722_amd import Context, inputs
+    w0 = inputs.paper_setting("dual")
+    p64, m64 = w0["p"].astype(np.int64), w0["m"].astype(np.int64)
+    lb = max(int(p64.sum(axis=1).max()), max(int(-(-p64[:, k].sum() // m64[k])) for k in range(p64.shape[1])))
+    configs = [(v, 500) for v in inputs.ISLAND_VARIANTS] + \
+              [("dual", i) for i in (10, 20, 50, 100, 200, 300, 800)]
+    checkpoints = [c for c in (50, 100, 200, 500, 1000, 2000) if c < generations] + [generations]
+    rows = []
+    for variant, interval in configs:
+        w = inputs.paper_setting(variant, interval=interval)
+        ctx = Context(device=0)
+        for r in range(runs):
+            ctx.add_instance(w["m"], w["p"], w["islands"], interval=interval, theta=w["theta"],
+                             topology=w["topology"], seed=1000 + r)
+        ctx.bind()
+        curve = []
+        ms, done = 0.0, 0
+        for c in checkpoints:
+            e0 = torch.cuda.Event(enable_timing=True)
+            e1 = torch.cuda.Event(enable_timing=True)
+            e0.record(ctx.stream)
+            ctx.evolve(c - done)
+            e1.record(ctx.stream)
+            best = np.array([ctx.best(i)["makespan"] for i in range(runs)], dtype=np.float64)
+            ms += e0.elapsed_time(e1)
+            done = c
+            curve.append({"generation": c, "best_mean": float(best.mean())})
+        found = [ctx.best(i)["generation"] for i in range(runs)]
+        ctx.close()
+        rows.append({"layout": variant,
+                     "islands": [f"cellular {x['rows']}x{x['cols']}" if x["kind"] == 0 else f"pseudo {x['size']}"
+                                 for x in w["islands"]],
+                     "interval": interval if len(w["islands"]) > 1 else None,
+                     "best_mean": float(best.mean()), "best_std": float(best.std(ddof=1)) if runs > 1 else 0.0,
+                     "best_min": int(best.min()), "best_max": int(best.max()),
+                     "gap_to_lb_mean": float((best.mean() - lb) / lb),
+                     "found_generation_mean": float(np.mean(found)), "curve": curve,
+                     "ms_per_generation_all_runs": ms / generations})
+        print(f"[islands] {variant} interval={interval}: mean {best.mean():.2f}", file=sys.stderr, flush=True)
+    return {"experiment": "islands",
+            "setting": "300 jobs, 4 stages, 2 machines per stage, p U[1,5]; 512 individuals; cellular rates "
+                       "1.00/0.05, pseudo crossover 0.75; theta 1; makespan objective",
+            "generations": generations, "runs": runs, "ga_seeds": f"1000..{1000 + runs - 1}",
+            "lower_bound": lb, "rows": rows}
+
+
 def main():
     args = parse()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}); the island GA of this "
               f"build keeps every island on a single MI355X.", file=sys.stderr)
         sys.exit(2)
+    if args.experiment == "islands":
+        print(json.dumps(islands_experiment(args.runs, args.generations)), flush=True)
+        return
     if args.calibrate_copy_mib:
         calibrate_copy(args.calibrate_copy_mib)
         return

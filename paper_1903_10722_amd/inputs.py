@@ -84,6 +84,59 @@ def workload(name: str, seed: int = 1, scale: int = 1) -> dict:
     raise KeyError(name)
 
 
+# Island layouts of the ablation (which kind of island, and how many), all
+# with the same number of individuals per generation.
+ISLAND_VARIANTS = ("dual", "cellular", "pseudo", "cellular2", "pseudo2")
+
+
+def _layout(variant: str, side: int, cell_rates, pair_rates) -> list:
+    half = side * side - (side * side) % 2
+    c = lambda r, k: cellular(r, k, *cell_rates)
+    if variant == "dual":
+        return [c(side, side), pseudo(half, *pair_rates)]
+    if variant == "cellular":
+        return [c(side, 2 * side)]
+    if variant == "pseudo":
+        return [pseudo(2 * half, *pair_rates)]
+    if variant == "cellular2":
+        return [c(side, side), c(side, side)]
+    if variant == "pseudo2":
+        return [pseudo(half, *pair_rates), pseudo(half, *pair_rates)]
+    raise KeyError(variant)
+
+
+def island_variant(variant: str, seed: int = 1, scale: int = 1, interval: int = 20) -> dict:
+    """The medium instance (n=100, S=5) with its 8192 individuals arranged as
+    dual (64x64 cellular + 4096 pseudo, the benchmarked layout), cellular (one
+    64x128 torus), pseudo (one island of 8192), cellular2 (two 64x64 tori) or
+    pseudo2 (two islands of 4096); two-island layouts migrate every
+    `interval` generations with the adaptive rule.  `scale` divides island
+    sides (and pseudo sizes by its square) for oracle-sized runs."""
+    m, p = make_instance(100, 5, 1, 5, seed=seed)
+    isl = _layout(variant, max(3, 64 // scale), (CELL_PC, CELL_PM), (PAIR_PC, PAIR_PM))
+    return dict(name=f"islands:{variant}", m=m, p=p, islands=isl, generations=2000, interval=interval,
+                theta=1.0, topology=0)
+
+
+# Section 5's experimental setting: 300 jobs, 4 stages, 2 machines per stage,
+# processing times uniform in [1, 5] (Table 1), 256 individuals per island
+# (512 for a single-population GA), crossover 1.00 / mutation 0.05 on the
+# cellular island and crossover 0.75 on the pseudo island, 2000 generations,
+# theta 1.  Identical machines and the makespan objective replace Table 1's
+# unrelated machines, release and due dates.
+PAPER_CELL_RATES = (1.0, 0.05)
+PAPER_PAIR_RATES = (0.75, 0.0)
+
+
+def paper_setting(variant: str = "dual", seed: int = 1, interval: int = 500) -> dict:
+    """Section 5's problem and population sizes with the layouts of
+    island_variant at 512 individuals (dual = 16x16 cellular + 256 pseudo)."""
+    m, p = make_instance(300, 4, 2, 2, p_lo=1, p_hi=5, seed=seed, machines=[2, 2, 2, 2])
+    isl = _layout(variant, 16, PAPER_CELL_RATES, PAPER_PAIR_RATES)
+    return dict(name=f"paper:{variant}", m=m, p=p, islands=isl, generations=2000, interval=interval,
+                theta=1.0, topology=0)
+
+
 def batched_workloads(count: int = 256, batch_seed: int = 7, scale: int = 1, n_choices=None) -> list[dict]:
     """The uneven batch: per instance n in {20,50,100,200,500}, S in {5,10,20},
     machines per stage uniform [1,5], p uniform [1,99], a dual island with an

@@ -61,3 +61,14 @@ def test_oracle_and_library_share_no_code():
     for f in os.listdir(os.path.join(ROOT, "paper_1903_10722_amd")):
         if f.endswith(".py"):
             assert "import oracle" not in open(os.path.join(ROOT, "paper_1903_10722_amd", f)).read()
+
+
+def test_island_variants_hold_8192_individuals():
+    """Host-side check of the ablation layouts: every layout holds the same
+    8192 individuals per generation on the same instance."""
+    from paper_1903_10722_amd import inputs
+    base = inputs.island_variant("dual")
+    for v in inputs.ISLAND_VARIANTS:
+        w = inputs.island_variant(v)
+        assert sum(x["size"] for x in w["islands"]) == 8192
+        assert (w["p"] == base["p"]).all() and (w["m"] == base["m"]).all()
