@@ -179,7 +179,9 @@ def islands_experiment(runs: int, generations: int) -> dict:
     (300 jobs, 4 stages, 2 machines per stage, p uniform in [1, 5], 512
     individuals; makespan objective): the dual heterogeneous layout, a single
     cellular torus, a single pseudo population, two islands of one kind, and
-    the dual layout at migration gaps 10 ... 800.  `runs` GA seeds run as
+    the dual layout at migration gaps 10 ... 800, and the cellular parent
+    selection variants (self + best neighbour, binary tournaments) on the
+    layouts with cellular islands.  `runs` GA seeds run as
     instances of one batched context; best makespans are read at checkpoints."""
     import numpy as np
     import torch
@@ -188,12 +190,13 @@ def islands_experiment(runs: int, generations: int) -> dict:
     w0 = inputs.paper_setting("dual")
     p64, m64 = w0["p"].astype(np.int64), w0["m"].astype(np.int64)
     lb = max(int(p64.sum(axis=1).max()), max(int(-(-p64[:, k].sum() // m64[k])) for k in range(p64.shape[1])))
-    configs = [(v, 500) for v in inputs.ISLAND_VARIANTS] + \
-              [("dual", i) for i in (10, 20, 50, 100, 200, 300, 800)]
+    configs = [(v, 500, 0) for v in inputs.ISLAND_VARIANTS] + \
+              [("dual", i, 0) for i in (10, 20, 50, 100, 200, 300, 800)] + \
+              [(v, 500, sel) for sel in (1, 2) for v in ("dual", "cellular", "cellular2")]
     checkpoints = [c for c in (50, 100, 200, 500, 1000, 2000) if c < generations] + [generations]
     rows = []
-    for variant, interval in configs:
-        w = inputs.paper_setting(variant, interval=interval)
+    for variant, interval, sel in configs:
+        w = inputs.paper_setting(variant, interval=interval, sel=sel)
         ctx = Context(device=0)
         for r in range(runs):
             ctx.add_instance(w["m"], w["p"], w["islands"], interval=interval, theta=w["theta"],
@@ -213,7 +216,7 @@ def islands_experiment(runs: int, generations: int) -> dict:
             curve.append({"generation": c, "best_mean": float(best.mean())})
         found = [ctx.best(i)["generation"] for i in range(runs)]
         ctx.close()
-        rows.append({"layout": variant,
+        rows.append({"layout": variant, "selection": sel,
                      "islands": [f"cellular {x['rows']}x{x['cols']}" if x["kind"] == 0 else f"pseudo {x['size']}"
                                  for x in w["islands"]],
                      "interval": interval if len(w["islands"]) > 1 else None,
@@ -222,7 +225,8 @@ def islands_experiment(runs: int, generations: int) -> dict:
                      "gap_to_lb_mean": float((best.mean() - lb) / lb),
                      "found_generation_mean": float(np.mean(found)), "curve": curve,
                      "ms_per_generation_all_runs": ms / generations})
-        print(f"[islands] {variant} interval={interval}: mean {best.mean():.2f}", file=sys.stderr, flush=True)
+        print(f"[islands] {variant} interval={interval} selection={sel}: mean {best.mean():.2f}", file=sys.stderr,
+              flush=True)
     return {"experiment": "islands",
             "setting": "300 jobs, 4 stages, 2 machines per stage, p U[1,5]; 512 individuals; cellular rates "
                        "1.00/0.05, pseudo crossover 0.75; theta 1; makespan objective",

@@ -51,10 +51,18 @@ enum {
 /* One island.  Paper Section 4.1: island A runs the cellular GA, island B the
  * pseudo GA, each with its own crossover / mutation rates (parameter level).
  *   kind 0 (cellular): individuals on a rows x cols torus (rows, cols >= 3);
- *          each cell mates the two best of its von Neumann neighbourhood
- *          (self, north, east, south, west), applies order crossover with
- *          probability p_c and a swap mutation with probability p_m, and
- *          keeps the child only if its makespan is strictly lower.
+ *          each cell picks two parents in its von Neumann neighbourhood
+ *          (self, north, east, south, west) by `selection`, applies order
+ *          crossover with probability p_c and a swap mutation with
+ *          probability p_m, and keeps the child only if its makespan is
+ *          strictly lower.  selection (the paper only says two individuals
+ *          of the nearby area are selected, Section 4.2):
+ *            0: the two best by (makespan, neighbourhood order);
+ *            1: the cell itself and the best of north, east, south, west;
+ *            2: two binary tournaments: draws 6 and 7 of the cell's CELL
+ *               block each give x uniform in [0, 25), the neighbourhood
+ *               positions x / 5 and x % 5, and the better of the two by
+ *               (makespan, position) is the parent.
  *   kind 1 (pseudo): `size` individuals (even, >= 2) in fixed pairs; each pair
  *          mates its better member with that member's complement (the
  *          reversed permutation) and both children replace the pair.
@@ -64,6 +72,7 @@ typedef struct {
     int32_t rows, cols;   /* kind 0 */
     int32_t size;         /* kind 1; ignored for kind 0 (rows*cols)           */
     double p_c, p_m;      /* in [0, 1]                                        */
+    int32_t selection;    /* kind 0: 0, 1 or 2 (above); kind 1: must be 0     */
 } ffs_island_spec;
 
 /* Migration (paper Section 4.3).  Islands are paired (i, i + H), H = half the

@@ -66,6 +66,11 @@ def _load():
     lib.or_fisher_yates.restype = None
     lib.or_cell_parents.argtypes = [ctypes.c_int, ctypes.c_int, _i32p, ctypes.c_int, _i32p, _i32p]
     lib.or_cell_parents.restype = None
+    lib.or_cell_parents_sel.argtypes = [ctypes.c_int, ctypes.c_int, _i32p, ctypes.c_int, ctypes.c_int,
+                                        ctypes.c_uint32, ctypes.c_uint32, _i32p, _i32p]
+    lib.or_cell_parents_sel.restype = None
+    lib.or_ga_set_selection.argtypes = [ctypes.c_void_p, ctypes.c_int, ctypes.c_int]
+    lib.or_ga_set_selection.restype = None
     lib.or_migration_policy.argtypes = [ctypes.c_int64, ctypes.c_int64, ctypes.c_int64,
                                         ctypes.c_int64, ctypes.c_int64, ctypes.c_double,
                                         ctypes.POINTER(ctypes.c_int)]
@@ -154,11 +159,16 @@ def fisher_yates(n: int, seed: int, inst: int, island: int, slot: int) -> np.nda
     return out
 
 
-def cell_parents(rows: int, cols: int, mk, slot: int) -> tuple[int, int]:
+def cell_parents(rows: int, cols: int, mk, slot: int, sel: int = 0, d6: int = 0, d7: int = 0) -> tuple[int, int]:
+    """Parent slots of cell `slot` (selection variant `sel`; d6, d7 are the
+    cell's draws 6 and 7, used by the binary tournaments of sel 2)."""
     mk = _i32(mk)
     a = ctypes.c_int32()
     b = ctypes.c_int32()
-    _load().or_cell_parents(rows, cols, _ptr(mk, _i32p), slot, ctypes.byref(a), ctypes.byref(b))
+    if sel == 0:
+        _load().or_cell_parents(rows, cols, _ptr(mk, _i32p), slot, ctypes.byref(a), ctypes.byref(b))
+    else:
+        _load().or_cell_parents_sel(rows, cols, _ptr(mk, _i32p), slot, sel, d6, d7, ctypes.byref(a), ctypes.byref(b))
     return a.value, b.value
 
 
@@ -191,6 +201,9 @@ class GA:
                                          _ptr(kinds, _i32p), _ptr(rows, _i32p), _ptr(cols, _i32p),
                                          _ptr(sizes, _i32p), _ptr(pc, _f64p), _ptr(pm, _f64p),
                                          interval, theta, topology, seed, inst)
+        for i, x in enumerate(self.islands):
+            if x["kind"] == 0 and int(x.get("sel", 0)):
+                self._lib.or_ga_set_selection(self._h, i, int(x["sel"]))
 
     def __del__(self):
         h = getattr(self, "_h", None)

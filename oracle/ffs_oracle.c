@@ -189,7 +189,24 @@ void or_fisher_yates(int n, uint64_t seed, uint64_t inst, int island, int slot, 
 /* Parent choice on the torus: the von Neumann neighbourhood in the fixed
  * order (self, north, east, south, west); P1 is the best by (makespan, order
  * position), P2 the best of the other four.                                 */
-void or_cell_parents(int rows, int cols, const int *mk, int slot, int *p1, int *p2)
+/* Parent selection variants (the paper only says two individuals are
+ * selected from the nearby area; Section 4.2):
+ *   sel 0: P1 = the best of (self, N, E, S, W) by (makespan, order position),
+ *          P2 = the best of the other four;
+ *   sel 1: P1 = self, P2 = the best of (N, E, S, W) by (makespan, order);
+ *   sel 2: binary tournaments: draw d6 gives x uniform in [0, 25), the
+ *          positions x / 5 and x % 5 of the neighbourhood, and P1 is the
+ *          better of the two by (makespan, order position); draw d7 gives P2
+ *          the same way (P2 may equal P1).                                   */
+static int better_pos(const int *mk, const int *nb, int i, int j)
+{
+    if (mk[nb[j]] < mk[nb[i]]) return j;
+    if (mk[nb[j]] == mk[nb[i]] && j < i) return j;
+    return i;
+}
+
+void or_cell_parents_sel(int rows, int cols, const int *mk, int slot, int sel, uint32_t d6, uint32_t d7,
+                         int *p1, int *p2)
 {
     int r = slot / cols, c = slot % cols;
     int nb[5];
@@ -198,6 +215,19 @@ void or_cell_parents(int rows, int cols, const int *mk, int slot, int *p1, int *
     nb[2] = r * cols + (c + 1) % cols;
     nb[3] = ((r + 1) % rows) * cols + c;
     nb[4] = r * cols + (c - 1 + cols) % cols;
+    if (sel == 1) {
+        int b = 1;
+        for (int t = 2; t < 5; ++t) if (mk[nb[t]] < mk[nb[b]]) b = t;
+        *p1 = nb[0];
+        *p2 = nb[b];
+        return;
+    }
+    if (sel == 2) {
+        uint32_t x = uniform_below(d6, 25u), y = uniform_below(d7, 25u);
+        *p1 = nb[better_pos(mk, nb, (int)(x / 5), (int)(x % 5))];
+        *p2 = nb[better_pos(mk, nb, (int)(y / 5), (int)(y % 5))];
+        return;
+    }
     int b1 = 0;
     for (int t = 1; t < 5; ++t) if (mk[nb[t]] < mk[nb[b1]]) b1 = t;
     int b2 = -1;
@@ -207,6 +237,11 @@ void or_cell_parents(int rows, int cols, const int *mk, int slot, int *p1, int *
     }
     *p1 = nb[b1];
     *p2 = nb[b2];
+}
+
+void or_cell_parents(int rows, int cols, const int *mk, int slot, int *p1, int *p2)
+{
+    or_cell_parents_sel(rows, cols, mk, slot, 0, 0u, 0u, p1, p2);
 }
 
 /* Migration decision for one island pair (Section 4.3, eq. (1)-(2)), with
@@ -242,6 +277,7 @@ typedef struct {
     int rows, cols;      /* cellular                                          */
     int size;            /* number of individuals                            */
     uint64_t tc, tm;     /* crossover / mutation thresholds                  */
+    int sel;             /* cellular parent selection variant (or_cell_parents_sel) */
     int *genes;          /* size * n, current generation                     */
     int *mk;             /* size                                             */
 } or_island_t;
@@ -355,11 +391,11 @@ static void cell_offspring(or_ga_t *g, int island, int s, int sub, int *child, i
     or_island_t *I = &g->isl[island];
     int n = g->n;
     int p1, p2;
-    or_cell_parents(I->rows, I->cols, I->mk, s, &p1, &p2);
-    uint32_t d[6];
-    for (int t = 0; t < 6; ++t)
+    uint32_t d[8];
+    for (int t = 0; t < 8; ++t)
         d[t] = or_draw(g->seed, g->inst, (uint32_t)island, (uint32_t)s, (uint32_t)sub, (uint32_t)g->gen, OR_CELL,
                        (uint32_t)t);
+    or_cell_parents_sel(I->rows, I->cols, I->mk, s, I->sel, d[6], d[7], &p1, &p2);
     const int *P1 = I->genes + (size_t)p1 * n, *P2 = I->genes + (size_t)p2 * n;
     int cx = (uint64_t)d[0] < I->tc;
     int u = (int)uniform_below(d[1], (uint32_t)n), v = (int)uniform_below(d[2], (uint32_t)n);
@@ -374,6 +410,13 @@ static void cell_offspring(or_ga_t *g, int island, int s, int sub, int *child, i
         meta[0] = p1; meta[1] = p2; meta[2] = cx; meta[3] = a; meta[4] = b;
         meta[5] = mx; meta[6] = mi; meta[7] = mj;
     }
+}
+
+/* Parent selection variant of a cellular island (see or_cell_parents_sel). */
+void or_ga_set_selection(void *h, int island, int sel)
+{
+    or_ga_t *g = (or_ga_t *)h;
+    g->isl[island].sel = sel;
 }
 
 /* Test access: the offspring a cell would get at the next generation from

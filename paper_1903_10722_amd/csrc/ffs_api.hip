@@ -660,11 +660,14 @@ int ffs_create_instance(ffs_ctx* c, int32_t n, int32_t S, const int32_t* machine
             return fail(c, FFS_EINVAL, "island %d: rates must be in [0, 1]", x);
         if (sp.kind == 0) {
             if (sp.rows < 3 || sp.cols < 3) return fail(c, FFS_EINVAL, "island %d: grid must be at least 3x3", x);
+            if (sp.selection < 0 || sp.selection > 2)
+                return fail(c, FFS_EINVAL, "island %d: selection must be 0, 1 or 2", x);
             if ((long long)sp.rows * sp.cols > 16384)
                 return fail(c, FFS_EUNSUPPORTED, "island %d: more than 16384 individuals", x);
             L.size = sp.rows * sp.cols;
         } else if (sp.kind == 1) {
             if (sp.size < 2 || (sp.size % 2) != 0) return fail(c, FFS_EINVAL, "island %d: pseudo size must be even >= 2", x);
+            if (sp.selection != 0) return fail(c, FFS_EINVAL, "island %d: selection applies to cellular islands", x);
             if (sp.size > 16384) return fail(c, FFS_EUNSUPPORTED, "island %d: more than 16384 individuals", x);
             L.size = sp.size;
         } else {
@@ -832,6 +835,7 @@ int ffs_bind_workspace(ffs_ctx* c, void* dptr, size_t bytes)
             e.inst = (int)ii;
             e.local = (int)x;
             e.cell_base = L.cell_base;
+            e.sel = L.spec.kind == 0 ? L.spec.selection : 0;
             hl.push_back(e);
         }
         isl_base += (int)I.isl.size();

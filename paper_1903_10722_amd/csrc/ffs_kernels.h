@@ -64,7 +64,7 @@ struct IslandDesc {
     int inst;
     int local;                   // island index inside its instance
     int cell_base;               // index of slot 0 among the instance's cellular cells
-    int pad;
+    int sel;                     // cellular parent selection variant (0, 1, 2)
 };
 
 struct WorkItem {
@@ -553,20 +553,61 @@ __device__ __forceinline__ CellMeta cellular_offspring(const InstDesc* I, const 
     const int nb3 = ((r == rows - 1) ? 0 : r + 1) * cols + c;
     const int nb4 = r * cols + ((c == 0) ? cols - 1 : c - 1);
     const int v0 = mkp[nb0], v1 = mkp[nb1], v2 = mkp[nb2], v3 = mkp[nb3], v4 = mkp[nb4];
-    int bv = v0, bs = nb0, bo = 0;
-    if (v1 < bv) { bv = v1; bs = nb1; bo = 1; }
-    if (v2 < bv) { bv = v2; bs = nb2; bo = 2; }
-    if (v3 < bv) { bv = v3; bs = nb3; bo = 3; }
-    if (v4 < bv) { bv = v4; bs = nb4; bo = 4; }
-    int sv = 0x7FFFFFFF, ss = -1;
-    if (bo != 0 && v0 < sv) { sv = v0; ss = nb0; }
-    if (bo != 1 && v1 < sv) { sv = v1; ss = nb1; }
-    if (bo != 2 && v2 < sv) { sv = v2; ss = nb2; }
-    if (bo != 3 && v3 < sv) { sv = v3; ss = nb3; }
-    if (bo != 4 && v4 < sv) { sv = v4; ss = nb4; }
-    if (ss < 0) ss = nb1;   // only when every makespan is INT_MAX (never)
     const Block4 bk = stream_block(I->seed, (uint64_t)I->inst_id, (uint32_t)L->local, (uint32_t)slot, sub,
                                    (uint32_t)gen, kCell, 0);
+    int bv, bs, sv, ss;
+    const int sel = L->sel;
+    if (sel == 1) {
+        // self + the best of (N, E, S, W) by (makespan, order)
+        bv = v0;
+        bs = nb0;
+        sv = v1;
+        ss = nb1;
+        if (v2 < sv) { sv = v2; ss = nb2; }
+        if (v3 < sv) { sv = v3; ss = nb3; }
+        if (v4 < sv) { sv = v4; ss = nb4; }
+    } else if (sel == 2) {
+        // binary tournaments: draws 6 and 7 each pick two positions of the
+        // neighbourhood (x / 5, x % 5 with x uniform in [0, 25)); the better
+        // by (makespan, position) wins
+        const int vv[5] = {v0, v1, v2, v3, v4}, nn[5] = {nb0, nb1, nb2, nb3, nb4};
+        int win[2];
+#pragma unroll
+        for (int t = 0; t < 2; ++t) {
+            const int x = (int)below(draw32(bk, 6 + t), 25u);
+            const int i = x / 5, j = x - 5 * (x / 5);
+            int vi = vv[0], vj = vv[0];
+#pragma unroll
+            for (int q = 1; q < 5; ++q) {
+                vi = (i == q) ? vv[q] : vi;
+                vj = (j == q) ? vv[q] : vj;
+            }
+            win[t] = (vj < vi || (vj == vi && j < i)) ? j : i;
+        }
+        bv = vv[0]; bs = nn[0]; sv = vv[0]; ss = nn[0];
+#pragma unroll
+        for (int q = 1; q < 5; ++q) {
+            if (win[0] == q) { bv = vv[q]; bs = nn[q]; }
+            if (win[1] == q) { sv = vv[q]; ss = nn[q]; }
+        }
+    } else {
+        // the two best of (self, N, E, S, W) by (makespan, order)
+        int bo = 0;
+        bv = v0;
+        bs = nb0;
+        if (v1 < bv) { bv = v1; bs = nb1; bo = 1; }
+        if (v2 < bv) { bv = v2; bs = nb2; bo = 2; }
+        if (v3 < bv) { bv = v3; bs = nb3; bo = 3; }
+        if (v4 < bv) { bv = v4; bs = nb4; bo = 4; }
+        sv = 0x7FFFFFFF;
+        ss = -1;
+        if (bo != 0 && v0 < sv) { sv = v0; ss = nb0; }
+        if (bo != 1 && v1 < sv) { sv = v1; ss = nb1; }
+        if (bo != 2 && v2 < sv) { sv = v2; ss = nb2; }
+        if (bo != 3 && v3 < sv) { sv = v3; ss = nb3; }
+        if (bo != 4 && v4 < sv) { sv = v4; ss = nb4; }
+        if (ss < 0) ss = nb1;   // only when every makespan is INT_MAX (never)
+    }
     const bool cx = (uint64_t)draw32(bk, 0) < L->tc;
     const int u = (int)below(draw32(bk, 1), (uint32_t)n), w = (int)below(draw32(bk, 2), (uint32_t)n);
     const int a = u < w ? u : w, b = u < w ? w : u;

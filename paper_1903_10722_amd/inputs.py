@@ -40,8 +40,11 @@ def random_perms(count: int, n: int, seed: int = 0) -> np.ndarray:
     return np.argsort(keys, axis=1).astype(np.int32)
 
 
-def cellular(rows: int, cols: int, pc: float, pm: float) -> dict:
-    return dict(kind=0, rows=rows, cols=cols, size=rows * cols, pc=pc, pm=pm)
+def cellular(rows: int, cols: int, pc: float, pm: float, sel: int = 0) -> dict:
+    """A rows x cols cellular island; `sel` is the parent selection variant
+    (0 two best of the neighbourhood, 1 self + best neighbour, 2 binary
+    tournaments)."""
+    return dict(kind=0, rows=rows, cols=cols, size=rows * cols, pc=pc, pm=pm, sel=sel)
 
 
 def pseudo(size: int, pc: float, pm: float) -> dict:
@@ -128,11 +131,12 @@ PAPER_CELL_RATES = (1.0, 0.05)
 PAPER_PAIR_RATES = (0.75, 0.0)
 
 
-def paper_setting(variant: str = "dual", seed: int = 1, interval: int = 500) -> dict:
+def paper_setting(variant: str = "dual", seed: int = 1, interval: int = 500, sel: int = 0) -> dict:
     """Section 5's problem and population sizes with the layouts of
-    island_variant at 512 individuals (dual = 16x16 cellular + 256 pseudo)."""
+    island_variant at 512 individuals (dual = 16x16 cellular + 256 pseudo);
+    `sel` is the cellular islands' parent selection variant."""
     m, p = make_instance(300, 4, 2, 2, p_lo=1, p_hi=5, seed=seed, machines=[2, 2, 2, 2])
-    isl = _layout(variant, 16, PAPER_CELL_RATES, PAPER_PAIR_RATES)
+    isl = _layout(variant, 16, PAPER_CELL_RATES + (sel,), PAPER_PAIR_RATES)
     return dict(name=f"paper:{variant}", m=m, p=p, islands=isl, generations=2000, interval=interval,
                 theta=1.0, topology=0)
 

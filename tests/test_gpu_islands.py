@@ -94,3 +94,33 @@ def test_paper_setting_batched_seeds(variant):
         assert ctx.best(i)["makespan"] == ga.best()["makespan"]
         assert ctx.migration_counters(i) == ga.counters()
     ctx.close()
+
+
+@pytest.mark.parametrize("sel", [1, 2])
+@pytest.mark.parametrize("variant", ["dual", "cellular2"])
+def test_selection_variants_trajectory(variant, sel):
+    """Parent selection variants (1: self + best neighbour, 2: binary
+    tournaments) on the medium instance's layouts at 1/8 of the side, and in
+    Section 5's setting with two GA seeds as two instances; 25 generations."""
+    ensure_built()
+    w = inputs.island_variant(variant, seed=1, scale=8, interval=10)
+    for x in w["islands"]:
+        if x["kind"] == 0:
+            x["sel"] = sel
+    ws = [w]
+    for r in range(2):
+        v = inputs.paper_setting(variant, interval=10, sel=sel)
+        v["seed"] = 2000 + r
+        ws.append(v)
+    n_isl = len(w["islands"])
+    say(f"[islands] {variant} selection {sel}")
+    ctx = make_ctx(ws)
+    gas = [oracle_ga(v, inst=i) for i, v in enumerate(ws)]
+    for g in (5, 20):
+        ctx.evolve(g)
+        for i, ga in enumerate(gas):
+            ga.evolve(g)
+            assert_same_state(ctx, ga, i, n_isl, f"{variant} sel {sel} instance {i} generation {ctx.generation}")
+    for i, ga in enumerate(gas):
+        assert ctx.best(i)["makespan"] == ga.best()["makespan"]
+    ctx.close()

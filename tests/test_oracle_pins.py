@@ -478,3 +478,59 @@ def test_ga_best_not_below_brute_force_optimum():
         assert b >= opt
         hits += b == opt
     assert hits >= 1
+
+
+# ---- parent selection variants (alternative readings of Section 4.2) ------
+def _d_for(x: int) -> int:
+    """A 32-bit draw whose multiply-shift value in [0, 25) is x."""
+    d = -(-(x << 32) // 25)
+    assert (d * 25) >> 32 == x
+    return d
+
+
+def test_selection_self_plus_best_neighbour_worked_example():
+    """sel 1 on the 3x3 grid of the worked example (hand-read): cell 4 keeps
+    itself as P1 and mates S (slot 7, makespan 30); cell 8 mates W (slot 7,
+    30, against N 40, E 90, S 60); cell 0 mates E (slot 1, 40, ahead of
+    S = slot 3, also 40, by order)."""
+    g = gold("cell_parents_worked_example.json")
+    got = [oracle.cell_parents(3, 3, g["mk"], s, sel=1) for s in (4, 8, 0)]
+    assert got == [(4, 7), (8, 7), (0, 1)]
+
+
+def test_selection_self_plus_best_neighbour_properties():
+    rng = np.random.default_rng(11)
+    for _ in range(200):
+        rows, cols = int(rng.integers(3, 7)), int(rng.integers(3, 7))
+        mk = rng.integers(10, 20, rows * cols).astype(np.int32)
+        s = int(rng.integers(0, rows * cols))
+        r, c = divmod(s, cols)
+        nbs = [((r - 1) % rows) * cols + c, r * cols + (c + 1) % cols, ((r + 1) % rows) * cols + c,
+               r * cols + (c - 1) % cols]
+        p1, p2 = oracle.cell_parents(rows, cols, mk, s, sel=1)
+        assert p1 == s
+        assert mk[p2] == min(mk[x] for x in nbs)
+        assert p2 == next(x for x in nbs if mk[x] == mk[p2])   # first in N, E, S, W order
+
+
+def test_selection_binary_tournament_counts():
+    """sel 2 over all 25 position pairs of a neighbourhood with distinct
+    makespans: the best of the five wins 9 of the 25 tournaments, the k-th
+    best wins 2(5-k)+1 of them, the worst only the one pair (worst, worst)."""
+    mk = np.array([50, 40, 60, 42, 70, 45, 90, 30, 35], dtype=np.int32)   # 3x3 torus
+    nbs = [4, 1, 5, 7, 3]                                                 # cell 4: self, N, E, S, W
+    order = sorted(nbs, key=lambda x: mk[x])                              # best first: 7, 1, 3, 5, 4
+    assert len({int(mk[x]) for x in nbs}) == 5
+    wins = {x: 0 for x in nbs}
+    for x in range(25):
+        p1, p2 = oracle.cell_parents(3, 3, mk, 4, sel=2, d6=_d_for(x), d7=_d_for(24 - x))
+        wins[p1] += 1
+        assert p1 in nbs and p2 in nbs
+    assert [wins[x] for x in order] == [9, 7, 5, 3, 1]
+
+
+def test_selection_binary_tournament_ties_go_to_order():
+    """Equal makespans: the earlier position of the neighbourhood wins."""
+    mk = np.full(9, 40, dtype=np.int32)
+    # x = 1 * 5 + 3: positions N (1) and S (3) -> N (slot 1); x = 4*5 + 0: W and self -> self
+    assert oracle.cell_parents(3, 3, mk, 4, sel=2, d6=_d_for(8), d7=_d_for(20)) == (1, 4)
