@@ -774,7 +774,18 @@ __global__ void __launch_bounds__(512) k_generation(const InstDesc* __restrict__
         if (ctl->best_gen < prev) fold_best(insts, isls, n_inst, prev, ctl, reinterpret_cast<int*>(ffs_smem));
         return;
     }
-    const WorkItem wi = work[blockIdx.x];
+    // When every workgroup is resident at once, give each XCD (the hardware
+    // places workgroup b on XCD b % 8) a contiguous run of work items, so
+    // that neighbouring cells share an L2; larger grids keep the
+    // largest-first order.
+    const int nw = (mode == 0) ? (int)gridDim.x - 1 : (int)gridDim.x;
+    int widx = (int)blockIdx.x;
+    if (nw <= 256) {
+        const int per = (nw + 7) / 8, full = nw - 8 * (per - 1);
+        const int xcd = widx & 7, rnk = widx >> 3;
+        widx = (xcd < full) ? xcd * per + rnk : full * per + (xcd - full) * (per - 1) + rnk;
+    }
+    const WorkItem wi = work[widx];
     const InstDesc* I = insts + wi.inst;
     const IslandDesc* L = isls + wi.island;
     const int n = I->n, S = I->S, n_pad = I->n_pad, jb = I->jb, G = I->G;
