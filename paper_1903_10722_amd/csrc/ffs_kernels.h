@@ -262,9 +262,13 @@ __device__ __forceinline__ void pipe_step(uint32_t (&key)[MMAX], uint32_t& o_key
     const uint32_t in_p = from_prev_lane(o_p);
     if (!PRED || rel < n_act) {
         const bool have = !PRED || rel < un;
-        const uint32_t j = first ? (ap & 0xFFFFu) : (in_key & jmask);
-        const uint32_t r = first ? 0u : (in_key >> jb);
-        const uint32_t pj = first ? (ap >> 16) : in_p;
+        // stage 0 takes its job word (p << jb | job) from AP, the others the
+        // handed-on key (completion << jb | job) and processing time
+        const uint32_t x = first ? ap : in_key;
+        const uint32_t j = x & jmask;
+        const uint32_t hi = x >> jb;
+        const uint32_t r = first ? 0u : hi;
+        const uint32_t pj = first ? hi : in_p;
         const uint32_t o = key[0];
         const uint32_t f = o >> jb;
         const uint32_t st = f > r ? f : r;
@@ -284,8 +288,10 @@ __device__ __forceinline__ void pipe_step(uint32_t (&key)[MMAX], uint32_t& o_key
         o_key = o;
         o_p = pn_pre;
     }
+    // every lane holds real jobs while all stages dispatch, so only the
+    // predicated fill and drain steps clamp the index
     const uint32_t q = key[0] & jmask;
-    pn_pre = (uint32_t)prow_next[min(q, un - 1u)];
+    pn_pre = (uint32_t)prow_next[PRED ? min(q, un - 1u) : q];
 }
 
 // One group of S lanes decodes one permutation; lane k runs stage k.
@@ -312,7 +318,7 @@ __device__ __forceinline__ void pipe_step(uint32_t (&key)[MMAX], uint32_t& o_key
 // without per-lane predication; lanes of unused groups then compute values
 // nobody reads (their loads stay in bounds).
 //
-// AP[t] = (p[job][0] << 16) | job for the permutation's t-th job.  Returns
+// AP[t] = (p[job][0] << jb) | job for the permutation's t-th job.  Returns
 // the makespan on the lane of the last stage.
 template <int MMAX, typename PT>
 __device__ __forceinline__ uint32_t decode_pipelined(const uint32_t* AP, const PT* prow_next, const int* mach,
@@ -371,10 +377,10 @@ __device__ __forceinline__ uint32_t decode_pipelined(const uint32_t* AP, const P
     return cmax;
 }
 
-// AP[t] = (p[A[t]][0] << 16) | A[t], built by the group's lanes.
+// AP[t] = (p[A[t]][0] << jb) | A[t], built by the group's lanes.
 template <typename PT>
-__device__ __forceinline__ void build_ap(uint32_t* AP, const uint16_t* A, const PT* prow0, int n, int k, int S,
-                                         bool active)
+__device__ __forceinline__ void build_ap(uint32_t* AP, const uint16_t* A, const PT* prow0, int n, int jb, int k,
+                                         int S, bool active)
 {
     constexpr int U = 4;
     if (active)
@@ -390,7 +396,7 @@ __device__ __forceinline__ void build_ap(uint32_t* AP, const uint16_t* A, const 
 #pragma unroll
             for (int u = 0; u < U; ++u) {
                 const int t = t0 + u * S;
-                if (t < n) AP[t] = (pj[u] << 16) | j[u];
+                if (t < n) AP[t] = (pj[u] << jb) | j[u];
             }
         }
     wave_sync();
@@ -896,7 +902,7 @@ __global__ void __launch_bounds__(512) k_generation(const InstDesc* __restrict__
     }
 
     uint32_t* AP = reinterpret_cast<uint32_t*>(B);   // B..V: n_pad words
-    build_ap<PT>(AP, A, pT, n, k, S, active);
+    build_ap<PT>(AP, A, pT, n, jb, k, S, active);
     const uint32_t cm = decode_pipelined<MMAX, PT>(AP, prow_next, I->mach, k, S, n, jb, active);
     const int src = active ? (g * S + S - 1) : lane;
     const int cmg = __shfl((int)cm, src, 64);
@@ -993,7 +999,7 @@ __global__ void __launch_bounds__(512) k_evaluate(const InstDesc* __restrict__ I
     const int shift = g * S;
     const bool gbad = ((shift < 64 ? (bb >> shift) : 0ull) & gmask) != 0ull;
     uint32_t* AP = reinterpret_cast<uint32_t*>(A + n_pad);   // B..V: n_pad words
-    build_ap<PT>(AP, A, pT, n, k, S, active);
+    build_ap<PT>(AP, A, pT, n, jb, k, S, active);
     const uint32_t cm = decode_pipelined<MMAX, PT>(AP, pT + (size_t)(k + 1 < S ? k + 1 : S - 1) * pt_stride<PT>(n_pad), I->mach,
                                                    k, S, n, jb, active);
     if (active && k == S - 1) out[idx] = gbad ? -1 : (int)cm;
@@ -1042,7 +1048,7 @@ __global__ void __launch_bounds__(512) k_candidates(const InstDesc* __restrict__
     features_group<PT>(A, pT, I, k, active, meta, Xout + (size_t)qq * kFeat);
     if (Tout) {
         uint32_t* AP = reinterpret_cast<uint32_t*>(B);
-        build_ap<PT>(AP, A, pT, n, k, S, active);
+        build_ap<PT>(AP, A, pT, n, jb, k, S, active);
         const uint32_t cm = decode_pipelined<MMAX, PT>(AP, pT + (size_t)(k + 1 < S ? k + 1 : S - 1) * pt_stride<PT>(n_pad),
                                                        I->mach, k, S, n, jb, active);
         const int cmg = __shfl((int)cm, active ? (g * S + S - 1) : lane, 64);
