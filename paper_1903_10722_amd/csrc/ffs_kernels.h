@@ -419,6 +419,7 @@ __device__ __forceinline__ uint32_t wrap_sub(uint32_t x, uint32_t n)
 // genes once, so the whole crossover costs three LDS round trips plus the
 // group scan.
 constexpr int kOxReg = 24;
+constexpr int kOxMid = 64;   // rows with up to this many positions per lane keep P2 in registers
 
 __device__ __forceinline__ int group_exclusive_scan(int v, int k, int S)
 {
@@ -466,6 +467,50 @@ __device__ __forceinline__ void ox_group(uint16_t* A, const uint16_t* B, uint16_
 #pragma unroll
             for (int u = 0; u < kOxReg; ++u)
                 if (keep & (1u << u)) {
+                    A[dst] = (uint16_t)x2[u];
+                    dst = wrap_sub(dst + 1u, un);
+                }
+        }
+        wave_sync();
+        return;
+    }
+    if (C <= kOxMid) {
+        // P2's genes held in registers between the count and the write
+        constexpr int U = 8;
+        if (doit) {
+            for (int t0 = o0; t0 < o1; t0 += U) {
+                uint32_t x[U];
+#pragma unroll
+                for (int u = 0; u < U; ++u) x[u] = A[t0 + u < o1 ? t0 + u : 0];
+#pragma unroll
+                for (int u = 0; u < U; ++u)
+                    if (t0 + u < o1) V[x[u]] = (uint16_t)(t0 + u);
+            }
+        }
+        wave_sync();
+        uint32_t x2[kOxMid];
+        unsigned long long keep = 0ull;
+        int cnt = 0;
+        if (doit) {
+#pragma unroll
+            for (int u = 0; u < kOxMid; ++u) {
+                const uint32_t p = wrap_sub(ub + 1u + (uint32_t)(o0 + u), un);
+                x2[u] = B[(o0 + u < o1) ? p : 0u];
+            }
+#pragma unroll
+            for (int u = 0; u < kOxMid; ++u) {
+                const uint32_t iv = V[x2[u]];
+                const bool kp = (o0 + u < o1) && (iv < ua || iv > ub);
+                keep |= kp ? (1ull << u) : 0ull;
+                cnt += kp ? 1 : 0;
+            }
+        }
+        const int pre = group_exclusive_scan(cnt, k, S);
+        if (doit) {
+            uint32_t dst = wrap_sub(ub + 1u + (uint32_t)pre, un);
+#pragma unroll
+            for (int u = 0; u < kOxMid; ++u)
+                if (keep & (1ull << u)) {
                     A[dst] = (uint16_t)x2[u];
                     dst = wrap_sub(dst + 1u, un);
                 }
