@@ -181,7 +181,8 @@ def islands_experiment(runs: int, generations: int) -> dict:
     cellular torus, a single pseudo population, two islands of one kind, and
     the dual layout at migration gaps 10 ... 800, and the cellular parent
     selection variants (self + best neighbour, binary tournaments) on the
-    layouts with cellular islands.  `runs` GA seeds run as
+    layouts with cellular islands, and sixteen islands with ring-then-pairs
+    against the rule on every ring edge.  `runs` GA seeds run as
     instances of one batched context; best makespans are read at checkpoints."""
     import numpy as np
     import torch
@@ -190,13 +191,14 @@ def islands_experiment(runs: int, generations: int) -> dict:
     w0 = inputs.paper_setting("dual")
     p64, m64 = w0["p"].astype(np.int64), w0["m"].astype(np.int64)
     lb = max(int(p64.sum(axis=1).max()), max(int(-(-p64[:, k].sum() // m64[k])) for k in range(p64.shape[1])))
-    configs = [(v, 500, 0) for v in inputs.ISLAND_VARIANTS] + \
-              [("dual", i, 0) for i in (10, 20, 50, 100, 200, 300, 800)] + \
-              [(v, 500, sel) for sel in (1, 2) for v in ("dual", "cellular", "cellular2")]
+    configs = [(v, 500, 0, 0) for v in inputs.ISLAND_VARIANTS] + \
+              [("dual", i, 0, 0) for i in (10, 20, 50, 100, 200, 300, 800)] + \
+              [(v, 500, sel, 0) for sel in (1, 2) for v in ("dual", "cellular", "cellular2")] + \
+              [("ring16", i, 0, top) for top in (1, 2) for i in (50, 500)]
     checkpoints = [c for c in (50, 100, 200, 500, 1000, 2000) if c < generations] + [generations]
     rows = []
-    for variant, interval, sel in configs:
-        w = inputs.paper_setting(variant, interval=interval, sel=sel)
+    for variant, interval, sel, top in configs:
+        w = inputs.paper_setting(variant, interval=interval, sel=sel, topology=top)
         ctx = Context(device=0)
         for r in range(runs):
             ctx.add_instance(w["m"], w["p"], w["islands"], interval=interval, theta=w["theta"],
@@ -216,7 +218,7 @@ def islands_experiment(runs: int, generations: int) -> dict:
             curve.append({"generation": c, "best_mean": float(best.mean())})
         found = [ctx.best(i)["generation"] for i in range(runs)]
         ctx.close()
-        rows.append({"layout": variant, "selection": sel,
+        rows.append({"layout": variant, "selection": sel, "topology": w["topology"],
                      "islands": [f"cellular {x['rows']}x{x['cols']}" if x["kind"] == 0 else f"pseudo {x['size']}"
                                  for x in w["islands"]],
                      "interval": interval if len(w["islands"]) > 1 else None,

@@ -84,7 +84,11 @@ typedef struct {
  *               ceil(alpha * min(N_A, N_B)) best individuals of the fitter
  *               island overwrite as many worst individuals of the other.
  *   topology 1: first a ring (island order 0, H, 1, H+1, ...): every island's
- *               best overwrites its successor's worst; then topology 0.    */
+ *               best overwrites its successor's worst; then topology 0.
+ *   topology 2: the rule of topology 0 on every edge of that ring in turn,
+ *               (0, H), (H, 1), (1, H+1), ..., (2H-1, 0), each edge on the
+ *               state the previous edges left (two islands: the one edge
+ *               (0, 1)); an alternative reading for more than two islands. */
 typedef struct {
     int32_t migration_interval;
     int32_t topology;

@@ -551,12 +551,27 @@ static void adaptive_pair(or_ga_t *g, int a, int b)
 
 /* one migration epoch.  Islands are paired (i, i + H), H = n_islands / 2.
  * Topology 1 first runs a ring c0, p0, c1, p1, ... in which every island's
- * best (taken from a snapshot) overwrites its successor's worst.            */
+ * best (taken from a snapshot) overwrites its successor's worst.
+ * Topology 2 (an alternative reading of the multi-island case) applies the
+ * penetration rule of equations (1)-(2) to every edge of that ring in turn,
+ * (c0, p0), (p0, c1), ..., (p_{H-1}, c0), each on the state the previous
+ * edges left; two islands have the single edge (c0, p0).                   */
 void or_ga_migrate(void *h)
 {
     or_ga_t *g = (or_ga_t *)h;
     int H = g->n_islands / 2;
     if (H == 0) return;
+    if (g->topology == 2) {
+        int L = 2 * H;
+        int edges = (L == 2) ? 1 : L;
+        for (int t = 0; t < edges; ++t) {
+            int x = (t % 2 == 0) ? t / 2 : H + t / 2;
+            int u = (t + 1) % L;
+            int y = (u % 2 == 0) ? u / 2 : H + u / 2;
+            adaptive_pair(g, x, y);
+        }
+        return;
+    }
     if (g->topology == 1) {
         int L = 2 * H;
         int *ring = (int *)malloc(sizeof(int) * (size_t)L);

@@ -41,6 +41,8 @@ struct HostInstance {
     int msum, n_cells;
     std::vector<long long> Pk;
     size_t off_pT, off_best_perm, off_best_rec, off_counters;
+    int edge0 = 0, n_edges = 0;   // topology 2: this instance's ring edges in the pair list
+    int isl_base = 0;
 };
 
 using GenKernel = void (*)(const InstDesc*, const IslandDesc*, const WorkItem*, Control*, int, int);
@@ -117,7 +119,7 @@ struct ffs_ctx {
     // layout
     size_t off_ctl = 0, off_insts = 0, off_isls = 0, off_work = 0, off_pairs = 0, off_counts = 0, total = 0;
     int max_work = 0;
-    int n_isl = 0, n_work = 0, n_pairs = 0, max_size = 0;
+    int n_isl = 0, n_work = 0, n_pairs = 0, max_size = 0, max_edges = 0;
     int mm = 2, ptb = 1;
     size_t lds_gen = 0, lds_sort = 0;
     bool any_ring = false;
@@ -207,8 +209,25 @@ void layout(ffs_ctx* c)
             }
         }
         const int H = (int)I.isl.size() / 2;
-        for (int i = 0; i < H; ++i) c->pairs.push_back(PairDesc{isl_base + i, isl_base + i + H, (int)ii, 0});
+        if (I.cfg.topology != 2)
+            for (int i = 0; i < H; ++i) c->pairs.push_back(PairDesc{isl_base + i, isl_base + i + H, (int)ii, 0});
+        I.isl_base = isl_base;
         isl_base += (int)I.isl.size();
+    }
+    c->n_pairs = (int)c->pairs.size();
+    // topology 2: the ring c0, p0, c1, p1, ... as a list of edges after the pairs
+    c->max_edges = 0;
+    for (size_t ii = 0; ii < c->inst.size(); ++ii) {
+        auto& I = c->inst[ii];
+        I.edge0 = (int)c->pairs.size();
+        I.n_edges = 0;
+        const int H = (int)I.isl.size() / 2;
+        if (I.cfg.topology != 2 || H == 0) continue;
+        const int L = 2 * H, edges = (L == 2) ? 1 : L;
+        auto ring = [&](int q) { return I.isl_base + ((q % 2 == 0) ? q / 2 : H + q / 2); };
+        for (int e = 0; e < edges; ++e) c->pairs.push_back(PairDesc{ring(e), ring((e + 1) % L), (int)ii, 0});
+        I.n_edges = edges;
+        c->max_edges = std::max(c->max_edges, edges);
     }
     std::stable_sort(c->work.begin(), c->work.end(), [&](const WorkItem& a, const WorkItem& b) {
         const auto& A = c->inst[a.inst];
@@ -216,7 +235,6 @@ void layout(ffs_ctx* c)
         return (long long)A.n * A.S * a.count > (long long)B.n * B.S * b.count;
     });
     c->n_work = (int)c->work.size();
-    c->n_pairs = (int)c->pairs.size();
 
     c->off_ctl = take(sizeof(Control));
     c->off_insts = take(sizeof(InstDesc) * c->inst.size());
@@ -229,7 +247,7 @@ void layout(ffs_ctx* c)
     c->off_work = take(sizeof(WorkItem) * std::max<size_t>(1, max_work));
     c->max_work = (int)max_work;
     c->off_counts = take(sizeof(int) * (max_work + 1));
-    c->off_pairs = take(sizeof(PairDesc) * (size_t)std::max(1, c->n_pairs));
+    c->off_pairs = take(sizeof(PairDesc) * std::max<size_t>(1, c->pairs.size()));
     c->lds_gen = 0;
     for (auto& I : c->inst) {
         I.off_pT = take((size_t)I.S * I.n_pad * c->ptb);
@@ -373,11 +391,24 @@ int launch_migration(ffs_ctx* c, int force_inst)
         hipLaunchKernelGGL(k_mig_minmax, dim3(c->n_isl), dim3(256), 0, c->stream, di, dl, ctl, force_inst);
         hipLaunchKernelGGL(k_mig_ring, dim3(c->n_isl), dim3(256), 0, c->stream, di, dl, ctl, force_inst);
     }
-    hipLaunchKernelGGL(k_mig_sort, dim3(c->n_isl), dim3(kSortThreads), c->lds_sort, c->stream, di, dl, ctl, force_inst);
-    if (c->n_pairs > 0) {
-        const int chunks = (c->max_size + kMigRows - 1) / kMigRows;
+    const int chunks = (c->max_size + kMigRows - 1) / kMigRows;
+    hipLaunchKernelGGL(k_mig_sort, dim3(c->n_isl), dim3(kSortThreads), c->lds_sort, c->stream, di, dl, ctl, force_inst,
+                       -1);
+    if (c->n_pairs > 0)
         hipLaunchKernelGGL(k_mig_adapt, dim3(c->n_pairs, chunks), dim3(256), 0, c->stream, di, dl, dp, ctl,
                            force_inst);
+    // topology 2: the edges of each ring in turn, each on the state the
+    // previous edge left (re-sorted)
+    for (size_t ii = 0; ii < c->inst.size(); ++ii) {
+        const auto& I = c->inst[ii];
+        if (I.n_edges == 0 || (force_inst >= 0 && force_inst != (int)ii)) continue;
+        for (int e = 0; e < I.n_edges; ++e) {
+            if (e > 0)
+                hipLaunchKernelGGL(k_mig_sort, dim3(c->n_isl), dim3(kSortThreads), c->lds_sort, c->stream, di, dl, ctl,
+                                   force_inst, (int)ii);
+            hipLaunchKernelGGL(k_mig_adapt, dim3(1, chunks), dim3(256), 0, c->stream, di, dl, dp + I.edge0 + e, ctl,
+                               force_inst);
+        }
     }
     HIP_TRY(c, hipGetLastError());
     return FFS_OK;
@@ -622,7 +653,7 @@ int ffs_create_instance(ffs_ctx* c, int32_t n, int32_t S, const int32_t* machine
     if (n_islands < 1) return fail(c, FFS_EINVAL, "need at least one island");
     if (n_islands > 1 && (n_islands % 2) != 0) return fail(c, FFS_EINVAL, "island count must be even (pairs)");
     if (cfg->migration_interval < 0) return fail(c, FFS_EINVAL, "migration_interval must be >= 0");
-    if (cfg->topology != 0 && cfg->topology != 1) return fail(c, FFS_EINVAL, "topology must be 0 or 1");
+    if (cfg->topology < 0 || cfg->topology > 2) return fail(c, FFS_EINVAL, "topology must be 0, 1 or 2");
     if (!(cfg->theta >= 0.0 && cfg->theta <= 1.0)) return fail(c, FFS_EINVAL, "theta must be in [0, 1]");
     HostInstance I;
     I.n = n;

@@ -1240,11 +1240,12 @@ __host__ __device__ inline size_t sort_lds_bytes(int R)
 
 __global__ void __launch_bounds__(kSortThreads) k_mig_sort(const InstDesc* __restrict__ insts,
                                                            const IslandDesc* __restrict__ isls,
-                                                           const Control* ctl, int force_inst)
+                                                           const Control* ctl, int force_inst, int only_inst)
 {
     const IslandDesc* L = isls + blockIdx.x;
     const InstDesc* I = insts + L->inst;
     const int gen = completed_gen(ctl);
+    if (only_inst >= 0 && L->inst != only_inst) return;
     if (!migrating_now(I, L->inst, gen, force_inst)) return;
     const int N = L->size;
     int R = 1;

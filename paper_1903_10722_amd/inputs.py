@@ -105,6 +105,8 @@ def _layout(variant: str, side: int, cell_rates, pair_rates) -> list:
         return [c(side, side), c(side, side)]
     if variant == "pseudo2":
         return [pseudo(half, *pair_rates), pseudo(half, *pair_rates)]
+    if variant == "ring16":
+        return [c(side, side) for _ in range(8)] + [pseudo(half, *pair_rates) for _ in range(8)]
     raise KeyError(variant)
 
 
@@ -131,14 +133,17 @@ PAPER_CELL_RATES = (1.0, 0.05)
 PAPER_PAIR_RATES = (0.75, 0.0)
 
 
-def paper_setting(variant: str = "dual", seed: int = 1, interval: int = 500, sel: int = 0) -> dict:
+def paper_setting(variant: str = "dual", seed: int = 1, interval: int = 500, sel: int = 0,
+                  topology: int = 0) -> dict:
     """Section 5's problem and population sizes with the layouts of
-    island_variant at 512 individuals (dual = 16x16 cellular + 256 pseudo);
-    `sel` is the cellular islands' parent selection variant."""
+    island_variant at 512 individuals (dual = 16x16 cellular + 256 pseudo),
+    or ring16: eight such pairs (4096 individuals) migrating with `topology`
+    (1 ring then pairs, 2 the rule on every ring edge); `sel` is the cellular
+    islands' parent selection variant."""
     m, p = make_instance(300, 4, 2, 2, p_lo=1, p_hi=5, seed=seed, machines=[2, 2, 2, 2])
     isl = _layout(variant, 16, PAPER_CELL_RATES + (sel,), PAPER_PAIR_RATES)
     return dict(name=f"paper:{variant}", m=m, p=p, islands=isl, generations=2000, interval=interval,
-                theta=1.0, topology=0)
+                theta=1.0, topology=topology if variant == "ring16" else 0)
 
 
 def batched_workloads(count: int = 256, batch_seed: int = 7, scale: int = 1, n_choices=None) -> list[dict]:

@@ -124,3 +124,32 @@ def test_selection_variants_trajectory(variant, sel):
     for i, ga in enumerate(gas):
         assert ctx.best(i)["makespan"] == ga.best()["makespan"]
     ctx.close()
+
+
+@pytest.mark.parametrize("n_pairs", [1, 2, 8])
+def test_ring_edge_topology(n_pairs):
+    """Topology 2 (the penetration rule on every ring edge in turn) with 2, 4
+    and 16 islands, against the oracle; with a topology-1 instance of the
+    same shape in the same context, 40 generations and one forced epoch."""
+    ensure_built()
+    m, p = inputs.make_instance(60, 4, 1, 4, seed=9)
+    isl = [inputs.cellular(4, 4, 0.9, 0.1) for _ in range(n_pairs)] + \
+          [inputs.pseudo(16, 0.75, 0.05) for _ in range(n_pairs)]
+    ws = [dict(m=m, p=p, islands=isl, interval=5, topology=2, seed=31),
+          dict(m=m, p=p, islands=isl, interval=5, topology=1, seed=32)]
+    n_isl = len(isl)
+    say(f"[islands] ring-edge topology, {n_isl} islands")
+    ctx = make_ctx(ws)
+    gas = [oracle_ga(v, inst=i) for i, v in enumerate(ws)]
+    for g in (5, 15, 20):
+        ctx.evolve(g)
+        for i, ga in enumerate(gas):
+            ga.evolve(g)
+            assert_same_state(ctx, ga, i, n_isl, f"topology {ws[i]['topology']} generation {ctx.generation}")
+    ctx.migrate(0)
+    gas[0].migrate()
+    for i, ga in enumerate(gas):
+        assert_same_state(ctx, ga, i, n_isl, f"topology {ws[i]['topology']} after forced epoch")
+        assert ctx.migration_counters(i) == ga.counters()
+        assert ctx.best(i)["makespan"] == ga.best()["makespan"]
+    ctx.close()
