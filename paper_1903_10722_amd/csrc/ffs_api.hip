@@ -12,6 +12,7 @@
 #include <cstdarg>
 #include <cstdio>
 #include <cstring>
+#include <functional>
 #include <string>
 #include <vector>
 
@@ -43,9 +44,11 @@ struct HostInstance {
     size_t off_pT, off_best_perm, off_best_rec, off_counters;
     int edge0 = 0, n_edges = 0;   // topology 2: this instance's ring edges in the pair list
     int isl_base = 0;
+    size_t lds = 0;               // LDS bytes of one generation workgroup
+    int lds_bucket = 0, cls = 0;  // its LDS class
 };
 
-using GenKernel = void (*)(const InstDesc*, const IslandDesc*, const WorkItem*, Control*, int, int);
+using GenKernel = void (*)(const InstDesc*, const IslandDesc*, const WorkItem*, Control*, int, int, int, int);
 using EvalKernel = void (*)(const InstDesc*, const int*, int, int*, Control*);
 
 template <int M, typename PT>
@@ -119,7 +122,9 @@ struct ffs_ctx {
     // layout
     size_t off_ctl = 0, off_insts = 0, off_isls = 0, off_work = 0, off_pairs = 0, off_counts = 0, total = 0;
     int max_work = 0;
-    int n_isl = 0, n_work = 0, n_pairs = 0, max_size = 0, max_edges = 0;
+    int n_isl = 0, n_work = 0, n_pairs = 0, max_size = 0, max_edges = 0, n_cls = 1;
+    std::vector<int> cls_w0;         // work range of LDS class k: [cls_w0[k], cls_w0[k+1])
+    std::vector<size_t> cls_lds;     // LDS bytes of class k's launch
     int mm = 2, ptb = 1;
     size_t lds_gen = 0, lds_sort = 0;
     bool any_ring = false;
@@ -190,6 +195,21 @@ void layout(ffs_ctx* c)
     }
     c->mm = round_mmax(mmax);
     c->ptb = (maxP <= 255) ? 1 : 2;
+    // LDS classes: instances whose workgroups need LDS within the same
+    // power-of-two bucket share a launch sized for that bucket, so small
+    // instances are not held to the occupancy of the largest one
+    std::vector<int> buckets;
+    for (auto& I : c->inst) {
+        I.lds = align16((size_t)I.S * ((size_t)I.n_pad * c->ptb + 4)) + (size_t)c->wpb * wave_lds_bytes(I.G, I.n_pad);
+        int b = 0;
+        while (((size_t)8192 << b) < I.lds) ++b;
+        I.lds_bucket = b;
+        if (std::find(buckets.begin(), buckets.end(), b) == buckets.end()) buckets.push_back(b);
+    }
+    std::sort(buckets.begin(), buckets.end(), std::greater<int>());
+    for (auto& I : c->inst)
+        I.cls = (int)(std::find(buckets.begin(), buckets.end(), I.lds_bucket) - buckets.begin());
+    c->n_cls = (int)buckets.size();
     // work items: per island, chunks of (waves per block) x G chromosomes,
     // ordered by cost (n * S * count), largest first
     c->work.clear();
@@ -232,9 +252,17 @@ void layout(ffs_ctx* c)
     std::stable_sort(c->work.begin(), c->work.end(), [&](const WorkItem& a, const WorkItem& b) {
         const auto& A = c->inst[a.inst];
         const auto& B = c->inst[b.inst];
+        if (A.cls != B.cls) return A.cls < B.cls;
         return (long long)A.n * A.S * a.count > (long long)B.n * B.S * b.count;
     });
     c->n_work = (int)c->work.size();
+    // one launch per class: its work range, LDS bytes and launch-count slots
+    // (the first class's launch also carries the best-ever workgroup)
+    c->cls_w0.assign(c->n_cls + 1, 0);
+    c->cls_lds.assign(c->n_cls, 0);
+    for (auto& w : c->work) c->cls_w0[c->inst[w.inst].cls + 1] += 1;
+    for (int k = 0; k < c->n_cls; ++k) c->cls_w0[k + 1] += c->cls_w0[k];
+    for (auto& I : c->inst) c->cls_lds[I.cls] = std::max(c->cls_lds[I.cls], I.lds);
 
     c->off_ctl = take(sizeof(Control));
     c->off_insts = take(sizeof(InstDesc) * c->inst.size());
@@ -246,7 +274,7 @@ void layout(ffs_ctx* c)
         for (auto& L : I.isl) max_work += (size_t)((L.size + I.G - 1) / I.G);
     c->off_work = take(sizeof(WorkItem) * std::max<size_t>(1, max_work));
     c->max_work = (int)max_work;
-    c->off_counts = take(sizeof(int) * (max_work + 1));
+    c->off_counts = take(sizeof(int) * (max_work + 16));
     c->off_pairs = take(sizeof(PairDesc) * std::max<size_t>(1, c->pairs.size()));
     c->lds_gen = 0;
     for (auto& I : c->inst) {
@@ -263,9 +291,7 @@ void layout(ffs_ctx* c)
             L.off_minmax = take(16);
             L.off_sorted = take((size_t)L.size * sizeof(int));
         }
-        const size_t lds = align16((size_t)I.S * ((size_t)I.n_pad * c->ptb + 4)) +
-                           (size_t)c->wpb * wave_lds_bytes(I.G, I.n_pad);
-        c->lds_gen = std::max(c->lds_gen, lds);
+        c->lds_gen = std::max(c->lds_gen, I.lds);
     }
     int R = 1;
     while (R * kSortThreads < c->max_size) R <<= 1;
@@ -341,7 +367,10 @@ int launch_generation(ffs_ctx* c, int mode)
     const WorkItem* dw = reinterpret_cast<const WorkItem*>(c->ws + c->off_work);
     Control* ctl = reinterpret_cast<Control*>(c->ws + c->off_ctl);
     int n_inst = (int)c->inst.size();
-    void* args[] = {(void*)&di, (void*)&dl, (void*)&dw, (void*)&ctl, (void*)&n_inst, (void*)&mode};
+    int cnt_off = 0, extra = 0;
+    const WorkItem* dwk = dw;
+    void* args[] = {(void*)&di, (void*)&dl, (void*)&dwk, (void*)&ctl, (void*)&n_inst, (void*)&mode, (void*)&cnt_off,
+                    (void*)&extra};
     hipEvent_t e0 = nullptr, e1 = nullptr;
     if (c->timing && mode == 0) {
         while (c->ev_pool.size() < 2) {
@@ -355,10 +384,18 @@ int launch_generation(ffs_ctx* c, int mode)
         c->ev_pool.pop_back();
         HIP_TRY(c, hipEventRecord(e0, c->stream));
     }
-    // a generation launch has one workgroup more than work items: it folds
-    // the previous generation into the best-ever records
-    const unsigned grid = (unsigned)c->n_work + (mode == 0 ? 1u : 0u);
-    HIP_TRY(c, hipLaunchKernel(c->kgen, dim3(grid), dim3(64 * c->wpb), args, c->lds_gen, c->stream));
+    // one launch per LDS class; the first has one workgroup more than work
+    // items, which folds the previous generation into the best-ever records
+    cnt_off = 0;
+    for (int k = 0; k < c->n_cls; ++k) {
+        const int nw = c->cls_w0[k + 1] - c->cls_w0[k];
+        extra = (mode == 0 && k == 0) ? 1 : 0;
+        if (nw + extra == 0) continue;
+        dwk = dw + c->cls_w0[k];
+        HIP_TRY(c, hipLaunchKernel(c->kgen, dim3((unsigned)(nw + extra)), dim3(64 * c->wpb), args, c->cls_lds[k],
+                                   c->stream));
+        cnt_off += nw + extra;
+    }
     if (e0) {
         HIP_TRY(c, hipEventRecord(e1, c->stream));
         c->ev_used.emplace_back(e0, e1);
@@ -450,7 +487,7 @@ int apply_tile(ffs_ctx* c)
     if (c->bound) {
         // new launch width: count launches afresh from the current generation
         HIP_TRY(c, hipStreamSynchronize(c->stream));
-        std::vector<int> zeros(c->max_work + 1, 0);
+        std::vector<int> zeros(c->max_work + 16, 0);
         HIP_TRY(c, hipMemcpy(c->ws + c->off_counts, zeros.data(), zeros.size() * sizeof(int), hipMemcpyHostToDevice));
         const int base = c->gen;
         HIP_TRY(c, hipMemcpy(c->ws + c->off_ctl + offsetof(Control, base), &base, sizeof base, hipMemcpyHostToDevice));
@@ -876,7 +913,7 @@ int ffs_bind_workspace(ffs_ctx* c, void* dptr, size_t bytes)
     ctl.counts = reinterpret_cast<int*>(c->ws + c->off_counts);
     ctl.best_gen = -1;
     {
-        std::vector<int> zeros(c->max_work + 1, 0);
+        std::vector<int> zeros(c->max_work + 16, 0);
         HIP_TRY(c, hipMemcpy(c->ws + c->off_counts, zeros.data(), zeros.size() * sizeof(int), hipMemcpyHostToDevice));
     }
     HIP_TRY(c, hipMemcpy(c->ws + c->off_ctl, &ctl, sizeof ctl, hipMemcpyHostToDevice));

@@ -803,14 +803,14 @@ template <int MMAX, typename PT>
 __global__ void __launch_bounds__(512) k_generation(const InstDesc* __restrict__ insts,
                                                     const IslandDesc* __restrict__ isls,
                                                     const WorkItem* __restrict__ work, Control* ctl, int n_inst,
-                                                    int mode)
+                                                    int mode, int cnt_off, int has_extra)
 {
     // generation number from this workgroup's launch count (generation 0 has none)
     __shared__ int s_gen;
     if (threadIdx.x == 0) {
         int gg = 0;
         if (mode == 0) {
-            int* cnt = ctl->counts + blockIdx.x;
+            int* cnt = ctl->counts + cnt_off + blockIdx.x;
             const int t = *cnt;
             *cnt = t + 1;
             gg = ctl->base + 1 + t;
@@ -819,7 +819,7 @@ __global__ void __launch_bounds__(512) k_generation(const InstDesc* __restrict__
     }
     // the workgroup after the work items folds the previous generation into
     // the best-ever records while the others run this one
-    if (mode == 0 && blockIdx.x == gridDim.x - 1) {
+    if (has_extra && blockIdx.x == gridDim.x - 1) {
         __syncthreads();
         const int prev = s_gen - 1;
         if (ctl->best_gen < prev) fold_best(insts, isls, n_inst, prev, ctl, reinterpret_cast<int*>(ffs_smem));
@@ -829,7 +829,7 @@ __global__ void __launch_bounds__(512) k_generation(const InstDesc* __restrict__
     // places workgroup b on XCD b % 8) a contiguous run of work items, so
     // that neighbouring cells share an L2; larger grids keep the
     // largest-first order.
-    const int nw = (mode == 0) ? (int)gridDim.x - 1 : (int)gridDim.x;
+    const int nw = (int)gridDim.x - has_extra;
     int widx = (int)blockIdx.x;
     if (nw <= 256) {
         const int per = (nw + 7) / 8, full = nw - 8 * (per - 1);
