@@ -196,13 +196,14 @@ void layout(ffs_ctx* c)
     c->mm = round_mmax(mmax);
     c->ptb = (maxP <= 255) ? 1 : 2;
     // LDS classes: instances whose workgroups need LDS within the same
-    // power-of-two bucket share a launch sized for that bucket, so small
-    // instances are not held to the occupancy of the largest one
+    // half-octave bucket (8 KB * sqrt(2)^b) share a launch sized for the
+    // class, so small instances are not held to the occupancy of the
+    // largest one
     std::vector<int> buckets;
     for (auto& I : c->inst) {
         I.lds = align16((size_t)I.S * ((size_t)I.n_pad * c->ptb + 4)) + (size_t)c->wpb * wave_lds_bytes(I.G, I.n_pad);
         int b = 0;
-        while (((size_t)8192 << b) < I.lds) ++b;
+        while ((size_t)(8192.0 * std::pow(1.41421356, (double)b)) < I.lds) ++b;
         I.lds_bucket = b;
         if (std::find(buckets.begin(), buckets.end(), b) == buckets.end()) buckets.push_back(b);
     }
