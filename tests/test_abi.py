@@ -72,3 +72,14 @@ def test_island_variants_hold_8192_individuals():
         w = inputs.island_variant(v)
         assert sum(x["size"] for x in w["islands"]) == 8192
         assert (w["p"] == base["p"]).all() and (w["m"] == base["m"]).all()
+
+
+def test_bench_refuses_more_than_one_gpu():
+    """bench.py measures one GPU; asking for more exits with a message."""
+    import subprocess
+    import sys
+    root = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+    r = subprocess.run([sys.executable, os.path.join(root, "bench.py"), "--gpus", "2"], capture_output=True, text=True,
+                       timeout=120)
+    assert r.returncode == 2
+    assert "one GPU" in r.stderr

@@ -534,3 +534,42 @@ def test_selection_binary_tournament_ties_go_to_order():
     mk = np.full(9, 40, dtype=np.int32)
     # x = 1 * 5 + 3: positions N (1) and S (3) -> N (slot 1); x = 4*5 + 0: W and self -> self
     assert oracle.cell_parents(3, 3, mk, 4, sel=2, d6=_d_for(8), d7=_d_for(20)) == (1, 4)
+
+
+def test_ring_edge_topology_is_the_pair_rule_edge_by_edge():
+    """Topology 2 on four islands equals the two-island rule (topology 0, itself
+    pinned by the worked example and the rational equations) applied to the
+    ring edges (c0, p0), (p0, c1), (c1, p1), (p1, c0) in turn, each pair on the
+    state the previous edges left; with two islands it is the one pair."""
+    m, p = inputs.make_instance(12, 3, 1, 3, seed=21)
+    isl = [inputs.cellular(3, 3, 0.9, 0.1), inputs.cellular(3, 4, 0.9, 0.1),
+           inputs.pseudo(10, 0.75, 0.05), inputs.pseudo(8, 0.75, 0.05)]
+    src = oracle.GA(m, p, isl, interval=0, seed=22)
+    src.evolve(3)
+    state = [src.population(i) for i in range(4)]
+    ga = oracle.GA(m, p, isl, interval=0, topology=2, seed=22)
+    for i in range(4):
+        ga.set_population(i, *state[i])
+    ga.migrate()
+    work = [(g.copy(), mk.copy()) for g, mk in state]
+    ring = [0, 2, 1, 3]                       # c0, p0, c1, p1
+    moved = 0
+    for t in range(4):
+        x, y = ring[t], ring[(t + 1) % 4]
+        pair = oracle.GA(m, p, [isl[x], isl[y]], interval=0, topology=0, seed=22)
+        pair.set_population(0, *work[x])
+        pair.set_population(1, *work[y])
+        pair.migrate()
+        work[x], work[y] = pair.population(0), pair.population(1)
+        moved += pair.counters()[0]
+    assert moved > 0
+    for i in range(4):
+        g1, mk1 = ga.population(i)
+        assert (g1 == work[i][0]).all() and (mk1 == work[i][1]).all()
+    assert ga.counters()[0] == moved
+    two = oracle.GA(m, p, isl[:1] + isl[2:3], interval=0, topology=2, seed=23)
+    zero = oracle.GA(m, p, isl[:1] + isl[2:3], interval=0, topology=0, seed=23)
+    two.migrate()
+    zero.migrate()
+    for i in range(2):
+        assert (two.population(i)[0] == zero.population(i)[0]).all()
