@@ -75,6 +75,33 @@ def test_medium_full_size_generations():
     ctx.close()
 
 
+def test_surrogate_size_full_generations():
+    """The plain GA on the longest instance (n=1000, S=20, m in [2,6]) at
+    full size (64x64 + 4096): generation 0 whole, then the GPU state after
+    19 generations loaded into the oracle and generations 20 (with its
+    migration epoch) and 21 compared exactly.  At n=1000 the crossover chunk
+    per lane exceeds the register path, so this covers the longer paths."""
+    ensure_built()
+    w = inputs.workload("surrogate", seed=2)
+    say("[evolve] n=1000 S=20 full size")
+    ctx = make_ctx([w])
+    ga = oracle_ga(w)
+    assert_same_state(ctx, ga, 0, 2, "generation 0")
+    ctx.evolve(19)
+    for isl in range(2):
+        genes, mk = ctx.population(0, isl)
+        ga.set_population(isl, genes, mk)
+    ga.set_generation(19)
+    for g in (20, 21):
+        ctx.evolve(1)
+        ga.evolve(1)
+        assert_same_state(ctx, ga, 0, 2, f"generation {g}")
+    # the best-so-far record holds at most the current populations' minimum
+    cur = min(int(ga.population(i)[1].min()) for i in range(2))
+    assert ctx.best(0)["makespan"] <= cur
+    ctx.close()
+
+
 def test_sixteen_islands_ring_then_adaptive():
     """Large instance (n=500, S=10, m in [3,5]) on 16 islands (8 cellular
     8x8, 8 pseudo 64), ring-then-adaptive migration every 20, 40 generations,
