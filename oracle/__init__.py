@@ -13,6 +13,9 @@ Functions and the passage of the paper each follows:
   migration_policy Section 4.3, equations (1) and (2)
   GA               Sections 4.1-4.3 (one whole island-GA trajectory)
   philox           Salmon et al. SC'11 (the counter-based generator)
+  tardiness        the paper-faithful variant (``ffs_tt_oracle.c``): Section 3's
+                   objective with release and due dates on unrelated machines,
+                   Section 4.1's machine-assignment genotype, Table 1's data
 """
 from __future__ import annotations
 
@@ -24,6 +27,7 @@ import numpy as np
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
 _SRC = os.path.join(_HERE, "ffs_oracle.c")
+_SRC_TT = os.path.join(_HERE, "ffs_tt_oracle.c")
 _BUILD = os.path.join(_HERE, "_build")
 _LIB = os.path.join(_BUILD, "liboracle.so")
 
@@ -40,7 +44,7 @@ def build() -> str:
     os.makedirs(_BUILD, exist_ok=True)
     tmp = _LIB + ".tmp"
     subprocess.check_call(["gcc", "-O2", "-std=c11", "-Wall", "-Wextra", "-shared", "-fPIC",
-                           _SRC, "-o", tmp])
+                           _SRC, _SRC_TT, "-o", tmp])
     os.replace(tmp, _LIB)
     return _LIB
 
