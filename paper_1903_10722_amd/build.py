@@ -1,4 +1,4 @@
-"""Build of the gfx950 shared library behind include/ffs.h (hipcc, in-tree)."""
+"""Build of the gfx950 shared library behind include/ffs.h and include/ffs_tt.h (hipcc, in-tree)."""
 from __future__ import annotations
 
 import os
@@ -18,12 +18,12 @@ HIPCC_FLAGS = [
 
 
 def build_library(verbose: bool = False) -> str:
-    """Compile csrc/ffs_api.hip (+ headers) into _build/libffs.so; always recompiles."""
+    """Compile csrc/ffs_api.hip and csrc/ffs_tt.hip (+ headers) into _build/libffs.so; always recompiles."""
     os.makedirs(BUILD, exist_ok=True)
     hipcc = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
     tmp = LIB + ".tmp"
     cmd = [hipcc, *HIPCC_FLAGS, "-I", os.path.join(ROOT, "include"), "-I", CSRC,
-           os.path.join(CSRC, "ffs_api.hip"), "-o", tmp]
+           os.path.join(CSRC, "ffs_api.hip"), os.path.join(CSRC, "ffs_tt.hip"), "-o", tmp]
     res = subprocess.run(cmd, capture_output=True, text=True)
     if res.returncode != 0:
         raise RuntimeError("hipcc failed:\n" + res.stderr[-8000:])

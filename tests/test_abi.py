@@ -1,5 +1,6 @@
 """The C-ABI library builds, loads and exports every entry point that
-include/ffs.h declares (no device calls: runs without a GPU)."""
+include/ffs.h and include/ffs_tt.h declare (no device calls: runs without a
+GPU)."""
 import ctypes
 import os
 import re
@@ -14,9 +15,12 @@ ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 
 
 def _declared():
-    src = open(os.path.join(ROOT, "include", "ffs.h")).read()
-    src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
-    return sorted(set(re.findall(r"\b(ffs_[a-z_]+)\s*\(", src)))
+    names = set()
+    for h in ("ffs.h", "ffs_tt.h"):
+        src = open(os.path.join(ROOT, "include", h)).read()
+        src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
+        names |= set(re.findall(r"\b(ffs_[a-z_]+)\s*\(", src))
+    return sorted(names)
 
 
 @pytest.fixture(scope="module")
@@ -37,7 +41,8 @@ def test_library_exports_every_declared_symbol(lib_path):
     exported = set(re.findall(r"\bT (ffs_[a-z_]+)\b", out))
     missing = [n for n in _declared() if n not in exported]
     assert not missing, missing
-    assert sorted(binding.EXPORTS) == sorted(_declared())
+    from paper_1903_10722_amd import tardiness
+    assert sorted(binding.EXPORTS + tardiness.TT_EXPORTS) == sorted(_declared())
 
 
 def test_library_loads_and_reports_errors_without_device(lib_path):

@@ -1,0 +1,130 @@
+"""GPU parity of the paper-faithful variant (include/ffs_tt.h) against its
+oracle: decodes of caller-supplied assignments and whole GA trajectories,
+bit-exact (int64 objectives in hundredths, machine indices)."""
+import numpy as np
+import pytest
+
+from gpu_util import ensure_built, say
+from oracle import tardiness as ot
+from paper_1903_10722_amd import inputs
+
+pytestmark = pytest.mark.gpu
+
+
+def _ctx(inst, islands, interval, runs=1, seed=101):
+    from paper_1903_10722_amd.tardiness import TtContext
+    return TtContext(inst, islands, interval=interval, theta=1.0, seed=seed, runs=runs)
+
+
+def _random_genes(inst, count, seed):
+    rng = np.random.default_rng(seed)
+    M = np.asarray(inst["M"])
+    S = len(M)
+    J = inst["P"].shape[0]
+    return (rng.random((count, J * S)) * np.tile(M, J)).astype(np.int32)
+
+
+@pytest.mark.parametrize("shape", [(300, 4, [2, 2, 2, 2]), (37, 3, [1, 3, 4]), (1, 2, [2, 1]), (64, 2, [4, 2]),
+                                   (65, 5, [2, 3, 1, 4, 2]), (1024, 2, [2, 2]), (130, 7, [3, 1, 2, 4, 1, 2, 3])])
+def test_decode_matches_oracle(shape):
+    ensure_built()
+    J, S, M = shape
+    inst = inputs.tardiness_instance(J, S, M, seed=J + S)
+    say(f"[tt] decode J={J} S={S} M={M}")
+    ctx = _ctx(inst, [inputs.pseudo(2, 0.75, 0.0)], interval=0)
+    genes = _random_genes(inst, 96, seed=J)
+    got = ctx.evaluate(genes).cpu().numpy()
+    want = np.array([ot.decode(inst, g)[0] for g in genes], dtype=np.int64)
+    assert np.array_equal(got, want), np.nonzero(got != want)[0][:10]
+    ctx.close()
+
+
+def test_decode_rejects_out_of_range_genes():
+    ensure_built()
+    inst = inputs.tardiness_instance(20, 3, [2, 3, 1], seed=3)
+    ctx = _ctx(inst, [inputs.pseudo(2, 0.75, 0.0)], interval=0)
+    genes = _random_genes(inst, 4, seed=1)
+    genes[1, 5] = 3          # stage 2 has 3 machines: 3 is out of range
+    genes[3, 2] = 1          # stage 3 has 1 machine
+    got = ctx.evaluate(genes).cpu().numpy()
+    assert got[1] == -1 and got[3] == -1
+    assert got[0] == ot.decode(inst, genes[0])[0] and got[2] == ot.decode(inst, genes[2])[0]
+    ctx.close()
+
+
+def _same(ctx, ga, run, n_isl, what):
+    for i in range(n_isl):
+        g1, o1 = ctx.population(run, i)
+        g2, o2 = ga.population(i)
+        if not np.array_equal(o1, o2):
+            bad = np.nonzero(o1 != o2)[0]
+            raise AssertionError(f"{what} island {i}: objectives differ at {bad[:8]} gpu={o1[bad[:4]]} oracle={o2[bad[:4]]}")
+        assert np.array_equal(g1, g2), f"{what} island {i}: genes differ"
+
+
+@pytest.mark.parametrize("runs", [1, 3])
+def test_small_trajectory_with_migration(runs):
+    ensure_built()
+    inst = inputs.tardiness_instance(20, 3, [2, 3, 1], seed=5)
+    isl = [inputs.cellular(6, 6, 1.0, 0.05), inputs.pseudo(36, 0.75, 0.1)]
+    say(f"[tt] small trajectory runs={runs}")
+    ctx = _ctx(inst, isl, interval=5, runs=runs, seed=11)
+    gas = [ot.GA(inst, isl, interval=5, seed=11, inst_id=r) for r in range(runs)]
+    for r, ga in enumerate(gas):
+        _same(ctx, ga, r, 2, f"run {r} generation 0")
+    done = 0
+    for chunk in (1, 4, 5, 7, 13):
+        ctx.evolve(chunk)
+        done += chunk
+        for r, ga in enumerate(gas):
+            ga.evolve(chunk)
+            _same(ctx, ga, r, 2, f"run {r} generation {done}")
+            b1, b2 = ctx.best(r), ga.best()
+            assert (b1["objective"], b1["generation"], b1["island"], b1["slot"]) == \
+                   (b2["objective"], b2["generation"], b2["island"], b2["slot"])
+            assert np.array_equal(b1["genes"], b2["genes"])
+            assert ctx.counters(r) == ga.counters()
+    ctx.close()
+
+
+def test_section5_size_trajectory():
+    """Section 5's sizes: 300 jobs, 4 stages, 2 unrelated machines each, a
+    16x16 cellular island and a pseudo island of 256 (rates 1.00 / 0.05 and
+    0.75), migration every 10 generations here so that epochs are covered."""
+    ensure_built()
+    w = inputs.tardiness_setting("dual", seed=1)
+    say("[tt] section-5 size trajectory")
+    ctx = _ctx(w["inst"], w["islands"], interval=10, seed=3)
+    ga = ot.GA(w["inst"], w["islands"], interval=10, seed=3)
+    _same(ctx, ga, 0, 2, "generation 0")
+    for g in (9, 1, 10, 15):
+        ctx.evolve(g)
+        ga.evolve(g)
+        _same(ctx, ga, 0, 2, f"generation {ga.generation}")
+    assert ctx.best(0)["objective"] == ga.best()["objective"]
+    assert ctx.counters(0) == ga.counters()
+    ctx.close()
+
+
+def test_forced_migration_and_restored_state():
+    ensure_built()
+    inst = inputs.tardiness_instance(30, 4, [2, 2, 3, 2], seed=9)
+    isl = [inputs.cellular(4, 5, 1.0, 0.05), inputs.pseudo(20, 0.75, 0.0),
+           inputs.cellular(3, 4, 0.9, 0.1), inputs.pseudo(12, 0.5, 0.05)]
+    say("[tt] four islands, forced epoch, restored state")
+    ctx = _ctx(inst, isl, interval=0, seed=5)
+    ga = ot.GA(inst, isl, interval=0, seed=5)
+    ctx.evolve(6)
+    ga.evolve(6)
+    _same(ctx, ga, 0, 4, "generation 6")
+    ctx.migrate()
+    ga.migrate()
+    _same(ctx, ga, 0, 4, "forced epoch")
+    assert ctx.counters(0) == ga.counters()
+    # a state taken from the GPU, loaded into the oracle at another generation
+    ctx.set_generation(11)
+    ga.set_generation(11)
+    ctx.evolve(3)
+    ga.evolve(3)
+    _same(ctx, ga, 0, 4, "after restore")
+    ctx.close()
