@@ -41,7 +41,6 @@ using flowshop::draw32;
 using flowshop::stream_block;
 
 constexpr int kMaxJ = 1024, kMaxS = 32, kMaxM = 4, kMaxIsl = 8, kMaxIslSize = 4096, kMaxRuns = 1024;
-constexpr int kKMax = kMaxJ / 64;     // positions per lane
 constexpr int kNeg = -(1 << 30) - 1;  // A of the identity; every real A is >= 0
 constexpr int kSortThreads = 1024;
 
@@ -162,21 +161,11 @@ __device__ __forceinline__ int scan_add(int x, int lane)
     return x;
 }
 
-// Number of entries of keys[0..n) below `key` (keys ascending).
-__device__ __forceinline__ int count_below(const unsigned long long* keys, int n, unsigned long long key)
-{
-    int lo = 0, hi = n;
-    while (lo < hi) {
-        const int mid = (lo + hi) >> 1;
-        if (keys[mid] < key) lo = mid + 1;
-        else hi = mid;
-    }
-    return lo;
-}
-
 // The objective of the assignment in `child` (LDS, J*S genes), decoded by
 // the whole wave; -1 if a gene is out of range.  Work arrays in LDS:
-// ord/rdy (two buffers each, Jp entries) and keys (Jp entries).
+// ord/rdy (two buffers each, Jp entries) and keys (Jp entries).  A lane owns
+// K = ceil(J / 64) <= KMAX consecutive positions.
+template <int KMAX>
 __device__ long long decode_wave(const TtDesc& d, const Smem& sm, const uint8_t* child, uint16_t* ordA,
                                  uint16_t* ordB, int* rdyA, int* rdyB, unsigned long long* keys, int lane)
 {
@@ -193,11 +182,11 @@ __device__ long long decode_wave(const TtDesc& d, const Smem& sm, const uint8_t*
         }
     }
     wave_sync();
-    int cloc[kKMax];
-    int jloc[kKMax];
+    int cloc[KMAX];
+    int jloc[KMAX];
     for (int s = 0; s < S; ++s) {
         const int Ms = sm.M[s];
-        int mloc[kKMax], rloc[kKMax], ploc[kKMax];
+        int mloc[KMAX], rloc[KMAX], ploc[KMAX];
         int A[kMaxM], B[kMaxM], cnt[kMaxM];
 #pragma unroll
         for (int m = 0; m < kMaxM; ++m) {
@@ -207,7 +196,7 @@ __device__ long long decode_wave(const TtDesc& d, const Smem& sm, const uint8_t*
         }
         // the lane's positions: machine, ready time, processing time
 #pragma unroll
-        for (int u = 0; u < kKMax; ++u) {
+        for (int u = 0; u < KMAX; ++u) {
             mloc[u] = -1;
             if (u < K && t0 + u < J) {
                 const int t = t0 + u;
@@ -250,9 +239,9 @@ __device__ long long decode_wave(const TtDesc& d, const Smem& sm, const uint8_t*
             run_off += (m < Ms) ? tot[m] : 0;
         }
         // completions, and each machine's list of (completion << 16 | position)
-        int own[kKMax];
+        int own[KMAX];
 #pragma unroll
-        for (int u = 0; u < kKMax; ++u) {
+        for (int u = 0; u < KMAX; ++u) {
             if (mloc[u] >= 0) {
                 const int m = mloc[u];
                 int c = 0, idx = 0, base = 0;
@@ -272,19 +261,42 @@ __device__ long long decode_wave(const TtDesc& d, const Smem& sm, const uint8_t*
             }
         }
         wave_sync();
-        // rank in the next stage's order; write it
+        // rank in the next stage's order: own index plus, in every other
+        // machine's list, the number of entries below the key -- a
+        // power-of-two search with a fixed step sequence, run for all of the
+        // lane's positions in lockstep so that their LDS reads overlap
+        unsigned long long key[KMAX];
 #pragma unroll
-        for (int u = 0; u < kKMax; ++u) {
-            if (mloc[u] >= 0) {
-                const unsigned long long key = ((unsigned long long)(unsigned)cloc[u] << 16) | (unsigned)(t0 + u);
-                int rank = own[u];
+        for (int u = 0; u < KMAX; ++u)
+            key[u] = ((unsigned long long)(unsigned)(mloc[u] >= 0 ? cloc[u] : 0) << 16) | (unsigned)(t0 + u);
+        int top = 1;
+        while (top <= J) top <<= 1;
 #pragma unroll
-                for (int mm = 0; mm < kMaxM; ++mm)
-                    if (mm < Ms && mm != mloc[u]) rank += count_below(keys + off[mm], tot[mm], key);
-                ordB[rank] = (uint16_t)jloc[u];
-                rdyB[rank] = cloc[u];
+        for (int mm = 0; mm < kMaxM; ++mm) {
+            if (mm >= Ms) break;
+            const unsigned long long* lst = keys + off[mm];
+            const int n = tot[mm];
+            int pos[KMAX];
+#pragma unroll
+            for (int u = 0; u < KMAX; ++u) pos[u] = 0;
+            for (int step = top >> 1; step > 0; step >>= 1) {
+#pragma unroll
+                for (int u = 0; u < KMAX; ++u) {
+                    const int at = pos[u] + step;
+                    // entries lst[0..at) all below the key: advance
+                    if (at <= n && lst[at - 1] < key[u]) pos[u] = at;
+                }
             }
+#pragma unroll
+            for (int u = 0; u < KMAX; ++u)
+                if (mloc[u] >= 0 && mloc[u] != mm) own[u] += pos[u];
         }
+#pragma unroll
+        for (int u = 0; u < KMAX; ++u)
+            if (mloc[u] >= 0) {
+                ordB[own[u]] = (uint16_t)jloc[u];
+                rdyB[own[u]] = cloc[u];
+            }
         wave_sync();
         uint16_t* to = ordA;
         ordA = ordB;
@@ -297,7 +309,7 @@ __device__ long long decode_wave(const TtDesc& d, const Smem& sm, const uint8_t*
     long long tard = 0;
     int cmax = 0;
 #pragma unroll
-    for (int u = 0; u < kKMax; ++u)
+    for (int u = 0; u < KMAX; ++u)
         if (u < K && t0 + u < J) {
             const int late = cloc[u] - sm.D[jloc[u]];
             if (late > 0) tard += late;
@@ -342,6 +354,7 @@ extern __shared__ __align__(16) unsigned char tt_smem[];
 // Generation `gen` of every run: mode 1 builds generation 0 (random
 // assignments; a pseudo pair = X and its complement), mode 0 steps every
 // island from generation gen - 1.
+template <int KMAX>
 __global__ void __launch_bounds__(256) k_tt_generation(TtDesc d, int gen, int mode)
 {
     const Smem sm = smem_tables(tt_smem, d.J, d.S, d.MX);
@@ -483,7 +496,7 @@ __global__ void __launch_bounds__(256) k_tt_generation(TtDesc d, int gen, int mo
         }
     }
     wave_sync();
-    const long long o = decode_wave(d, sm, child, w.ordA, w.ordB, w.rdyA, w.rdyB, w.keys, lane);
+    const long long o = decode_wave<KMAX>(d, sm, child, w.ordA, w.ordB, w.rdyA, w.rdyB, w.keys, lane);
     // replacement (cellular: only if strictly better) and write-out
     uint8_t* dst = d.genes[nxt] + (rowbase + slot) * Lp;
     long long onew = o;
@@ -626,6 +639,7 @@ __global__ void __launch_bounds__(kSortThreads) k_tt_migrate(TtDesc d, int gen)
 }
 
 // Objectives of caller-supplied assignments (count rows of L genes).
+template <int KMAX>
 __global__ void __launch_bounds__(256) k_tt_evaluate(TtDesc d, const uint8_t* genes, int count, long long* out)
 {
     const Smem sm = smem_tables(tt_smem, d.J, d.S, d.MX);
@@ -638,7 +652,7 @@ __global__ void __launch_bounds__(256) k_tt_evaluate(TtDesc d, const uint8_t* ge
     const uint8_t* src = genes + row * d.L;
     for (int i = lane; i < d.L; i += 64) w.child[i] = src[i];
     wave_sync();
-    const long long o = decode_wave(d, sm, w.child, w.ordA, w.ordB, w.rdyA, w.rdyB, w.keys, lane);
+    const long long o = decode_wave<KMAX>(d, sm, w.child, w.ordA, w.ordB, w.rdyA, w.rdyB, w.keys, lane);
     if (lane == 0) out[row] = o;
 }
 
@@ -672,6 +686,7 @@ struct ffs_tt_ctx {
     int gen = 0;
     TtDesc desc{};
     int wpb = 4;
+    int kmax = 16;   // positions per lane bound of the decode (8 when J <= 512)
     size_t lds_gen = 0;
     // timing
     bool timing = false;
@@ -761,7 +776,12 @@ int launch_gen(ffs_tt_ctx* c, int gen, int mode)
         e1 = c->ev[c->ev_used++];
         TT_HIP(c, hipEventRecord(e0, c->stream));
     }
-    hipLaunchKernelGGL(k_tt_generation, dim3(blocks), dim3(64 * c->wpb), c->lds_gen, c->stream, c->desc, gen, mode);
+    if (c->kmax == 8)
+        hipLaunchKernelGGL(k_tt_generation<8>, dim3(blocks), dim3(64 * c->wpb), c->lds_gen, c->stream, c->desc, gen,
+                           mode);
+    else
+        hipLaunchKernelGGL(k_tt_generation<16>, dim3(blocks), dim3(64 * c->wpb), c->lds_gen, c->stream, c->desc, gen,
+                           mode);
     TT_HIP(c, hipGetLastError());
     if (c->timing) TT_HIP(c, hipEventRecord(e1, c->stream));
     hipLaunchKernelGGL(k_tt_fold, dim3((unsigned)((c->runs + 63) / 64)), dim3(64), 0, c->stream, c->desc, gen);
@@ -935,10 +955,13 @@ int ffs_tt_bind_workspace(ffs_tt_ctx* c, void* ptr, size_t bytes)
     if (tb + wpb * wb > 160 * 1024) return fail(c, FFS_EUNSUPPORTED, "instance tables need %zu bytes of LDS", tb + wb);
     c->wpb = wpb;
     c->lds_gen = tb + wpb * wb;
-    TT_HIP(c, hipFuncSetAttribute(reinterpret_cast<const void*>(&k_tt_generation),
-                                  hipFuncAttributeMaxDynamicSharedMemorySize, (int)c->lds_gen));
-    TT_HIP(c, hipFuncSetAttribute(reinterpret_cast<const void*>(&k_tt_evaluate),
-                                  hipFuncAttributeMaxDynamicSharedMemorySize, (int)c->lds_gen));
+    c->kmax = (c->J <= 512) ? 8 : 16;
+    const void* kg = c->kmax == 8 ? reinterpret_cast<const void*>(&k_tt_generation<8>)
+                                  : reinterpret_cast<const void*>(&k_tt_generation<16>);
+    const void* ke = c->kmax == 8 ? reinterpret_cast<const void*>(&k_tt_evaluate<8>)
+                                  : reinterpret_cast<const void*>(&k_tt_evaluate<16>);
+    TT_HIP(c, hipFuncSetAttribute(kg, hipFuncAttributeMaxDynamicSharedMemorySize, (int)c->lds_gen));
+    TT_HIP(c, hipFuncSetAttribute(ke, hipFuncAttributeMaxDynamicSharedMemorySize, (int)c->lds_gen));
     TT_HIP(c, hipFuncSetAttribute(reinterpret_cast<const void*>(&k_tt_migrate),
                                   hipFuncAttributeMaxDynamicSharedMemorySize, 2 * kMaxIslSize * 8));
     c->ws = reinterpret_cast<char*>(ptr);
@@ -1159,8 +1182,12 @@ int ffs_tt_evaluate(ffs_tt_ctx* c, const void* genes, int32_t count, void* out)
     if (count < 0 || (count > 0 && (!genes || !out))) return fail(c, FFS_EINVAL, "count %d", count);
     if (count == 0) return FFS_OK;
     const unsigned blocks = (unsigned)((count + c->wpb - 1) / c->wpb);
-    hipLaunchKernelGGL(k_tt_evaluate, dim3(blocks), dim3(64 * c->wpb), c->lds_gen, c->stream, c->desc,
-                       reinterpret_cast<const uint8_t*>(genes), count, reinterpret_cast<long long*>(out));
+    if (c->kmax == 8)
+        hipLaunchKernelGGL(k_tt_evaluate<8>, dim3(blocks), dim3(64 * c->wpb), c->lds_gen, c->stream, c->desc,
+                           reinterpret_cast<const uint8_t*>(genes), count, reinterpret_cast<long long*>(out));
+    else
+        hipLaunchKernelGGL(k_tt_evaluate<16>, dim3(blocks), dim3(64 * c->wpb), c->lds_gen, c->stream, c->desc,
+                           reinterpret_cast<const uint8_t*>(genes), count, reinterpret_cast<long long*>(out));
     TT_HIP(c, hipGetLastError());
     return FFS_OK;
 }
