@@ -96,9 +96,9 @@ __device__ __forceinline__ void wave_sync()
 __host__ __device__ inline int align16(int x) { return (x + 15) & ~15; }
 
 // LDS bytes of the shared tables and of one wave's work area.
-__host__ __device__ inline int tables_bytes(int J, int S, int MX)
+__host__ __device__ inline int tables_bytes(int J, int S, int MX, int Lp)
 {
-    return align16(J * S * MX * 2) + align16(J * 4) * 2 + align16(J * 2) + align16(S * 4);
+    return align16(J * S * MX * 2) + align16(J * 4) * 2 + align16(J * 2) + align16(S * 4) + Lp;
 }
 __host__ __device__ inline int wave_bytes(int Lp, int Jp) { return Lp + Jp * 2 * 2 + Jp * 4 * 2 + Jp * 8; }
 
@@ -108,6 +108,7 @@ struct Smem {
     int* R;
     uint16_t* ord0;
     int* M;
+    uint8_t* cb;   // [Lp]: M_s - 1 of gene i's stage (0 past the string): complement base
 };
 
 __device__ __forceinline__ Smem smem_tables(unsigned char* base, int J, int S, int MX)
@@ -122,6 +123,8 @@ __device__ __forceinline__ Smem smem_tables(unsigned char* base, int J, int S, i
     s.ord0 = reinterpret_cast<uint16_t*>(base);
     base += align16(J * 2);
     s.M = reinterpret_cast<int*>(base);
+    base += align16(S * 4);
+    s.cb = base;
     return s;
 }
 
@@ -135,6 +138,7 @@ __device__ void stage_tables(const TtDesc& d, const Smem& s)
         s.ord0[i] = d.ord0[i];
     }
     for (int i = threadIdx.x; i < d.S; i += blockDim.x) s.M[i] = d.M[i];
+    for (int i = threadIdx.x; i < d.Lp; i += blockDim.x) s.cb[i] = (uint8_t)(i < d.L ? d.M[i % d.S] - 1 : 0);
 }
 
 // Wave-wide inclusive scan of (A, B) under "left then right".
@@ -227,16 +231,19 @@ __device__ long long decode_wave(const TtDesc& d, const Smem& sm, const uint8_t*
         int run_off = 0;
 #pragma unroll
         for (int m = 0; m < kMaxM; ++m) {
-            int Ai = A[m], Bi = B[m];
-            scan_maxplus(Ai, Bi, lane);
-            const int Ae = __shfl_up(Ai, 1, 64), Be = __shfl_up(Bi, 1, 64);
-            A[m] = (lane == 0) ? kNeg : Ae;
-            B[m] = (lane == 0) ? 0 : Be;
-            const int ci = scan_add(cnt[m], lane);
-            tot[m] = __shfl(ci, 63, 64);
-            cnt[m] = ci - cnt[m];   // exclusive: entries of machine m before this lane
             off[m] = run_off;
-            run_off += (m < Ms) ? tot[m] : 0;
+            tot[m] = 0;
+            if (m < Ms) {   // the stage's machines only (uniform)
+                int Ai = A[m], Bi = B[m];
+                scan_maxplus(Ai, Bi, lane);
+                const int Ae = __shfl_up(Ai, 1, 64), Be = __shfl_up(Bi, 1, 64);
+                A[m] = (lane == 0) ? kNeg : Ae;
+                B[m] = (lane == 0) ? 0 : Be;
+                const int ci = scan_add(cnt[m], lane);
+                tot[m] = __shfl(ci, 63, 64);
+                cnt[m] = ci - cnt[m];   // exclusive: entries of machine m before this lane
+                run_off += tot[m];
+            }
         }
         // completions, and each machine's list of (completion << 16 | position)
         int own[KMAX];
@@ -271,25 +278,37 @@ __device__ long long decode_wave(const TtDesc& d, const Smem& sm, const uint8_t*
             key[u] = ((unsigned long long)(unsigned)(mloc[u] >= 0 ? cloc[u] : 0) << 16) | (unsigned)(t0 + u);
         int top = 1;
         while (top <= J) top <<= 1;
+        for (int oi = 1; oi < Ms; ++oi) {
+            // position u searches machine (m_u + oi) mod Ms: each other machine once
+            int lb[KMAX], n[KMAX], pos[KMAX];
 #pragma unroll
-        for (int mm = 0; mm < kMaxM; ++mm) {
-            if (mm >= Ms) break;
-            const unsigned long long* lst = keys + off[mm];
-            const int n = tot[mm];
-            int pos[KMAX];
+            for (int u = 0; u < KMAX; ++u) {
+                int om = (mloc[u] >= 0 ? mloc[u] : 0) + oi;
+                om = om >= Ms ? om - Ms : om;
+                int ob = 0, on = 0;
 #pragma unroll
-            for (int u = 0; u < KMAX; ++u) pos[u] = 0;
+                for (int mm = 0; mm < kMaxM; ++mm)
+                    if (mm == om) {
+                        ob = off[mm];
+                        on = tot[mm];
+                    }
+                lb[u] = ob - 1;
+                n[u] = (mloc[u] >= 0) ? on : 0;
+                pos[u] = 0;
+            }
             for (int step = top >> 1; step > 0; step >>= 1) {
 #pragma unroll
                 for (int u = 0; u < KMAX; ++u) {
-                    const int at = pos[u] + step;
-                    // entries lst[0..at) all below the key: advance
-                    if (at <= n && lst[at - 1] < key[u]) pos[u] = at;
+                    if (u < K) {   // uniform
+                        const int at = pos[u] + step;
+                        // entries lst[0..at) all below the key: advance
+                        if (at <= n[u] && keys[lb[u] + at] < key[u]) pos[u] = at;
+                    }
                 }
             }
 #pragma unroll
             for (int u = 0; u < KMAX; ++u)
-                if (mloc[u] >= 0 && mloc[u] != mm) own[u] += pos[u];
+                if (mloc[u] >= 0) own[u] += pos[u];
         }
 #pragma unroll
         for (int u = 0; u < KMAX; ++u)
@@ -371,7 +390,7 @@ __global__ void __launch_bounds__(256) k_tt_generation(TtDesc d, int gen, int mo
     const TtIsland I = island_at(d, isl);
     const int slot = ind - I.off;
     const int L = d.L, Lp = d.Lp, S = d.S;
-    const WaveMem w = wave_mem(tt_smem + tables_bytes(d.J, S, d.MX) + wave * wave_bytes(Lp, d.Jp), Lp, d.Jp);
+    const WaveMem w = wave_mem(tt_smem + tables_bytes(d.J, S, d.MX, d.Lp) + wave * wave_bytes(Lp, d.Jp), Lp, d.Jp);
     const int cur = (gen + 1) & 1, nxt = gen & 1;
     const long long rowbase = (long long)run * d.N + I.off;   // individual index of slot 0
     uint8_t* child = w.child;
@@ -469,22 +488,25 @@ __global__ void __launch_bounds__(256) k_tt_generation(TtDesc d, int gen, int mo
         const uint8_t* X = d.genes[cur] + (rowbase + xs) * Lp;
         for (int i0 = lane * 16; i0 < Lp; i0 += 64 * 16) {
             const uint4 x1 = *reinterpret_cast<const uint4*>(X + i0);
+            const uint4 c1 = *reinterpret_cast<const uint4*>(sm.cb + i0);
             uint32_t o[4];
 #pragma unroll
             for (int wd = 0; wd < 4; ++wd) {
                 const uint32_t xw = word_of(x1, wd);
-                uint32_t ow = 0;
+                // complement of four genes at once: every byte of the base is
+                // >= the gene below it, so the subtraction borrows only in the
+                // padding past the string (higher bytes)
+                const uint32_t yw = word_of(c1, wd) - xw;
+                uint32_t mask = 0;
 #pragma unroll
                 for (int q = 0; q < 4; ++q) {
                     const int i = i0 + wd * 4 + q;
-                    const int x = (int)((xw >> (8 * q)) & 0xFFu);
-                    const int y = (i < L) ? sm.M[i % S] - 1 - x : 0;
                     // even child: X on [a, b], complement elsewhere (X if no
                     // crossover); odd child: the opposite
                     const bool takex = cx ? ((i >= a && i <= e) != odd) : !odd;
-                    ow |= (uint32_t)((takex ? x : y) & 0xFF) << (8 * q);
+                    if (takex) mask |= 0xFFu << (8 * q);
                 }
-                o[wd] = ow;
+                o[wd] = (xw & mask) | (yw & ~mask);
             }
             *reinterpret_cast<uint4*>(child + i0) = make_uint4(o[0], o[1], o[2], o[3]);
         }
@@ -648,7 +670,7 @@ __global__ void __launch_bounds__(256) k_tt_evaluate(TtDesc d, const uint8_t* ge
     const int wpb = blockDim.x >> 6, wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
     const long long row = (long long)blockIdx.x * wpb + wave;
     if (row >= count) return;
-    const WaveMem w = wave_mem(tt_smem + tables_bytes(d.J, d.S, d.MX) + wave * wave_bytes(d.Lp, d.Jp), d.Lp, d.Jp);
+    const WaveMem w = wave_mem(tt_smem + tables_bytes(d.J, d.S, d.MX, d.Lp) + wave * wave_bytes(d.Lp, d.Jp), d.Lp, d.Jp);
     const uint8_t* src = genes + row * d.L;
     for (int i = lane; i < d.L; i += 64) w.child[i] = src[i];
     wave_sync();
@@ -949,7 +971,7 @@ int ffs_tt_bind_workspace(ffs_tt_ctx* c, void* ptr, size_t bytes)
     const Layout l = layout_of(c);
     if (bytes < l.total) return fail(c, FFS_ENOMEM, "workspace %zu < %zu", bytes, l.total);
     // LDS: tables + waves; up to 4 waves per workgroup, fewer if that does not fit
-    const size_t tb = (size_t)tables_bytes(c->J, c->S, c->MX), wb = (size_t)wave_bytes(c->Lp, c->Jp);
+    const size_t tb = (size_t)tables_bytes(c->J, c->S, c->MX, c->Lp), wb = (size_t)wave_bytes(c->Lp, c->Jp);
     int wpb = 4;
     while (wpb > 1 && tb + wpb * wb > 160 * 1024) --wpb;
     if (tb + wpb * wb > 160 * 1024) return fail(c, FFS_EUNSUPPORTED, "instance tables need %zu bytes of LDS", tb + wb);
