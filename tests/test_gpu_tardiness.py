@@ -128,3 +128,43 @@ def test_forced_migration_and_restored_state():
     ga.evolve(3)
     _same(ctx, ga, 0, 4, "after restore")
     ctx.close()
+
+
+def test_theta_below_one_and_largest_islands():
+    """theta = 0.3 (the threshold branch of equation (1) in exact 128-bit
+    arithmetic) on islands of 4096 (the largest sort span), four machines at
+    one stage."""
+    ensure_built()
+    inst = inputs.tardiness_instance(12, 3, [4, 2, 1], seed=12)
+    isl = [inputs.cellular(64, 64, 1.0, 0.05), inputs.pseudo(4096, 0.75, 0.05)]
+    say("[tt] theta 0.3, islands of 4096")
+    from paper_1903_10722_amd.tardiness import TtContext
+    ctx = TtContext(inst, isl, interval=4, theta=0.3, seed=21, runs=1)
+    ga = ot.GA(inst, isl, interval=4, theta=0.3, seed=21)
+    for g in (4, 4, 3):
+        ctx.evolve(g)
+        ga.evolve(g)
+        _same(ctx, ga, 0, 2, f"generation {ga.generation}")
+    assert ctx.counters(0) == ga.counters()
+    ctx.close()
+
+
+def test_state_loaded_from_the_oracle():
+    """ffs_tt_set_population: a state the oracle reached, loaded into the GPU
+    context, evolves identically on both sides."""
+    ensure_built()
+    inst = inputs.tardiness_instance(40, 4, [2, 3, 2, 1], seed=13)
+    isl = [inputs.cellular(5, 6, 1.0, 0.1), inputs.pseudo(30, 0.75, 0.1)]
+    say("[tt] state loaded from the oracle")
+    ga = ot.GA(inst, isl, interval=6, seed=31)
+    ga.evolve(9)
+    ctx = _ctx(inst, isl, interval=6, seed=31)
+    ctx.set_generation(9)
+    for i in range(2):
+        g, o = ga.population(i)
+        ctx.set_population(0, i, g, o)
+    _same(ctx, ga, 0, 2, "loaded")
+    ctx.evolve(8)
+    ga.evolve(8)
+    _same(ctx, ga, 0, 2, "after 8 generations")
+    ctx.close()
