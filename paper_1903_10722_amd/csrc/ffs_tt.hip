@@ -141,28 +141,55 @@ __device__ void stage_tables(const TtDesc& d, const Smem& s)
     for (int i = threadIdx.x; i < d.Lp; i += blockDim.x) s.cb[i] = (uint8_t)(i < d.L ? d.M[i % d.S] - 1 : 0);
 }
 
-// Wave-wide inclusive scan of (A, B) under "left then right".
-__device__ __forceinline__ void scan_maxplus(int& A, int& B, int lane)
+// Wave-wide inclusive scans in registers (DPP): row_shr 1, 2, 4, 8 inside
+// each 16-lane row, then row_bcast 15 (rows 1 and 3 take the last lane of the
+// row before) and row_bcast 31 (rows 2 and 3 take lane 31).  A lane whose
+// source is outside its row, or whose row is masked off, reads the identity.
+template <int CTRL, int ROWS>
+__device__ __forceinline__ void maxplus_step(int& A, int& B)
 {
-#pragma unroll
-    for (int off = 1; off < 64; off <<= 1) {
-        const int Al = __shfl_up(A, off, 64), Bl = __shfl_up(B, off, 64);
-        if (lane >= off) {
-            const int a2 = A - Bl;
-            A = Al > a2 ? Al : a2;
-            B = Bl + B;
-        }
-    }
+    const int Al = __builtin_amdgcn_update_dpp(kNeg, A, CTRL, ROWS, 0xF, false);
+    int Bl = __builtin_amdgcn_update_dpp(0, B, CTRL, ROWS, 0xF, false);
+    // keep the shifted value in its own register: fused into the subtraction
+    // (v_subrev_u32_dpp) the shift was measured to apply to the other operand
+    asm volatile("" : "+v"(Bl));
+    const int a2 = A - Bl;
+    A = Al > a2 ? Al : a2;
+    B = Bl + B;
 }
 
-__device__ __forceinline__ int scan_add(int x, int lane)
+// (A, B) under "left then right": (max(A_l, A_r - B_l), B_l + B_r)
+__device__ __forceinline__ void scan_maxplus(int& A, int& B)
 {
-#pragma unroll
-    for (int off = 1; off < 64; off <<= 1) {
-        const int y = __shfl_up(x, off, 64);
-        if (lane >= off) x += y;
-    }
+    maxplus_step<0x111, 0xF>(A, B);
+    maxplus_step<0x112, 0xF>(A, B);
+    maxplus_step<0x114, 0xF>(A, B);
+    maxplus_step<0x118, 0xF>(A, B);
+    maxplus_step<0x142, 0xA>(A, B);
+    maxplus_step<0x143, 0xC>(A, B);
+}
+
+template <int CTRL, int ROWS>
+__device__ __forceinline__ int add_step(int x)
+{
+    return x + __builtin_amdgcn_update_dpp(0, x, CTRL, ROWS, 0xF, false);
+}
+
+__device__ __forceinline__ int scan_add(int x)
+{
+    x = add_step<0x111, 0xF>(x);
+    x = add_step<0x112, 0xF>(x);
+    x = add_step<0x114, 0xF>(x);
+    x = add_step<0x118, 0xF>(x);
+    x = add_step<0x142, 0xA>(x);
+    x = add_step<0x143, 0xC>(x);
     return x;
+}
+
+// value of lane - 1 (lane 0 reads `first`)
+__device__ __forceinline__ int from_lane_below(int x, int first)
+{
+    return __builtin_amdgcn_update_dpp(first, x, 0x138 /* wave_shr:1 */, 0xF, 0xF, false);
 }
 
 // The objective of the assignment in `child` (LDS, J*S genes), decoded by
@@ -235,12 +262,11 @@ __device__ long long decode_wave(const TtDesc& d, const Smem& sm, const uint8_t*
             tot[m] = 0;
             if (m < Ms) {   // the stage's machines only (uniform)
                 int Ai = A[m], Bi = B[m];
-                scan_maxplus(Ai, Bi, lane);
-                const int Ae = __shfl_up(Ai, 1, 64), Be = __shfl_up(Bi, 1, 64);
-                A[m] = (lane == 0) ? kNeg : Ae;
-                B[m] = (lane == 0) ? 0 : Be;
-                const int ci = scan_add(cnt[m], lane);
-                tot[m] = __shfl(ci, 63, 64);
+                scan_maxplus(Ai, Bi);
+                A[m] = from_lane_below(Ai, kNeg);   // exclusive prefix
+                B[m] = from_lane_below(Bi, 0);
+                const int ci = scan_add(cnt[m]);
+                tot[m] = __builtin_amdgcn_readlane(ci, 63);
                 cnt[m] = ci - cnt[m];   // exclusive: entries of machine m before this lane
                 run_off += tot[m];
             }
