@@ -117,9 +117,17 @@ int ffs_tt_counters(ffs_tt_ctx* ctx, int32_t run, int64_t* migrations, int64_t* 
  * count int64 objectives.  A gene out of range gives -1 for its row. */
 int ffs_tt_evaluate(ffs_tt_ctx* ctx, const void* genes, int32_t count, void* out);
 
-/* Timing of the generation kernel: on = 1 brackets every launch with HIP
- * events; ffs_tt_kernel_time (syncs) returns the summed milliseconds and the
- * launch count since timing was switched on. */
+/* Update schedule of the cellular islands (an alternative reading of
+ * Section 4.2, which gives none): 0 = synchronous (every cell reads the
+ * previous generation; the default), 1 = asynchronous line sweep (cells in
+ * row-major order, each reading its neighbours as already updated in this
+ * generation).  May be changed between calls to ffs_tt_evolve. */
+int ffs_tt_set_update(ffs_tt_ctx* ctx, int32_t mode);
+
+/* Timing of the generation kernel: on = 1 brackets the kernel launches of
+ * every generation with HIP events; ffs_tt_kernel_time (syncs) returns the
+ * summed milliseconds and the number of generations since timing was
+ * switched on. */
 int ffs_tt_set_timing(ffs_tt_ctx* ctx, int32_t on);
 int ffs_tt_kernel_time(ffs_tt_ctx* ctx, double* ms, int64_t* launches);
 

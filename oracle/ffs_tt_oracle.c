@@ -28,6 +28,10 @@
  *   - Cellular GA (Sections 4.1, 4.2): the two best of the von Neumann
  *     neighbourhood, two-point crossover (reading), mutation of one gene to
  *     another machine of its stage (reading), replacement if strictly better.
+ *     Update schedule: synchronous (every cell reads the previous
+ *     generation), or, as an alternative reading, an asynchronous line sweep:
+ *     cells in row-major order, each reading its neighbours as they are at
+ *     that moment (already updated ones included).
  *   - Pseudo GA (Section 4.1): pairs (X, complement of X); X = the better of
  *     the pair mates with its complement, the two children replace the pair.
  *   - Migration (Section 4.3, equations (1) and (2)) on the fitness
@@ -211,6 +215,7 @@ typedef struct {
     int interval;
     double theta;
     uint64_t seed, inst;
+    int sweep;           /* cellular update: 0 synchronous, 1 line sweep */
     int gen;
     int64_t best_obj;
     int best_gen, best_island, best_slot;
@@ -303,6 +308,39 @@ static void tt_two_best(const int64_t *obj, const int *nb, int *p1, int *p2)
         if (c < 0 || obj[nb[t]] < obj[nb[c]]) c = t;
     }
     *p1 = nb[b]; *p2 = nb[c];
+}
+
+/* one generation of a cellular island as an asynchronous line sweep: cells
+ * in row-major order, in place, each seeing the current state. */
+static void tt_cellular_sweep(tt_ga_t *g, int island)
+{
+    tt_island_t *I = &g->isl[island];
+    int L = g->L;
+    int *child = (int *)malloc(sizeof(int) * (size_t)L);
+    for (int s = 0; s < I->size; ++s) {
+        int r = s / I->cols, c = s % I->cols;
+        int nb[5] = {s, ((r + I->rows - 1) % I->rows) * I->cols + c, r * I->cols + (c + 1) % I->cols,
+                     ((r + 1) % I->rows) * I->cols + c, r * I->cols + (c + I->cols - 1) % I->cols};
+        int p1, p2;
+        tt_two_best(I->obj, nb, &p1, &p2);
+        uint32_t d[6];
+        for (int t = 0; t < 6; ++t)
+            d[t] = or_draw(g->seed, g->inst, (uint32_t)island, (uint32_t)s, 0, (uint32_t)g->gen, TT_CELL, (uint32_t)t);
+        const int *P1 = I->genes + (size_t)p1 * L, *P2 = I->genes + (size_t)p2 * L;
+        if ((uint64_t)d[0] < I->tc) {
+            int u = (int)below(d[1], (uint32_t)L), v = (int)below(d[2], (uint32_t)L);
+            or_tt_two_point(L, P1, P2, u < v ? u : v, u < v ? v : u, child);
+        } else {
+            memcpy(child, P1, sizeof(int) * (size_t)L);
+        }
+        tt_mutate(g->J, g->S, g->M, child, d[3], d[4], d[5], I->tm);
+        int64_t co = tt_obj(g, child);
+        if (co < I->obj[s]) {
+            memcpy(I->genes + (size_t)s * L, child, sizeof(int) * (size_t)L);
+            I->obj[s] = co;
+        }
+    }
+    free(child);
 }
 
 static void tt_cellular_step(tt_ga_t *g, int island)
@@ -424,8 +462,12 @@ void or_tt_ga_evolve(void *h, int G)
     for (int it = 0; it < G; ++it) {
         g->gen += 1;
         for (int i = 0; i < g->n_islands; ++i) {
-            if (g->isl[i].kind == 0) tt_cellular_step(g, i);
-            else tt_pseudo_step(g, i);
+            if (g->isl[i].kind == 0) {
+                if (g->sweep) tt_cellular_sweep(g, i);
+                else tt_cellular_step(g, i);
+            } else {
+                tt_pseudo_step(g, i);
+            }
         }
         tt_update_best(g);
         if (g->interval > 0 && g->gen % g->interval == 0) or_tt_ga_migrate(g);
@@ -433,6 +475,7 @@ void or_tt_ga_evolve(void *h, int G)
 }
 
 int or_tt_ga_generation(void *h) { return ((tt_ga_t *)h)->gen; }
+void or_tt_ga_set_update(void *h, int sweep) { ((tt_ga_t *)h)->sweep = sweep; }
 void or_tt_ga_set_generation(void *h, int gen) { ((tt_ga_t *)h)->gen = gen; }
 int64_t or_tt_ga_emax(void *h) { return ((tt_ga_t *)h)->E; }
 

@@ -45,6 +45,7 @@ def _lib():
     lib.or_tt_ga_generation.argtypes = [ctypes.c_void_p]
     lib.or_tt_ga_generation.restype = ctypes.c_int
     lib.or_tt_ga_set_generation.argtypes = [ctypes.c_void_p, ctypes.c_int]
+    lib.or_tt_ga_set_update.argtypes = [ctypes.c_void_p, ctypes.c_int]
     lib.or_tt_ga_emax.argtypes = [ctypes.c_void_p]
     lib.or_tt_ga_emax.restype = ctypes.c_int64
     lib.or_tt_ga_get.argtypes = [ctypes.c_void_p, ctypes.c_int, _i32p, _i64p]
@@ -121,7 +122,7 @@ def migration_policy(E, best_a, best_b, n_a, n_b, theta):
 class GA:
     """One trajectory of the variant's island GA (same seed, same trajectory)."""
 
-    def __init__(self, inst, islands, interval=500, theta=1.0, seed=101, inst_id=0):
+    def __init__(self, inst, islands, interval=500, theta=1.0, seed=101, inst_id=0, sweep=False):
         lib = _lib()
         J, S, M, MX, P, R, D, WT = _inst_args(inst)
         self.J, self.S, self.L = J, S, J * S
@@ -137,6 +138,7 @@ class GA:
                                       len(islands), _ptr(kinds, _i32p), _ptr(rows, _i32p), _ptr(cols, _i32p),
                                       _ptr(sizes, _i32p), _ptr(pc, _f64p), _ptr(pm, _f64p), int(interval),
                                       float(theta), int(seed), int(inst_id))
+        lib.or_tt_ga_set_update(self._h, 1 if sweep else 0)
 
     def __del__(self):
         if getattr(self, "_h", None):

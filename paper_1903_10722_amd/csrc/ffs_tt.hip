@@ -396,25 +396,56 @@ __device__ __forceinline__ WaveMem wave_mem(unsigned char* base, int Lp, int Jp)
 
 extern __shared__ __align__(16) unsigned char tt_smem[];
 
-// Generation `gen` of every run: mode 1 builds generation 0 (random
-// assignments; a pseudo pair = X and its complement), mode 0 steps every
-// island from generation gen - 1.
+// Generation `gen` of every run:
+//   mode 1: generation 0 (random assignments; a pseudo pair = X and its
+//           complement), every individual;
+//   mode 0: every island steps from generation gen - 1 (synchronous update);
+//   mode 2: the cells of cellular island `sel` on anti-diagonal `diag`
+//           (r + c = diag) of a line-sweep generation.  In row-major order a
+//           neighbour precedes the cell exactly when its diagonal is lower
+//           (the torus's wrapped neighbours included), so it is read from the
+//           new generation's buffer then and from the previous one otherwise;
+//           the diagonals run in order, one launch each;
+//   mode 3: the individuals of the pseudo islands only (`count` per run).
 template <int KMAX>
-__global__ void __launch_bounds__(256) k_tt_generation(TtDesc d, int gen, int mode)
+__global__ void __launch_bounds__(256) k_tt_generation(TtDesc d, int gen, int mode, int sel, int diag, int count)
 {
     const Smem sm = smem_tables(tt_smem, d.J, d.S, d.MX);
     stage_tables(d, sm);
     __syncthreads();
     const int wpb = blockDim.x >> 6, wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
     const long long wg = (long long)blockIdx.x * wpb + wave;
-    if (wg >= (long long)d.runs * d.N) return;
-    const int run = (int)(wg / d.N), ind = (int)(wg - (long long)run * d.N);
-    int isl = 0;
+    const int per_run = (mode <= 1) ? d.N : count;
+    if (wg >= (long long)d.runs * per_run) return;
+    const int run = (int)(wg / per_run), q0 = (int)(wg - (long long)run * per_run);
+    int isl = 0, slot = 0;
+    if (mode <= 1) {
 #pragma unroll
-    for (int i = 1; i < kMaxIsl; ++i)
-        if (i < d.n_isl && ind >= d.isl[i].off) isl = i;
+        for (int i = 1; i < kMaxIsl; ++i)
+            if (i < d.n_isl && q0 >= d.isl[i].off) isl = i;
+        slot = q0 - island_at(d, isl).off;
+    } else if (mode == 2) {
+        const TtIsland C = island_at(d, sel);
+        const int rlo = diag - (C.cols - 1) > 0 ? diag - (C.cols - 1) : 0;
+        const int r = rlo + q0;
+        isl = sel;
+        slot = r * C.cols + (diag - r);
+    } else {
+        // q0-th individual among the pseudo islands, in island order
+        int left = q0;
+#pragma unroll
+        for (int i = 0; i < kMaxIsl; ++i) {
+            const TtIsland X = d.isl[i];
+            if (i < d.n_isl && X.kind == 1 && left >= 0) {
+                if (left < X.size) {
+                    isl = i;
+                    slot = left;
+                }
+                left -= X.size;
+            }
+        }
+    }
     const TtIsland I = island_at(d, isl);
-    const int slot = ind - I.off;
     const int L = d.L, Lp = d.Lp, S = d.S;
     const WaveMem w = wave_mem(tt_smem + tables_bytes(d.J, S, d.MX, d.Lp) + wave * wave_bytes(Lp, d.Jp), Lp, d.Jp);
     const int cur = (gen + 1) & 1, nxt = gen & 1;
@@ -439,16 +470,22 @@ __global__ void __launch_bounds__(256) k_tt_generation(TtDesc d, int gen, int mo
             }
         }
     } else if (I.kind == 0) {
-        const long long* ob = d.obj[cur] + rowbase;
         const int r = slot / I.cols, c = slot - r * I.cols;
-        const int nb[5] = {slot, ((r == 0) ? I.rows - 1 : r - 1) * I.cols + c,
-                           r * I.cols + ((c == I.cols - 1) ? 0 : c + 1),
-                           ((r == I.rows - 1) ? 0 : r + 1) * I.cols + c, r * I.cols + ((c == 0) ? I.cols - 1 : c - 1)};
+        const int rn = (r == 0) ? I.rows - 1 : r - 1, rs = (r == I.rows - 1) ? 0 : r + 1;
+        const int ce = (c == I.cols - 1) ? 0 : c + 1, cw = (c == 0) ? I.cols - 1 : c - 1;
+        const int nb[5] = {slot, rn * I.cols + c, r * I.cols + ce, rs * I.cols + c, r * I.cols + cw};
+        // buffer of each neighbour: the new generation's for the cells a line
+        // sweep has already updated (lower diagonal), else the previous one
+        const int nd[5] = {r + c, rn + c, r + ce, rs + c, r + cw};
+        int buf[5];
         long long v[5];
 #pragma unroll
-        for (int q = 0; q < 5; ++q) v[q] = ob[nb[q]];
+        for (int q = 0; q < 5; ++q) {
+            buf[q] = (mode == 2 && q > 0 && nd[q] < diag) ? nxt : cur;
+            v[q] = d.obj[buf[q]][rowbase + nb[q]];
+        }
         // the two best by (objective, neighbourhood order)
-        int b = 0, p1 = nb[0];
+        int b = 0, p1 = nb[0], b1 = buf[0];
         long long bv = v[0];
 #pragma unroll
         for (int q = 1; q < 5; ++q)
@@ -456,8 +493,9 @@ __global__ void __launch_bounds__(256) k_tt_generation(TtDesc d, int gen, int mo
                 bv = v[q];
                 b = q;
                 p1 = nb[q];
+                b1 = buf[q];
             }
-        int s2 = -1, p2 = nb[0];
+        int s2 = -1, p2 = nb[0], b2 = buf[0];
         long long sv = 0;
 #pragma unroll
         for (int q = 0; q < 5; ++q)
@@ -465,14 +503,15 @@ __global__ void __launch_bounds__(256) k_tt_generation(TtDesc d, int gen, int mo
                 sv = v[q];
                 s2 = q;
                 p2 = nb[q];
+                b2 = buf[q];
             }
         const Block4 bk = stream_block(d.seed, (uint64_t)run, (uint32_t)isl, (uint32_t)slot, 0, (uint32_t)gen,
                                        flowshop::kCell, 0);
         const bool cx = (unsigned long long)draw32(bk, 0) < I.tc;
         const int u = (int)below(draw32(bk, 1), (uint32_t)L), v2 = (int)below(draw32(bk, 2), (uint32_t)L);
         const int a = u < v2 ? u : v2, e = u < v2 ? v2 : u;
-        const uint8_t* P1 = d.genes[cur] + (rowbase + p1) * Lp;
-        const uint8_t* P2 = d.genes[cur] + (rowbase + p2) * Lp;
+        const uint8_t* P1 = d.genes[b1] + (rowbase + p1) * Lp;
+        const uint8_t* P2 = d.genes[b2] + (rowbase + p2) * Lp;
         for (int i0 = lane * 16; i0 < Lp; i0 += 64 * 16) {
             const uint4 x1 = *reinterpret_cast<const uint4*>(P1 + i0);
             const uint4 x2 = *reinterpret_cast<const uint4*>(P2 + i0);
@@ -549,7 +588,7 @@ __global__ void __launch_bounds__(256) k_tt_generation(TtDesc d, int gen, int mo
     uint8_t* dst = d.genes[nxt] + (rowbase + slot) * Lp;
     long long onew = o;
     const uint8_t* srow = child;
-    if (mode == 0 && I.kind == 0) {
+    if (mode != 1 && I.kind == 0) {
         const long long oold = d.obj[cur][rowbase + slot];
         if (!(o < oold)) {
             onew = oold;
@@ -733,6 +772,7 @@ struct ffs_tt_ctx {
     bool bound = false;
     int gen = 0;
     TtDesc desc{};
+    int sweep = 0;   // cellular update: 0 synchronous, 1 line sweep
     int wpb = 4;
     int kmax = 16;   // positions per lane bound of the decode (8 when J <= 512)
     size_t lds_gen = 0;
@@ -809,10 +849,25 @@ int check_ready(ffs_tt_ctx* c)
     return FFS_OK;
 }
 
+int launch_one(ffs_tt_ctx* c, int gen, int mode, int sel, int diag, int count, long long waves)
+{
+    if (waves <= 0) return FFS_OK;
+    const unsigned blocks = (unsigned)((waves + c->wpb - 1) / c->wpb);
+    if (c->kmax == 8)
+        hipLaunchKernelGGL(k_tt_generation<8>, dim3(blocks), dim3(64 * c->wpb), c->lds_gen, c->stream, c->desc, gen,
+                           mode, sel, diag, count);
+    else
+        hipLaunchKernelGGL(k_tt_generation<16>, dim3(blocks), dim3(64 * c->wpb), c->lds_gen, c->stream, c->desc, gen,
+                           mode, sel, diag, count);
+    TT_HIP(c, hipGetLastError());
+    return FFS_OK;
+}
+
+// One generation (mode 1: generation 0; mode 0: a step, synchronous or as a
+// line sweep: the pseudo islands in one launch, then every cellular island
+// one anti-diagonal per launch), then the best-ever fold.
 int launch_gen(ffs_tt_ctx* c, int gen, int mode)
 {
-    const long long waves = (long long)c->runs * c->desc.N;
-    const unsigned blocks = (unsigned)((waves + c->wpb - 1) / c->wpb);
     hipEvent_t e0 = nullptr, e1 = nullptr;
     if (c->timing) {
         while (c->ev.size() < c->ev_used + 2) {
@@ -824,13 +879,25 @@ int launch_gen(ffs_tt_ctx* c, int gen, int mode)
         e1 = c->ev[c->ev_used++];
         TT_HIP(c, hipEventRecord(e0, c->stream));
     }
-    if (c->kmax == 8)
-        hipLaunchKernelGGL(k_tt_generation<8>, dim3(blocks), dim3(64 * c->wpb), c->lds_gen, c->stream, c->desc, gen,
-                           mode);
-    else
-        hipLaunchKernelGGL(k_tt_generation<16>, dim3(blocks), dim3(64 * c->wpb), c->lds_gen, c->stream, c->desc, gen,
-                           mode);
-    TT_HIP(c, hipGetLastError());
+    int rc = FFS_OK;
+    const TtDesc& d = c->desc;
+    if (mode == 1 || !c->sweep) {
+        rc = launch_one(c, gen, mode, 0, 0, 0, (long long)c->runs * d.N);
+    } else {
+        int np = 0;
+        for (int i = 0; i < d.n_isl; ++i)
+            if (d.isl[i].kind == 1) np += d.isl[i].size;
+        rc = launch_one(c, gen, 3, 0, 0, np, (long long)c->runs * np);
+        for (int i = 0; i < d.n_isl && rc == FFS_OK; ++i) {
+            if (d.isl[i].kind != 0) continue;
+            const int rows = d.isl[i].rows, cols = d.isl[i].cols;
+            for (int g = 0; g <= rows + cols - 2 && rc == FFS_OK; ++g) {
+                const int rlo = std::max(0, g - (cols - 1)), rhi = std::min(rows - 1, g);
+                rc = launch_one(c, gen, 2, i, g, rhi - rlo + 1, (long long)c->runs * (rhi - rlo + 1));
+            }
+        }
+    }
+    if (rc != FFS_OK) return rc;
     if (c->timing) TT_HIP(c, hipEventRecord(e1, c->stream));
     hipLaunchKernelGGL(k_tt_fold, dim3((unsigned)((c->runs + 63) / 64)), dim3(64), 0, c->stream, c->desc, gen);
     TT_HIP(c, hipGetLastError());
@@ -1237,6 +1304,14 @@ int ffs_tt_evaluate(ffs_tt_ctx* c, const void* genes, int32_t count, void* out)
         hipLaunchKernelGGL(k_tt_evaluate<16>, dim3(blocks), dim3(64 * c->wpb), c->lds_gen, c->stream, c->desc,
                            reinterpret_cast<const uint8_t*>(genes), count, reinterpret_cast<long long*>(out));
     TT_HIP(c, hipGetLastError());
+    return FFS_OK;
+}
+
+int ffs_tt_set_update(ffs_tt_ctx* c, int32_t mode)
+{
+    if (!c) return FFS_EINVAL;
+    if (mode != 0 && mode != 1) return fail(c, FFS_EINVAL, "update mode %d", mode);
+    c->sweep = mode;
     return FFS_OK;
 }
 

@@ -15,6 +15,7 @@ TT_EXPORTS = [
     "ffs_tt_configure", "ffs_tt_workspace_size", "ffs_tt_bind_workspace", "ffs_tt_evolve", "ffs_tt_migrate",
     "ffs_tt_generation", "ffs_tt_get_population", "ffs_tt_set_population", "ffs_tt_set_generation",
     "ffs_tt_best", "ffs_tt_counters", "ffs_tt_evaluate", "ffs_tt_set_timing", "ffs_tt_kernel_time",
+    "ffs_tt_set_update",
 ]
 
 _ready = False
@@ -47,6 +48,7 @@ def load():
     lib.ffs_tt_counters.argtypes = [P, i32, pi64, pi64]
     lib.ffs_tt_evaluate.argtypes = [P, P, i32, P]
     lib.ffs_tt_set_timing.argtypes = [P, i32]
+    lib.ffs_tt_set_update.argtypes = [P, i32]
     lib.ffs_tt_kernel_time.argtypes = [P, ctypes.POINTER(ctypes.c_double), pi64]
     _ready = True
     return lib
@@ -70,7 +72,7 @@ class TtContext:
     (run r uses instance id r in its random streams)."""
 
     def __init__(self, inst: dict, islands, interval: int = 500, theta: float = 1.0, seed: int = 101,
-                 runs: int = 1, device: int = 0, stream=None):
+                 runs: int = 1, device: int = 0, stream=None, sweep: bool = False):
         import torch
         self._torch = torch
         self.lib = load()
@@ -97,6 +99,7 @@ class TtContext:
             self.sizes.append(int(isl["size"]))
         self.runs = runs
         self._check(self.lib.ffs_tt_configure(self._h, int(interval), float(theta), int(seed), int(runs)))
+        self._check(self.lib.ffs_tt_set_update(self._h, 1 if sweep else 0))
         b = ctypes.c_size_t()
         self._check(self.lib.ffs_tt_workspace_size(self._h, ctypes.byref(b)))
         nbytes = int(b.value)

@@ -168,3 +168,45 @@ def test_state_loaded_from_the_oracle():
     ga.evolve(8)
     _same(ctx, ga, 0, 2, "after 8 generations")
     ctx.close()
+
+
+@pytest.mark.parametrize("runs", [1, 2])
+def test_line_sweep_trajectory(runs):
+    """The asynchronous line-sweep update (one launch per anti-diagonal) on a
+    6x5 cellular island beside a pseudo island, with migration, then a switch
+    back to the synchronous update; every chunk bit-exact."""
+    ensure_built()
+    inst = inputs.tardiness_instance(24, 3, [2, 3, 2], seed=17)
+    isl = [inputs.cellular(6, 5, 1.0, 0.1), inputs.pseudo(30, 0.75, 0.05)]
+    say(f"[tt] line sweep runs={runs}")
+    from paper_1903_10722_amd.tardiness import TtContext
+    ctx = TtContext(inst, isl, interval=4, theta=1.0, seed=23, runs=runs, sweep=True)
+    gas = [ot.GA(inst, isl, interval=4, seed=23, inst_id=r, sweep=True) for r in range(runs)]
+    for chunk in (1, 3, 4, 6):
+        ctx.evolve(chunk)
+        for r, ga in enumerate(gas):
+            ga.evolve(chunk)
+            _same(ctx, ga, r, 2, f"run {r} sweep generation {ga.generation}")
+            assert ctx.best(r)["objective"] == ga.best()["objective"]
+    ctx.lib.ffs_tt_set_update(ctx._h, 0)
+    for ga in gas:
+        ga._lib.or_tt_ga_set_update(ga._h, 0)
+    ctx.evolve(3)
+    for r, ga in enumerate(gas):
+        ga.evolve(3)
+        _same(ctx, ga, r, 2, f"run {r} synchronous again")
+    ctx.close()
+
+
+def test_line_sweep_section5_size():
+    ensure_built()
+    w = inputs.tardiness_setting("dual", seed=1)
+    say("[tt] line sweep at section-5 size")
+    from paper_1903_10722_amd.tardiness import TtContext
+    ctx = TtContext(w["inst"], w["islands"], interval=10, seed=3, sweep=True)
+    ga = ot.GA(w["inst"], w["islands"], interval=10, seed=3, sweep=True)
+    for g in (5, 7):
+        ctx.evolve(g)
+        ga.evolve(g)
+        _same(ctx, ga, 0, 2, f"generation {ga.generation}")
+    ctx.close()

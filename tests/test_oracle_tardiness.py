@@ -181,3 +181,34 @@ def test_ga_migration_moves_best_into_worst():
     for r in range(count):
         assert dst_o2[worst[r]] == src_o[best[r]]
     assert ga.counters() == ((1, count) if count else (0, 0))
+
+
+def test_line_sweep_spreads_the_best_in_one_generation():
+    """With no crossover and no mutation a child copies its better parent.
+    A unique best cell at the start of the sweep then reaches every cell of
+    the torus in one line-sweep generation (each cell already sees its
+    updated north or west neighbour); the synchronous update reaches only the
+    cell's von Neumann neighbours."""
+    inst = inputs.tardiness_instance(6, 2, [2, 2], seed=1)
+    rows, cols = 5, 4
+    isl = [inputs.cellular(rows, cols, 0.0, 0.0)]
+    rng = np.random.default_rng(4)
+    while True:
+        genes = rng.integers(0, 2, size=(rows * cols, 12)).astype(np.int32)
+        obj = np.array([tt.decode(inst, x)[0] for x in genes], dtype=np.int64)
+        best = int(np.argmin(obj))
+        if (obj == obj[best]).sum() == 1:
+            break
+    # the unique best at the sweep's first cell
+    genes[[0, best]] = genes[[best, 0]]
+    obj[[0, best]] = obj[[best, 0]]
+    vmin = int(obj[0])
+    for sweep, want_best in ((True, set(range(rows * cols))), (False, {0, 1, cols - 1, cols, (rows - 1) * cols})):
+        ga = tt.GA(inst, isl, interval=0, seed=3, sweep=sweep)
+        ga.set_population(0, genes, obj)
+        ga.evolve(1)
+        g, o = ga.population(0)
+        got = {s for s in range(rows * cols) if o[s] == vmin}
+        assert got == want_best, (sweep, sorted(got))
+        for s in got:
+            assert np.array_equal(g[s], genes[0])
