@@ -52,6 +52,12 @@ def test_library_loads_and_reports_errors_without_device(lib_path):
     # argument checks that need no device
     assert lib.ffs_ctx_create(None, None) == binding.FFS_EINVAL
     assert lib.ffs_last_error(None) == b"null context"
+    from paper_1903_10722_amd import tardiness
+    tl = tardiness.load()
+    assert tl.ffs_tt_create(None, None) == binding.FFS_EINVAL
+    assert tl.ffs_tt_last_error(None) == b"null context"
+    assert tl.ffs_tt_evolve(None, 1) == binding.FFS_EINVAL
+    assert tl.ffs_tt_set_update(None, 1) == binding.FFS_EINVAL
 
 
 def test_oracle_and_library_share_no_code():

@@ -210,3 +210,39 @@ def test_line_sweep_section5_size():
         ga.evolve(g)
         _same(ctx, ga, 0, 2, f"generation {ga.generation}")
     ctx.close()
+
+
+def test_argument_errors_are_reported():
+    """Invalid instances, islands and call orders give the documented status
+    and leave the context usable."""
+    ensure_built()
+    import ctypes
+    from paper_1903_10722_amd import binding
+    from paper_1903_10722_amd.tardiness import load
+    lib = load()
+    h = ctypes.c_void_p()
+    assert lib.ffs_tt_create(None, ctypes.byref(h)) == binding.FFS_OK
+    i32p = ctypes.POINTER(ctypes.c_int32)
+    i64p = ctypes.POINTER(ctypes.c_int64)
+
+    def inst_rc(J, S, M, MX, P, R, D, WT=100):
+        M, P, R = (np.ascontiguousarray(x, dtype=np.int32) for x in (M, P, R))
+        D = np.ascontiguousarray(D, dtype=np.int64)
+        return lib.ffs_tt_set_instance(h, J, S, M.ctypes.data_as(i32p), MX, P.ctypes.data_as(i32p),
+                                       R.ctypes.data_as(i32p), D.ctypes.data_as(i64p), WT)
+
+    good = inputs.tardiness_instance(5, 2, [2, 1], seed=1)
+    P = good["P"].copy()
+    P[0, 0, 1] = 0
+    assert inst_rc(5, 2, good["M"], 2, P, good["R"], good["D"]) == binding.FFS_EINVAL           # p < 1
+    assert inst_rc(5, 2, [2, 1], 3, np.ones((5, 2, 3)), good["R"], good["D"]) == binding.FFS_EINVAL   # MX != max M
+    assert inst_rc(1100, 1, [1], 1, np.ones((1100, 1, 1)), np.zeros(1100), np.zeros(1100)) == binding.FFS_EUNSUPPORTED
+    assert inst_rc(5, 2, good["M"], 2, good["P"], good["R"], good["D"]) == binding.FFS_OK
+    odd = binding.IslandSpec(1, 0, 0, 7, 0.75, 0.0, 0)
+    assert lib.ffs_tt_add_island(h, ctypes.byref(odd)) == binding.FFS_EINVAL                      # odd pseudo size
+    sel = binding.IslandSpec(0, 4, 4, 16, 1.0, 0.05, 2)
+    assert lib.ffs_tt_add_island(h, ctypes.byref(sel)) == binding.FFS_EINVAL                      # selection != 0
+    assert lib.ffs_tt_evolve(h, 1) == binding.FFS_ESTATE                                          # before bind
+    assert lib.ffs_tt_set_update(h, 2) == binding.FFS_EINVAL
+    assert b"update mode" in lib.ffs_tt_last_error(h)
+    assert lib.ffs_tt_destroy(h) == binding.FFS_OK
