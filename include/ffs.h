@@ -45,7 +45,7 @@ enum {
     FFS_ENOMEM = -2,        /* the bound workspace is too small                 */
     FFS_EDEVICE = -3,       /* a HIP call failed or a kernel reported a fault   */
     FFS_ESTATE = -4,        /* call out of order (e.g. evolve before bind)      */
-    FFS_EUNSUPPORTED = -5   /* valid problem outside this build's limits        */
+    FFS_EUNSUPPORTED = -5   /* valid problem outside this library's limits        */
 };
 
 /* One island.  Paper Section 4.1: island A runs the cellular GA, island B the
@@ -66,7 +66,7 @@ enum {
  *   kind 1 (pseudo): `size` individuals (even, >= 2) in fixed pairs; each pair
  *          mates its better member with that member's complement (the
  *          reversed permutation) and both children replace the pair.
- * Island sizes are limited to 16384 individuals in this build.             */
+ * Island sizes are limited to 16384 individuals in this library.             */
 typedef struct {
     int32_t kind;
     int32_t rows, cols;   /* kind 0 */
@@ -121,7 +121,7 @@ const char *ffs_last_error(const ffs_ctx *ctx);
  *   p[n_jobs * n_stages], job-major (p[j * n_stages + s]), each in [1, 65535];
  *   islands[n_islands], n_islands even >= 2 (or 1 with no migration);
  *   seed: the random stream key together with the instance id.
- * Limits of this build: n_jobs <= 4096, and the packed schedule key
+ * Limits of this library: n_jobs <= 4096, and the packed schedule key
  * needs sum(p) < 2^(32 - ceil(log2 n_jobs)) - 1 (FFS_EUNSUPPORTED otherwise).
  * Must be called before ffs_bind_workspace.  *out_instance_id = 0, 1, ...  */
 int ffs_create_instance(ffs_ctx *ctx, int32_t n_jobs, int32_t n_stages,

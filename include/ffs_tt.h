@@ -52,7 +52,7 @@ extern "C" {
 
 typedef struct ffs_tt_ctx ffs_tt_ctx;
 
-/* Limits of this build: J <= 1024, S <= 32, M_s <= 4, WT >= 0, islands <= 8,
+/* Limits of this library: J <= 1024, S <= 32, M_s <= 4, WT >= 0, islands <= 8,
  * island size <= 4096 (even for pseudo islands), runs <= 1024, every time
  * and H_t below 2^30, E_max below 2^39.  Violations give FFS_EUNSUPPORTED. */
 

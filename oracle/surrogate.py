@@ -17,7 +17,7 @@ What it computes:
 
 The pre-screen itself is not in the paper: it ranks candidate children of a
 cellular cell (Section 4.2's one-child-per-cell step) so that only the best
-candidate is decoded exactly; the decode stays the judge of every makespan.
+candidate is decoded exactly; the exact decode decides every makespan.
 """
 from __future__ import annotations
 

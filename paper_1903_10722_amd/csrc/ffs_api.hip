@@ -687,7 +687,7 @@ int ffs_create_instance(ffs_ctx* c, int32_t n, int32_t S, const int32_t* machine
     if (!machines || !p || !islands || !cfg || !out_id) return fail(c, FFS_EINVAL, "null argument");
     if (n < 1) return fail(c, FFS_EINVAL, "n_jobs must be >= 1");
     if (S < 1 || S > kMaxStages) return fail(c, FFS_EINVAL, "n_stages must be in [1, %d]", kMaxStages);
-    if (n > 4096) return fail(c, FFS_EUNSUPPORTED, "n_jobs above 4096 is outside this build's limits");
+    if (n > 4096) return fail(c, FFS_EUNSUPPORTED, "n_jobs above 4096 is outside this library's limits");
     if (n_islands < 1) return fail(c, FFS_EINVAL, "need at least one island");
     if (n_islands > 1 && (n_islands % 2) != 0) return fail(c, FFS_EINVAL, "island count must be even (pairs)");
     if (cfg->migration_interval < 0) return fail(c, FFS_EINVAL, "migration_interval must be >= 0");
