@@ -246,3 +246,21 @@ def test_argument_errors_are_reported():
     assert lib.ffs_tt_set_update(h, 2) == binding.FFS_EINVAL
     assert b"update mode" in lib.ffs_tt_last_error(h)
     assert lib.ffs_tt_destroy(h) == binding.FFS_OK
+
+
+def test_trajectory_above_512_jobs():
+    """More than 512 jobs: the decode's 16-positions-per-lane instantiation
+    inside the generation kernel, with migration and the line sweep."""
+    ensure_built()
+    inst = inputs.tardiness_instance(600, 2, [2, 3], seed=29)
+    isl = [inputs.cellular(4, 4, 1.0, 0.1), inputs.pseudo(16, 0.75, 0.05)]
+    say("[tt] J=600 trajectory")
+    from paper_1903_10722_amd.tardiness import TtContext
+    for sweep in (False, True):
+        ctx = TtContext(inst, isl, interval=3, seed=41, sweep=sweep)
+        ga = ot.GA(inst, isl, interval=3, seed=41, sweep=sweep)
+        _same(ctx, ga, 0, 2, f"sweep={sweep} generation 0")
+        ctx.evolve(4)
+        ga.evolve(4)
+        _same(ctx, ga, 0, 2, f"sweep={sweep} generation 4")
+        ctx.close()
