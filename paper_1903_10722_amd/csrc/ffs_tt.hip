@@ -196,7 +196,7 @@ __device__ __forceinline__ int from_lane_below(int x, int first)
 // the whole wave; -1 if a gene is out of range.  Work arrays in LDS:
 // ord/rdy (two buffers each, Jp entries) and keys (Jp entries).  A lane owns
 // K = ceil(J / 64) <= KMAX consecutive positions.
-template <int KMAX>
+template <int KMAX, int MMX>
 __device__ long long decode_wave(const TtDesc& d, const Smem& sm, const uint8_t* child, uint16_t* ordA,
                                  uint16_t* ordB, int* rdyA, int* rdyB, unsigned long long* keys, int lane)
 {
@@ -218,9 +218,9 @@ __device__ long long decode_wave(const TtDesc& d, const Smem& sm, const uint8_t*
     for (int s = 0; s < S; ++s) {
         const int Ms = sm.M[s];
         int mloc[KMAX], rloc[KMAX], ploc[KMAX];
-        int A[kMaxM], B[kMaxM], cnt[kMaxM];
+        int A[MMX], B[MMX], cnt[MMX];
 #pragma unroll
-        for (int m = 0; m < kMaxM; ++m) {
+        for (int m = 0; m < MMX; ++m) {
             A[m] = kNeg;
             B[m] = 0;
             cnt[m] = 0;
@@ -244,7 +244,7 @@ __device__ long long decode_wave(const TtDesc& d, const Smem& sm, const uint8_t*
                 rloc[u] = r;
                 ploc[u] = p;
 #pragma unroll
-                for (int mm = 0; mm < kMaxM; ++mm)
+                for (int mm = 0; mm < MMX; ++mm)
                     if (mm == m) {
                         const int a2 = r - B[mm];
                         A[mm] = A[mm] > a2 ? A[mm] : a2;
@@ -254,10 +254,10 @@ __device__ long long decode_wave(const TtDesc& d, const Smem& sm, const uint8_t*
             }
         }
         // across lanes: exclusive prefix of every machine's (A, B) and count
-        int off[kMaxM], tot[kMaxM];
+        int off[MMX], tot[MMX];
         int run_off = 0;
 #pragma unroll
-        for (int m = 0; m < kMaxM; ++m) {
+        for (int m = 0; m < MMX; ++m) {
             off[m] = run_off;
             tot[m] = 0;
             if (m < Ms) {   // the stage's machines only (uniform)
@@ -279,7 +279,7 @@ __device__ long long decode_wave(const TtDesc& d, const Smem& sm, const uint8_t*
                 const int m = mloc[u];
                 int c = 0, idx = 0, base = 0;
 #pragma unroll
-                for (int mm = 0; mm < kMaxM; ++mm)
+                for (int mm = 0; mm < MMX; ++mm)
                     if (mm == m) {
                         const int a2 = rloc[u] - B[mm];
                         A[mm] = A[mm] > a2 ? A[mm] : a2;
@@ -313,7 +313,7 @@ __device__ long long decode_wave(const TtDesc& d, const Smem& sm, const uint8_t*
                 om = om >= Ms ? om - Ms : om;
                 int ob = 0, on = 0;
 #pragma unroll
-                for (int mm = 0; mm < kMaxM; ++mm)
+                for (int mm = 0; mm < MMX; ++mm)
                     if (mm == om) {
                         ob = off[mm];
                         on = tot[mm];
@@ -407,7 +407,7 @@ extern __shared__ __align__(16) unsigned char tt_smem[];
 //           new generation's buffer then and from the previous one otherwise;
 //           the diagonals run in order, one launch each;
 //   mode 3: the individuals of the pseudo islands only (`count` per run).
-template <int KMAX>
+template <int KMAX, int MMX>
 __global__ void __launch_bounds__(256) k_tt_generation(TtDesc d, int gen, int mode, int sel, int diag, int count)
 {
     const Smem sm = smem_tables(tt_smem, d.J, d.S, d.MX);
@@ -583,7 +583,7 @@ __global__ void __launch_bounds__(256) k_tt_generation(TtDesc d, int gen, int mo
         }
     }
     wave_sync();
-    const long long o = decode_wave<KMAX>(d, sm, child, w.ordA, w.ordB, w.rdyA, w.rdyB, w.keys, lane);
+    const long long o = decode_wave<KMAX, MMX>(d, sm, child, w.ordA, w.ordB, w.rdyA, w.rdyB, w.keys, lane);
     // replacement (cellular: only if strictly better) and write-out
     uint8_t* dst = d.genes[nxt] + (rowbase + slot) * Lp;
     long long onew = o;
@@ -726,7 +726,7 @@ __global__ void __launch_bounds__(kSortThreads) k_tt_migrate(TtDesc d, int gen)
 }
 
 // Objectives of caller-supplied assignments (count rows of L genes).
-template <int KMAX>
+template <int KMAX, int MMX>
 __global__ void __launch_bounds__(256) k_tt_evaluate(TtDesc d, const uint8_t* genes, int count, long long* out)
 {
     const Smem sm = smem_tables(tt_smem, d.J, d.S, d.MX);
@@ -739,7 +739,7 @@ __global__ void __launch_bounds__(256) k_tt_evaluate(TtDesc d, const uint8_t* ge
     const uint8_t* src = genes + row * d.L;
     for (int i = lane; i < d.L; i += 64) w.child[i] = src[i];
     wave_sync();
-    const long long o = decode_wave<KMAX>(d, sm, w.child, w.ordA, w.ordB, w.rdyA, w.rdyB, w.keys, lane);
+    const long long o = decode_wave<KMAX, MMX>(d, sm, w.child, w.ordA, w.ordB, w.rdyA, w.rdyB, w.keys, lane);
     if (lane == 0) out[row] = o;
 }
 
@@ -775,6 +775,7 @@ struct ffs_tt_ctx {
     int sweep = 0;   // cellular update: 0 synchronous, 1 line sweep
     int wpb = 4;
     int kmax = 16;   // positions per lane bound of the decode (8 when J <= 512)
+    int mmx = 4;     // machines per stage bound of the decode (2 when every M_s <= 2)
     size_t lds_gen = 0;
     // timing
     bool timing = false;
@@ -853,11 +854,18 @@ int launch_one(ffs_tt_ctx* c, int gen, int mode, int sel, int diag, int count, l
 {
     if (waves <= 0) return FFS_OK;
     const unsigned blocks = (unsigned)((waves + c->wpb - 1) / c->wpb);
-    if (c->kmax == 8)
-        hipLaunchKernelGGL(k_tt_generation<8>, dim3(blocks), dim3(64 * c->wpb), c->lds_gen, c->stream, c->desc, gen,
+    const TtDesc& d = c->desc;
+    if (c->kmax == 8 && c->mmx == 2)
+        hipLaunchKernelGGL((k_tt_generation<8, 2>), dim3(blocks), dim3(64 * c->wpb), c->lds_gen, c->stream, d, gen,
+                           mode, sel, diag, count);
+    else if (c->kmax == 8)
+        hipLaunchKernelGGL((k_tt_generation<8, 4>), dim3(blocks), dim3(64 * c->wpb), c->lds_gen, c->stream, d, gen,
+                           mode, sel, diag, count);
+    else if (c->mmx == 2)
+        hipLaunchKernelGGL((k_tt_generation<16, 2>), dim3(blocks), dim3(64 * c->wpb), c->lds_gen, c->stream, d, gen,
                            mode, sel, diag, count);
     else
-        hipLaunchKernelGGL(k_tt_generation<16>, dim3(blocks), dim3(64 * c->wpb), c->lds_gen, c->stream, c->desc, gen,
+        hipLaunchKernelGGL((k_tt_generation<16, 4>), dim3(blocks), dim3(64 * c->wpb), c->lds_gen, c->stream, d, gen,
                            mode, sel, diag, count);
     TT_HIP(c, hipGetLastError());
     return FFS_OK;
@@ -1071,12 +1079,18 @@ int ffs_tt_bind_workspace(ffs_tt_ctx* c, void* ptr, size_t bytes)
     c->wpb = wpb;
     c->lds_gen = tb + wpb * wb;
     c->kmax = (c->J <= 512) ? 8 : 16;
-    const void* kg = c->kmax == 8 ? reinterpret_cast<const void*>(&k_tt_generation<8>)
-                                  : reinterpret_cast<const void*>(&k_tt_generation<16>);
-    const void* ke = c->kmax == 8 ? reinterpret_cast<const void*>(&k_tt_evaluate<8>)
-                                  : reinterpret_cast<const void*>(&k_tt_evaluate<16>);
-    TT_HIP(c, hipFuncSetAttribute(kg, hipFuncAttributeMaxDynamicSharedMemorySize, (int)c->lds_gen));
-    TT_HIP(c, hipFuncSetAttribute(ke, hipFuncAttributeMaxDynamicSharedMemorySize, (int)c->lds_gen));
+    c->mmx = (c->MX <= 2) ? 2 : 4;
+    const void* kg[4] = {reinterpret_cast<const void*>(&k_tt_generation<8, 2>),
+                         reinterpret_cast<const void*>(&k_tt_generation<8, 4>),
+                         reinterpret_cast<const void*>(&k_tt_generation<16, 2>),
+                         reinterpret_cast<const void*>(&k_tt_generation<16, 4>)};
+    const void* ke[4] = {reinterpret_cast<const void*>(&k_tt_evaluate<8, 2>),
+                         reinterpret_cast<const void*>(&k_tt_evaluate<8, 4>),
+                         reinterpret_cast<const void*>(&k_tt_evaluate<16, 2>),
+                         reinterpret_cast<const void*>(&k_tt_evaluate<16, 4>)};
+    const int kv = (c->kmax == 8 ? 0 : 2) + (c->mmx == 2 ? 0 : 1);
+    TT_HIP(c, hipFuncSetAttribute(kg[kv], hipFuncAttributeMaxDynamicSharedMemorySize, (int)c->lds_gen));
+    TT_HIP(c, hipFuncSetAttribute(ke[kv], hipFuncAttributeMaxDynamicSharedMemorySize, (int)c->lds_gen));
     TT_HIP(c, hipFuncSetAttribute(reinterpret_cast<const void*>(&k_tt_migrate),
                                   hipFuncAttributeMaxDynamicSharedMemorySize, 2 * kMaxIslSize * 8));
     c->ws = reinterpret_cast<char*>(ptr);
@@ -1297,12 +1311,20 @@ int ffs_tt_evaluate(ffs_tt_ctx* c, const void* genes, int32_t count, void* out)
     if (count < 0 || (count > 0 && (!genes || !out))) return fail(c, FFS_EINVAL, "count %d", count);
     if (count == 0) return FFS_OK;
     const unsigned blocks = (unsigned)((count + c->wpb - 1) / c->wpb);
-    if (c->kmax == 8)
-        hipLaunchKernelGGL(k_tt_evaluate<8>, dim3(blocks), dim3(64 * c->wpb), c->lds_gen, c->stream, c->desc,
-                           reinterpret_cast<const uint8_t*>(genes), count, reinterpret_cast<long long*>(out));
+    const uint8_t* g = reinterpret_cast<const uint8_t*>(genes);
+    long long* o = reinterpret_cast<long long*>(out);
+    if (c->kmax == 8 && c->mmx == 2)
+        hipLaunchKernelGGL((k_tt_evaluate<8, 2>), dim3(blocks), dim3(64 * c->wpb), c->lds_gen, c->stream, c->desc, g,
+                           count, o);
+    else if (c->kmax == 8)
+        hipLaunchKernelGGL((k_tt_evaluate<8, 4>), dim3(blocks), dim3(64 * c->wpb), c->lds_gen, c->stream, c->desc, g,
+                           count, o);
+    else if (c->mmx == 2)
+        hipLaunchKernelGGL((k_tt_evaluate<16, 2>), dim3(blocks), dim3(64 * c->wpb), c->lds_gen, c->stream, c->desc, g,
+                           count, o);
     else
-        hipLaunchKernelGGL(k_tt_evaluate<16>, dim3(blocks), dim3(64 * c->wpb), c->lds_gen, c->stream, c->desc,
-                           reinterpret_cast<const uint8_t*>(genes), count, reinterpret_cast<long long*>(out));
+        hipLaunchKernelGGL((k_tt_evaluate<16, 4>), dim3(blocks), dim3(64 * c->wpb), c->lds_gen, c->stream, c->desc, g,
+                           count, o);
     TT_HIP(c, hipGetLastError());
     return FFS_OK;
 }

@@ -248,11 +248,13 @@ def test_argument_errors_are_reported():
     assert lib.ffs_tt_destroy(h) == binding.FFS_OK
 
 
-def test_trajectory_above_512_jobs():
-    """More than 512 jobs: the decode's 16-positions-per-lane instantiation
-    inside the generation kernel, with migration and the line sweep."""
+@pytest.mark.parametrize("machines", [[2, 3], [2, 2]])
+def test_trajectory_above_512_jobs(machines):
+    """More than 512 jobs: the decode's 16-positions-per-lane instantiations
+    (up to 4 and up to 2 machines per stage) inside the generation kernel,
+    with migration and the line sweep."""
     ensure_built()
-    inst = inputs.tardiness_instance(600, 2, [2, 3], seed=29)
+    inst = inputs.tardiness_instance(600, 2, machines, seed=29)
     isl = [inputs.cellular(4, 4, 1.0, 0.1), inputs.pseudo(16, 0.75, 0.05)]
     say("[tt] J=600 trajectory")
     from paper_1903_10722_amd.tardiness import TtContext
