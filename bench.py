@@ -245,7 +245,8 @@ def tardiness_experiment(runs: int, generations: int) -> dict:
     Table 2's comparison of the heterogeneous GA (16x16 cellular + pseudo
     256, migration gap 500) with a cellular GA (16x32) and a pseudo GA (512),
     Fig. 4's gap sweep of the heterogeneous GA, and the asynchronous
-    line-sweep update of the cellular islands (an alternative reading).  `runs` seeds run as the
+    line-sweep update of the cellular islands (an alternative reading); all
+    of it again on a loaded shop whose releases span an eighth of the range.  `runs` seeds run as the
     batched runs of one context per configuration; objectives are reported in
     time units (the library works in hundredths)."""
     import numpy as np
@@ -253,13 +254,18 @@ def tardiness_experiment(runs: int, generations: int) -> dict:
 
     from paper_1903_10722_amd import inputs
     from paper_1903_10722_amd.tardiness import TtContext
-    configs = [(v, 500, False) for v in ("dual", "cellular", "pseudo")] + \
-              [("dual", g, False) for g in (10, 50, 100, 200, 800)] + \
-              [(v, 500, True) for v in ("dual", "cellular")]
+    # (layout, gap, line sweep, release scale): Table 1 read literally, then
+    # a loaded shop with the release range compressed by sum_s M_s = 8
+    configs = [(v, 500, False, 1.0) for v in ("dual", "cellular", "pseudo")] + \
+              [("dual", g, False, 1.0) for g in (10, 50, 100, 200, 800)] + \
+              [(v, 500, True, 1.0) for v in ("dual", "cellular")] + \
+              [(v, 500, False, 0.125) for v in ("dual", "cellular", "pseudo")] + \
+              [("dual", g, False, 0.125) for g in (10, 100, 800)] + \
+              [(v, 500, True, 0.125) for v in ("dual", "cellular")]
     checkpoints = [c for c in (100, 500, 1000) if c < generations] + [generations]
     rows, kernel = [], None
-    for variant, interval, sweep in configs:
-        w = inputs.tardiness_setting(variant, seed=1, interval=interval)
+    for variant, interval, sweep, rscale in configs:
+        w = inputs.tardiness_setting(variant, seed=1, interval=interval, release_scale=rscale)
         inst, isl = w["inst"], w["islands"]
         ctx = TtContext(inst, isl, interval=interval if len(isl) > 1 else 0, theta=w["theta"], seed=1000, runs=runs,
                         sweep=sweep)
@@ -295,6 +301,7 @@ def tardiness_experiment(runs: int, generations: int) -> dict:
         ctx.close()
         n_ind = sum(x["size"] for x in isl) * runs
         rows.append({"layout": variant, "cellular_update": "line sweep" if sweep else "synchronous",
+                     "release_scale": rscale,
                      "islands": [f"cellular {x['rows']}x{x['cols']}" if x["kind"] == 0 else f"pseudo {x['size']}"
                                  for x in isl],
                      "interval": interval if len(isl) > 1 else None,
@@ -303,8 +310,8 @@ def tardiness_experiment(runs: int, generations: int) -> dict:
                      "found_generation_mean": float(np.mean(found)), "curve": curve,
                      "ms_per_generation_all_runs": ms / generations,
                      "decodes_per_s": n_ind * generations / (ms / 1e3)})
-        print(f"[tardiness] {variant} gap={interval} sweep={sweep}: average {best.mean():.2f}", file=sys.stderr,
-              flush=True)
+        print(f"[tardiness] {variant} gap={interval} sweep={sweep} release_scale={rscale}: average "
+              f"{best.mean():.2f}", file=sys.stderr, flush=True)
     # the oracle on the heterogeneous layout, one run, about 5 s
     from oracle import tardiness as ot
     w = inputs.tardiness_setting("dual", seed=1, interval=500)

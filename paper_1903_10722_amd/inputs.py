@@ -170,13 +170,15 @@ WT_PAPER = 100
 
 
 def tardiness_instance(J: int = 300, S: int = 4, machines=None, seed: int = 1, wt: int = WT_PAPER,
-                       p_lo: int = 1, p_hi: int = 5) -> dict:
+                       p_lo: int = 1, p_hi: int = 5, release_scale: float = 1.0) -> dict:
     """Table 1's generator, every time in hundredths of a time unit:
     P[j][s][m] uniform integer in [p_lo, p_hi] (times 100), R_j uniform in
     [0, Pbar) with Pbar = sum_j sum_s (sum_m P_jsm / M_s), and
     D_j = R_j + Pbar_j (1 + sigma_j) with Pbar_j = sum_s (sum_m P_jsm / M_s)
     and sigma_j uniform in [0, 2]; R and D are floored to whole hundredths.
-    P is [J][S][MX] (MX = max M_s; unused machine slots hold 0)."""
+    P is [J][S][MX] (MX = max M_s; unused machine slots hold 0).
+    `release_scale` < 1 compresses the release range to [0, Pbar * scale): a
+    more loaded shop (an alternative reading of Table 1's R_j)."""
     M = np.asarray(machines if machines is not None else [2] * S, dtype=np.int32)
     assert M.shape == (S,) and (M >= 1).all()
     MX = int(M.max())
@@ -188,18 +190,18 @@ def tardiness_instance(J: int = 300, S: int = 4, machines=None, seed: int = 1, w
     for s in range(S):
         pbar_j += P[:, s, :M[s]].sum(axis=1) / float(M[s])     # hundredths
     pbar = float(pbar_j.sum())
-    R = np.floor(g.random(J) * pbar).astype(np.int32)
+    R = np.floor(g.random(J) * pbar * release_scale).astype(np.int32)
     sigma = g.random(J) * 2.0
     D = (R + np.floor(pbar_j * (1.0 + sigma))).astype(np.int64)
     return dict(J=J, S=S, M=M, P=P, R=R, D=D, WT=int(wt))
 
 
 def tardiness_setting(variant: str = "dual", seed: int = 1, interval: int = 500, J: int = 300,
-                      S: int = 4, side: int = 16) -> dict:
+                      S: int = 4, side: int = 16, release_scale: float = 1.0) -> dict:
     """Section 5's setting on the faithful variant: 300 jobs, 4 stages, 2
     unrelated machines per stage, a side x side cellular island (crossover
     1.00, mutation 0.05) and a pseudo island of side^2 (crossover 0.75)."""
-    inst = tardiness_instance(J, S, [2] * S, seed=seed)
+    inst = tardiness_instance(J, S, [2] * S, seed=seed, release_scale=release_scale)
     isl = _layout(variant, side, PAPER_CELL_RATES + (0,), PAPER_PAIR_RATES)
     return dict(name=f"tardiness:{variant}", inst=inst, islands=isl, generations=2000,
                 interval=interval, theta=1.0)
