@@ -192,6 +192,19 @@ __device__ __forceinline__ int from_lane_below(int x, int first)
     return __builtin_amdgcn_update_dpp(first, x, 0x138 /* wave_shr:1 */, 0xF, 0xF, false);
 }
 
+// Key of a position in its machine's list: ordered by (completion, position),
+// with the job in the low bits for whoever writes the merged order.
+__device__ __forceinline__ unsigned long long order_key(int c, int t, int j)
+{
+    return ((unsigned long long)(unsigned)c << 32) | ((unsigned)t << 16) | (unsigned)j;
+}
+
+// The largest power of two not above x (x >= 1).
+__device__ __forceinline__ int top_pow2(int x)
+{
+    return 1 << (31 - __builtin_clz((unsigned)x));
+}
+
 // The objective of the assignment in `child` (LDS, J*S genes), decoded by
 // the whole wave; -1 if a gene is out of range.  Work arrays in LDS:
 // ord/rdy (two buffers each, Jp entries) and keys (Jp entries).  A lane owns
@@ -271,7 +284,11 @@ __device__ long long decode_wave(const TtDesc& d, const Smem& sm, const uint8_t*
                 run_off += tot[m];
             }
         }
-        // completions, and each machine's list of (completion << 16 | position)
+        // completions; except at the last stage (whose order nobody reads),
+        // each machine's list of keys (completion << 32 | position << 16 |
+        // job), sorted by (completion, position): first in, first out on a
+        // machine, ties to the earlier position
+        const bool more = s + 1 < S;
         int own[KMAX];
 #pragma unroll
         for (int u = 0; u < KMAX; ++u) {
@@ -290,58 +307,95 @@ __device__ long long decode_wave(const TtDesc& d, const Smem& sm, const uint8_t*
                     }
                 cloc[u] = c;
                 own[u] = idx;
-                keys[base + idx] = ((unsigned long long)(unsigned)c << 16) | (unsigned)(t0 + u);
+                if (more) keys[base + idx] = order_key(c, t0 + u, jloc[u]);
             }
         }
+        if (!more) break;
         wave_sync();
-        // rank in the next stage's order: own index plus, in every other
-        // machine's list, the number of entries below the key -- a
-        // power-of-two search with a fixed step sequence, run for all of the
-        // lane's positions in lockstep so that their LDS reads overlap
-        unsigned long long key[KMAX];
-#pragma unroll
-        for (int u = 0; u < KMAX; ++u)
-            key[u] = ((unsigned long long)(unsigned)(mloc[u] >= 0 ? cloc[u] : 0) << 16) | (unsigned)(t0 + u);
-        int top = 1;
-        while (top <= J) top <<= 1;
-        for (int oi = 1; oi < Ms; ++oi) {
-            // position u searches machine (m_u + oi) mod Ms: each other machine once
-            int lb[KMAX], n[KMAX], pos[KMAX];
+        if constexpr (MMX == 2) {
+            // two lists (the second empty when M_s = 1): a merge path.  Lane
+            // l writes merged positions [l K, l K + K): a binary search on
+            // that diagonal finds how many of them come from the first list,
+            // then the lane merges its K outputs in order.
+            const unsigned long long* X = keys + off[0];
+            const unsigned long long* Y = keys + off[1];
+            const int nx = tot[0], ny = tot[1];
+            const int dg = t0 < J ? t0 : J;
+            int lo = dg - ny > 0 ? dg - ny : 0;
+            int hi = dg < nx ? dg : nx;
+            // the first list's share of positions [0, dg): the least i in
+            // [lo, hi] with X[i] > Y[dg - 1 - i] (i = hi if none)
+            for (int step = top_pow2(J); step > 0; step >>= 1) {
+                if (lo < hi) {
+                    const int mid = (lo + hi) >> 1;
+                    const bool x_first = X[mid] < Y[dg - 1 - mid];
+                    lo = x_first ? mid + 1 : lo;
+                    hi = x_first ? hi : mid;
+                }
+            }
+            int i = lo, jy = dg - lo;
 #pragma unroll
             for (int u = 0; u < KMAX; ++u) {
-                int om = (mloc[u] >= 0 ? mloc[u] : 0) + oi;
-                om = om >= Ms ? om - Ms : om;
-                int ob = 0, on = 0;
-#pragma unroll
-                for (int mm = 0; mm < MMX; ++mm)
-                    if (mm == om) {
-                        ob = off[mm];
-                        on = tot[mm];
-                    }
-                lb[u] = ob - 1;
-                n[u] = (mloc[u] >= 0) ? on : 0;
-                pos[u] = 0;
+                if (u < K && dg + u < J) {
+                    const unsigned long long x = i < nx ? X[i] : ~0ull;
+                    const unsigned long long y = jy < ny ? Y[jy] : ~0ull;
+                    const bool tx = x < y;
+                    const unsigned long long kk = tx ? x : y;
+                    i += tx ? 1 : 0;
+                    jy += tx ? 0 : 1;
+                    ordB[dg + u] = (uint16_t)(kk & 0xFFFFull);
+                    rdyB[dg + u] = (int)(kk >> 32);
+                }
             }
-            for (int step = top >> 1; step > 0; step >>= 1) {
+        } else {
+            // rank in the next stage's order: own index plus, in every other
+            // machine's list, the number of entries below the key -- a
+            // power-of-two search with a fixed step sequence, run for all of
+            // the lane's positions in lockstep so that their LDS reads overlap
+            unsigned long long key[KMAX];
+#pragma unroll
+            for (int u = 0; u < KMAX; ++u)
+                key[u] = order_key(mloc[u] >= 0 ? cloc[u] : 0, t0 + u, mloc[u] >= 0 ? jloc[u] : 0);
+            const int top = top_pow2(J) << 1;
+            for (int oi = 1; oi < Ms; ++oi) {
+                // position u searches machine (m_u + oi) mod Ms: each other machine once
+                int lb[KMAX], n[KMAX], pos[KMAX];
 #pragma unroll
                 for (int u = 0; u < KMAX; ++u) {
-                    if (u < K) {   // uniform
-                        const int at = pos[u] + step;
-                        // entries lst[0..at) all below the key: advance
-                        if (at <= n[u] && keys[lb[u] + at] < key[u]) pos[u] = at;
+                    int om = (mloc[u] >= 0 ? mloc[u] : 0) + oi;
+                    om = om >= Ms ? om - Ms : om;
+                    int ob = 0, on = 0;
+#pragma unroll
+                    for (int mm = 0; mm < MMX; ++mm)
+                        if (mm == om) {
+                            ob = off[mm];
+                            on = tot[mm];
+                        }
+                    lb[u] = ob - 1;
+                    n[u] = (mloc[u] >= 0) ? on : 0;
+                    pos[u] = 0;
+                }
+                for (int step = top >> 1; step > 0; step >>= 1) {
+#pragma unroll
+                    for (int u = 0; u < KMAX; ++u) {
+                        if (u < K) {   // uniform
+                            const int at = pos[u] + step;
+                            // entries lst[0..at) all below the key: advance
+                            if (at <= n[u] && keys[lb[u] + at] < key[u]) pos[u] = at;
+                        }
                     }
                 }
+#pragma unroll
+                for (int u = 0; u < KMAX; ++u)
+                    if (mloc[u] >= 0) own[u] += pos[u];
             }
 #pragma unroll
             for (int u = 0; u < KMAX; ++u)
-                if (mloc[u] >= 0) own[u] += pos[u];
+                if (mloc[u] >= 0) {
+                    ordB[own[u]] = (uint16_t)jloc[u];
+                    rdyB[own[u]] = cloc[u];
+                }
         }
-#pragma unroll
-        for (int u = 0; u < KMAX; ++u)
-            if (mloc[u] >= 0) {
-                ordB[own[u]] = (uint16_t)jloc[u];
-                rdyB[own[u]] = cloc[u];
-            }
         wave_sync();
         uint16_t* to = ordA;
         ordA = ordB;
