@@ -278,9 +278,16 @@ __device__ long long decode_wave(const TtDesc& d, const Smem& sm, const uint8_t*
                 scan_maxplus(Ai, Bi);
                 A[m] = from_lane_below(Ai, kNeg);   // exclusive prefix
                 B[m] = from_lane_below(Bi, 0);
-                const int ci = scan_add(cnt[m]);
-                tot[m] = __builtin_amdgcn_readlane(ci, 63);
-                cnt[m] = ci - cnt[m];   // exclusive: entries of machine m before this lane
+                if (MMX == 2 && m == 1) {
+                    // two machines: the lanes below hold min(t0, J) positions,
+                    // those not on machine 0 are on machine 1
+                    tot[1] = J - tot[0];
+                    cnt[1] = (t0 < J ? t0 : J) - cnt[0];
+                } else {
+                    const int ci = scan_add(cnt[m]);
+                    tot[m] = __builtin_amdgcn_readlane(ci, 63);
+                    cnt[m] = ci - cnt[m];   // exclusive: entries of machine m before this lane
+                }
                 run_off += tot[m];
             }
         }
@@ -324,8 +331,10 @@ __device__ long long decode_wave(const TtDesc& d, const Smem& sm, const uint8_t*
             int lo = dg - ny > 0 ? dg - ny : 0;
             int hi = dg < nx ? dg : nx;
             // the first list's share of positions [0, dg): the least i in
-            // [lo, hi] with X[i] > Y[dg - 1 - i] (i = hi if none)
-            for (int step = top_pow2(J); step > 0; step >>= 1) {
+            // [lo, hi] with X[i] > Y[dg - 1 - i] (i = hi if none); hi - lo is
+            // at most min(nx, ny), and every round halves the candidates
+            const int span = nx < ny ? nx : ny;
+            for (int step = span > 0 ? top_pow2(span) : 0; step > 0; step >>= 1) {
                 if (lo < hi) {
                     const int mid = (lo + hi) >> 1;
                     const bool x_first = X[mid] < Y[dg - 1 - mid];
