@@ -53,11 +53,8 @@ struct TtDesc {
     int J, S, MX, L, Lp, Jp, N, n_isl, runs, H;
     long long WT, E;
     unsigned long long theta_T;
-    const int* M;               // [S]
-    const uint16_t* P;          // [J][S][MX]
-    const int* R;               // [J]
-    const int* D;               // [J]
-    const uint16_t* ord0;       // [J] stage-1 order by (R_j, j)
+    const uint4* tab;           // the LDS image of the tables (see tab_off), tab_vec 16-byte vectors
+    int tab_vec;
     uint8_t* genes[2];          // [runs][N][Lp], by generation parity
     long long* obj[2];          // [runs][N]
     unsigned long long* genkey; // [runs][n_isl][2]: min of (objective << 13 | slot)
@@ -95,11 +92,29 @@ __device__ __forceinline__ void wave_sync()
 
 __host__ __device__ inline int align16(int x) { return (x + 15) & ~15; }
 
-// LDS bytes of the shared tables and of one wave's work area.
-__host__ __device__ inline int tables_bytes(int J, int S, int MX, int Lp)
+// Byte offsets of the shared tables in LDS, each piece 16-byte aligned:
+// P[J][S][MX] (u16), D[J] and R[J] (int), the stage-1 order ord0[J] (u16),
+// M[S] (int) and cb[Lp] (u8: M_s - 1 of gene i's stage, 0 past the string,
+// the complement base).  The host writes the same image into the workspace,
+// so that a workgroup stages it with one vector copy.
+struct TabOff {
+    int P, D, R, ord0, M, cb, bytes;
+};
+__host__ __device__ inline TabOff tab_off(int J, int S, int MX, int Lp)
 {
-    return align16(J * S * MX * 2) + align16(J * 4) * 2 + align16(J * 2) + align16(S * 4) + Lp;
+    TabOff o;
+    o.P = 0;
+    o.D = o.P + align16(J * S * MX * 2);
+    o.R = o.D + align16(J * 4);
+    o.ord0 = o.R + align16(J * 4);
+    o.M = o.ord0 + align16(J * 2);
+    o.cb = o.M + align16(S * 4);
+    o.bytes = o.cb + Lp;   // Lp is a multiple of 16
+    return o;
 }
+
+// LDS bytes of the shared tables and of one wave's work area.
+__host__ __device__ inline int tables_bytes(int J, int S, int MX, int Lp) { return tab_off(J, S, MX, Lp).bytes; }
 __host__ __device__ inline int wave_bytes(int Lp, int Jp) { return Lp + Jp * 2 * 2 + Jp * 4 * 2 + Jp * 8; }
 
 struct Smem {
@@ -111,34 +126,45 @@ struct Smem {
     uint8_t* cb;   // [Lp]: M_s - 1 of gene i's stage (0 past the string): complement base
 };
 
-__device__ __forceinline__ Smem smem_tables(unsigned char* base, int J, int S, int MX)
+__device__ __forceinline__ Smem smem_tables(unsigned char* base, const TtDesc& d)
 {
+    const TabOff o = tab_off(d.J, d.S, d.MX, d.Lp);
     Smem s;
-    s.P = reinterpret_cast<uint16_t*>(base);
-    base += align16(J * S * MX * 2);
-    s.D = reinterpret_cast<int*>(base);
-    base += align16(J * 4);
-    s.R = reinterpret_cast<int*>(base);
-    base += align16(J * 4);
-    s.ord0 = reinterpret_cast<uint16_t*>(base);
-    base += align16(J * 2);
-    s.M = reinterpret_cast<int*>(base);
-    base += align16(S * 4);
-    s.cb = base;
+    s.P = reinterpret_cast<uint16_t*>(base + o.P);
+    s.D = reinterpret_cast<int*>(base + o.D);
+    s.R = reinterpret_cast<int*>(base + o.R);
+    s.ord0 = reinterpret_cast<uint16_t*>(base + o.ord0);
+    s.M = reinterpret_cast<int*>(base + o.M);
+    s.cb = base + o.cb;
     return s;
 }
 
-__device__ void stage_tables(const TtDesc& d, const Smem& s)
+// Copy of the table image into LDS at `base`: every thread issues its (up to
+// four) 16-byte global reads before its LDS writes, so a workgroup waits for
+// one round trip per 4 x blockDim vectors.  Past the end a thread reads and
+// writes the last vector again, with the same value, so that no branch pulls
+// a read down to its write.
+typedef uint32_t tab_vec4 __attribute__((ext_vector_type(4)));
+
+__device__ void stage_tables(const TtDesc& d, unsigned char* base)
 {
-    const int np = d.J * d.S * d.MX;
-    for (int i = threadIdx.x; i < np; i += blockDim.x) s.P[i] = d.P[i];
-    for (int i = threadIdx.x; i < d.J; i += blockDim.x) {
-        s.D[i] = d.D[i];
-        s.R[i] = d.R[i];
-        s.ord0[i] = d.ord0[i];
+    constexpr int U = 4;
+    const auto* src = (const __attribute__((address_space(1))) tab_vec4*)d.tab;   // global, not flat, reads
+    tab_vec4* dst = reinterpret_cast<tab_vec4*>(base);
+    const int nv = d.tab_vec;
+    for (int v0 = threadIdx.x; v0 < nv; v0 += U * blockDim.x) {
+        tab_vec4 x[U];
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            const int v = v0 + u * (int)blockDim.x;
+            x[u] = src[v < nv ? v : nv - 1];
+        }
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            const int v = v0 + u * (int)blockDim.x;
+            dst[v < nv ? v : nv - 1] = x[u];
+        }
     }
-    for (int i = threadIdx.x; i < d.S; i += blockDim.x) s.M[i] = d.M[i];
-    for (int i = threadIdx.x; i < d.Lp; i += blockDim.x) s.cb[i] = (uint8_t)(i < d.L ? d.M[i % d.S] - 1 : 0);
 }
 
 // Wave-wide inclusive scans in registers (DPP): row_shr 1, 2, 4, 8 inside
@@ -473,8 +499,8 @@ extern __shared__ __align__(16) unsigned char tt_smem[];
 template <int KMAX, int MMX>
 __global__ void __launch_bounds__(256) k_tt_generation(TtDesc d, int gen, int mode, int sel, int diag, int count)
 {
-    const Smem sm = smem_tables(tt_smem, d.J, d.S, d.MX);
-    stage_tables(d, sm);
+    const Smem sm = smem_tables(tt_smem, d);
+    stage_tables(d, tt_smem);
     __syncthreads();
     const int wpb = blockDim.x >> 6, wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
     const long long wg = (long long)blockIdx.x * wpb + wave;
@@ -792,8 +818,8 @@ __global__ void __launch_bounds__(kSortThreads) k_tt_migrate(TtDesc d, int gen)
 template <int KMAX, int MMX>
 __global__ void __launch_bounds__(256) k_tt_evaluate(TtDesc d, const uint8_t* genes, int count, long long* out)
 {
-    const Smem sm = smem_tables(tt_smem, d.J, d.S, d.MX);
-    stage_tables(d, sm);
+    const Smem sm = smem_tables(tt_smem, d);
+    stage_tables(d, tt_smem);
     __syncthreads();
     const int wpb = blockDim.x >> 6, wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
     const long long row = (long long)blockIdx.x * wpb + wave;
@@ -875,7 +901,7 @@ unsigned long long rate_T(double p)
 }
 
 struct Layout {
-    size_t genes[2], obj[2], genkey, best, best_genes, counters, err, M, P, R, D, ord0, total;
+    size_t genes[2], obj[2], genkey, best, best_genes, counters, err, tab, total;
 };
 
 Layout layout_of(const ffs_tt_ctx* c)
@@ -897,11 +923,7 @@ Layout layout_of(const ffs_tt_ctx* c)
     l.best_genes = take(R * c->Lp);
     l.counters = take(R * 2 * 8);
     l.err = take(4);
-    l.M = take((size_t)c->S * 4);
-    l.P = take((size_t)c->J * c->S * c->MX * 2);
-    l.R = take((size_t)c->J * 4);
-    l.D = take((size_t)c->J * 4);
-    l.ord0 = take((size_t)c->J * 2);
+    l.tab = take((size_t)tables_bytes(c->J, c->S, c->MX, c->Lp));
     l.total = off;
     return l;
 }
@@ -1197,16 +1219,18 @@ int ffs_tt_bind_workspace(ffs_tt_ctx* c, void* ptr, size_t bytes)
     d.best_genes = reinterpret_cast<uint8_t*>(w + l.best_genes);
     d.counters = reinterpret_cast<long long*>(w + l.counters);
     d.err = reinterpret_cast<int*>(w + l.err);
-    d.M = reinterpret_cast<const int*>(w + l.M);
-    d.P = reinterpret_cast<const uint16_t*>(w + l.P);
-    d.R = reinterpret_cast<const int*>(w + l.R);
-    d.D = reinterpret_cast<const int*>(w + l.D);
-    d.ord0 = reinterpret_cast<const uint16_t*>(w + l.ord0);
-    TT_HIP(c, hipMemcpyAsync(w + l.M, c->M.data(), c->M.size() * 4, hipMemcpyHostToDevice, c->stream));
-    TT_HIP(c, hipMemcpyAsync(w + l.P, c->P.data(), c->P.size() * 2, hipMemcpyHostToDevice, c->stream));
-    TT_HIP(c, hipMemcpyAsync(w + l.R, c->R.data(), c->R.size() * 4, hipMemcpyHostToDevice, c->stream));
-    TT_HIP(c, hipMemcpyAsync(w + l.D, c->D.data(), c->D.size() * 4, hipMemcpyHostToDevice, c->stream));
-    TT_HIP(c, hipMemcpyAsync(w + l.ord0, c->ord0.data(), c->ord0.size() * 2, hipMemcpyHostToDevice, c->stream));
+    // the tables as the LDS image that every workgroup copies (tab_off)
+    const TabOff to = tab_off(c->J, c->S, c->MX, c->Lp);
+    std::vector<unsigned char> img((size_t)to.bytes, 0);
+    std::memcpy(img.data() + to.P, c->P.data(), c->P.size() * 2);
+    std::memcpy(img.data() + to.D, c->D.data(), c->D.size() * 4);
+    std::memcpy(img.data() + to.R, c->R.data(), c->R.size() * 4);
+    std::memcpy(img.data() + to.ord0, c->ord0.data(), c->ord0.size() * 2);
+    std::memcpy(img.data() + to.M, c->M.data(), c->M.size() * 4);
+    for (int i = 0; i < c->L; ++i) img[(size_t)to.cb + i] = (unsigned char)(c->M[i % c->S] - 1);
+    d.tab = reinterpret_cast<const uint4*>(w + l.tab);
+    d.tab_vec = to.bytes / 16;
+    TT_HIP(c, hipMemcpyAsync(w + l.tab, img.data(), img.size(), hipMemcpyHostToDevice, c->stream));
     std::vector<unsigned long long> gk((size_t)c->runs * d.n_isl * 2, ~0ull);
     TT_HIP(c, hipMemcpyAsync(w + l.genkey, gk.data(), gk.size() * 8, hipMemcpyHostToDevice, c->stream));
     std::vector<long long> best((size_t)c->runs * 4, 0);
