@@ -52,9 +52,11 @@ def parse():
     ap.add_argument("--cpu-seconds", type=float, default=12.0)
     ap.add_argument("--surrogate-seconds", type=float, default=8.0,
                     help="wall-clock budget of each side of the plain vs pre-screen comparison (0 = skip)")
-    ap.add_argument("--experiment", default="", choices=["", "islands", "tardiness"],
+    ap.add_argument("--experiment", default="", choices=["", "islands", "tardiness", "decode"],
                     help="islands: island-layout ablation and migration-gap sweep; tardiness: Section 5 on the "
                          "paper-faithful variant (each prints one JSON line)")
+    ap.add_argument("--decode-count", type=int, default=1_000_000,
+                    help="random permutations per workload shape of --experiment decode")
     ap.add_argument("--runs", type=int, default=20, help="seeds per configuration of --experiment")
     ap.add_argument("--generations", type=int, default=2000, help="generations per run of --experiment")
     ap.add_argument("--calibrate-copy-mib", type=int, default=0,
@@ -338,6 +340,72 @@ def tardiness_experiment(runs: int, generations: int) -> dict:
                                              "not a target"}}
 
 
+def decode_experiment(count: int) -> dict:
+    """The exact makespan decode alone, through ffs_evaluate: `count` uniformly
+    random permutations per workload shape (tiny, medium, large, surrogate),
+    generated on the device (argsort of seeded uniform keys) and resident in
+    HBM before the timed region; HIP events on the library's stream bracket
+    each call, median of three.  Work per decode as for the generation
+    kernel: n * sum_k (m_k + 6) integer operations.  The oracle decodes a
+    sample of the same shape on one host thread."""
+    import numpy as np
+    import torch
+
+    import oracle
+    from paper_1903_10722_amd import Context, inputs
+    rows = []
+    for name in ("tiny", "medium", "large", "surrogate"):
+        w = inputs.workload(name, seed=1)
+        n, S = w["p"].shape
+        m = [int(x) for x in w["m"]]
+        ctx = Context(device=0)
+        ctx.add_instance(w["m"], w["p"], w["islands"], interval=0, theta=w["theta"], topology=w["topology"],
+                         seed=101)
+        ctx.bind()
+        g = torch.Generator(device="cuda").manual_seed(1000 + n)
+        perms = torch.empty((count, n), dtype=torch.int32, device="cuda")
+        chunk = max(1, (1 << 27) // n)   # keys of at most 512 MB at a time
+        for r0 in range(0, count, chunk):
+            r1 = min(count, r0 + chunk)
+            perms[r0:r1] = torch.argsort(torch.rand((r1 - r0, n), device="cuda", generator=g), dim=1).to(torch.int32)
+        torch.cuda.synchronize()
+        ctx.evaluate(0, perms[:4096])   # warm-up
+        times = []
+        for _ in range(3):
+            e0 = torch.cuda.Event(enable_timing=True)
+            e1 = torch.cuda.Event(enable_timing=True)
+            e0.record(ctx.stream)
+            out = ctx.evaluate(0, perms)
+            e1.record(ctx.stream)
+            torch.cuda.synchronize()
+            times.append(e0.elapsed_time(e1))
+        ms = float(np.median(times))
+        ops = n * sum(x + 6 for x in m)
+        achieved = ops * count / (ms / 1e3) / 1e12
+        # the oracle on a sample of the same shape, about 2 s
+        sample = inputs.random_perms(64, n, seed=7)
+        t0, done = time.perf_counter(), 0
+        while time.perf_counter() - t0 < 2.0:
+            oracle.decode(w["m"], w["p"], sample[done % len(sample)])
+            done += 1
+        cpu = done / (time.perf_counter() - t0)
+        rows.append({"workload": WORKLOADS[name], "n": n, "S": S, "machines": m, "decodes": count,
+                     "ms": ms, "decodes_per_s": count / (ms / 1e3),
+                     "job_stage_steps_per_s": count * n * S / (ms / 1e3),
+                     "roofline": {"bound": "alu", "achieved": achieved, "peak": PEAK_INT_TOPS, "unit": "TOP/s",
+                                  "frac": achieved / PEAK_INT_TOPS, "ops_per_decode": ops},
+                     "cpu_baseline": {"value": cpu, "unit": "decodes/s", "cores": 1, "kind": "oracle",
+                                      "sample": f"oracle decode of {done} random permutations of this shape "
+                                                f"in about 2 s, one thread"},
+                     "makespan_min": int(out.min().item())})
+        print(f"[decode] {name}: {count / (ms / 1e3) / 1e6:.1f} M decodes/s", file=sys.stderr, flush=True)
+        del perms, out
+        ctx.close()
+    return {"experiment": "decode", "count_per_shape": count,
+            "timing": "HIP events around ffs_evaluate on the library's stream, median of 3; inputs resident",
+            "rows": rows}
+
+
 def main():
     args = parse()
     if args.gpus != 1:
@@ -349,6 +417,9 @@ def main():
         return
     if args.experiment == "tardiness":
         print(json.dumps(tardiness_experiment(args.runs, args.generations)), flush=True)
+        return
+    if args.experiment == "decode":
+        print(json.dumps(decode_experiment(args.decode_count)), flush=True)
         return
     if args.calibrate_copy_mib:
         calibrate_copy(args.calibrate_copy_mib)
