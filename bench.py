@@ -52,7 +52,7 @@ def parse():
     ap.add_argument("--cpu-seconds", type=float, default=12.0)
     ap.add_argument("--surrogate-seconds", type=float, default=8.0,
                     help="wall-clock budget of each side of the plain vs pre-screen comparison (0 = skip)")
-    ap.add_argument("--experiment", default="", choices=["", "islands", "tardiness", "decode"],
+    ap.add_argument("--experiment", default="", choices=["", "islands", "tardiness", "decode", "surrogate"],
                     help="islands: island-layout ablation and migration-gap sweep; tardiness: Section 5 on the "
                          "paper-faithful variant (each prints one JSON line)")
     ap.add_argument("--decode-count", type=int, default=1_000_000,
@@ -136,11 +136,17 @@ def cpu_baseline(w, seconds: float) -> dict:
             "generations_per_s": gens / dt}
 
 
-def surrogate_compare(seconds: float) -> dict:
+def _finite_or_none(x):
+    x = float(x)
+    return x if x == x and abs(x) != float("inf") else None
+
+
+def surrogate_compare(seconds: float, seed: int = 101) -> dict:
     """Best makespan at equal wall-clock: the plain GA and the GA with the
     learned pre-screen (k = 8 candidates per cell) on the surrogate workload
     (n=1000 jobs, 20 stages, machines U[2,6], p U[1,99]; cellular 64x64 +
-    pseudo 4096; migration every 20).  Both start from the same generation 0."""
+    pseudo 4096; migration every 20).  Both start from the same generation 0
+    (GA seed `seed`)."""
     import numpy as np
     import torch
     from scipy.stats import spearmanr
@@ -155,7 +161,7 @@ def surrogate_compare(seconds: float) -> dict:
     for name, k in (("plain", 0), ("prescreen", 8)):
         ctx = Context(device=0)
         ctx.add_instance(w["m"], w["p"], w["islands"], interval=w["interval"], theta=w["theta"],
-                         topology=w["topology"], seed=101, surrogate_k=k, surrogate_warmup=5)
+                         topology=w["topology"], seed=seed, surrogate_k=k, surrogate_warmup=5)
         ctx.bind()
         torch.cuda.synchronize()
         t0 = time.perf_counter()
@@ -168,14 +174,38 @@ def surrogate_compare(seconds: float) -> dict:
             cand = ctx.surrogate_candidates(exact=True)
             ex, pred = cand["exact"].astype(np.float64), cand["pred"].astype(np.float64)
             chosen = ex[np.arange(ex.shape[0]), cand["choice"]]
-            res.update({"spearman": float(spearmanr(pred.reshape(-1), ex.reshape(-1)).correlation),
-                        "spearman_within_cell": float(np.mean([spearmanr(pred[i], ex[i]).correlation
-                                                               for i in range(ex.shape[0]) if np.ptp(ex[i]) > 0])),
+            spread = [i for i in range(ex.shape[0]) if np.ptp(ex[i]) > 0]
+            # rank correlations are undefined (null) once every candidate of
+            # every cell decodes to the same makespan (a converged population)
+            res.update({"spearman": _finite_or_none(spearmanr(pred.reshape(-1), ex.reshape(-1)).correlation)
+                        if np.ptp(ex) > 0 else None,
+                        "spearman_within_cell": _finite_or_none(np.nanmean([spearmanr(pred[i], ex[i]).correlation
+                                                                           for i in spread])) if spread else None,
+                        "cells_with_distinct_candidates": len(spread),
                         "mae": float(np.abs(pred - ex).mean()),
                         "chosen_minus_candidate0": float(chosen.mean() - ex[:, 0].mean())})
         out[name] = res
         ctx.close()
+        print(f"[surrogate] seed {seed} {name}: best {res['best_makespan']} after {res['generations']} "
+              f"generations", file=sys.stderr, flush=True)
     return out
+
+
+def surrogate_experiment(seconds: float, seeds) -> dict:
+    """The learned pre-screen against the plain GA at equal wall-clock on the
+    surrogate workload, one pair of runs per GA seed: per-seed pairs, mean and
+    standard deviation of the best makespans and of their difference."""
+    import numpy as np
+    pairs = [surrogate_compare(seconds, seed=sd) for sd in seeds]
+    plain = np.array([x["plain"]["best_makespan"] for x in pairs], dtype=np.float64)
+    pre = np.array([x["prescreen"]["best_makespan"] for x in pairs], dtype=np.float64)
+    sd = (lambda a: float(a.std(ddof=1)) if len(a) > 1 else 0.0)
+    return {"experiment": "surrogate", "budget_s": seconds, "seeds": list(seeds),
+            "workload": pairs[0]["workload"], "lower_bound": pairs[0]["lower_bound"],
+            "plain_mean": float(plain.mean()), "plain_sd": sd(plain),
+            "prescreen_mean": float(pre.mean()), "prescreen_sd": sd(pre),
+            "prescreen_minus_plain_mean": float((pre - plain).mean()), "prescreen_minus_plain_sd": sd(pre - plain),
+            "pairs": [{"seed": sd_, "plain": x["plain"], "prescreen": x["prescreen"]} for sd_, x in zip(seeds, pairs)]}
 
 
 def islands_experiment(runs: int, generations: int) -> dict:
@@ -420,6 +450,10 @@ def main():
         return
     if args.experiment == "decode":
         print(json.dumps(decode_experiment(args.decode_count)), flush=True)
+        return
+    if args.experiment == "surrogate":
+        print(json.dumps(surrogate_experiment(args.surrogate_seconds, list(range(101, 101 + args.runs)))),
+              flush=True)
         return
     if args.calibrate_copy_mib:
         calibrate_copy(args.calibrate_copy_mib)
