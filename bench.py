@@ -58,6 +58,7 @@ def parse():
     ap.add_argument("--decode-count", type=int, default=1_000_000,
                     help="random permutations per workload shape of --experiment decode")
     ap.add_argument("--runs", type=int, default=20, help="seeds per configuration of --experiment")
+    ap.add_argument("--ga-seed0", type=int, default=101, help="first GA seed of --experiment surrogate")
     ap.add_argument("--generations", type=int, default=2000, help="generations per run of --experiment")
     ap.add_argument("--calibrate-copy-mib", type=int, default=0,
                     help="only run a plain device copy of this many MiB (5 times), to calibrate HBM counters")
@@ -452,7 +453,8 @@ def main():
         print(json.dumps(decode_experiment(args.decode_count)), flush=True)
         return
     if args.experiment == "surrogate":
-        print(json.dumps(surrogate_experiment(args.surrogate_seconds, list(range(101, 101 + args.runs)))),
+        print(json.dumps(surrogate_experiment(args.surrogate_seconds,
+                                              list(range(args.ga_seed0, args.ga_seed0 + args.runs)))),
               flush=True)
         return
     if args.calibrate_copy_mib:
