@@ -4,10 +4,11 @@
 // cellular and pseudo islands and the penetration migration (Sections
 // 4.1-4.3).  Host side of include/ffs_tt.h and its kernels.
 //
-// Mapping: one wave per individual.  A workgroup stages the instance tables
-// (processing times, due dates, stage-1 order, release times, machine
-// counts) into LDS once; each wave builds its child there and decodes it
-// stage by stage with the whole wave:
+// Mapping: one wave per individual.  A workgroup copies the instance tables
+// (processing times, due dates, release times, stage-1 order, machine
+// counts, complement base), which the host stores as their LDS image, into
+// LDS once; each wave builds its child there and decodes it stage by stage
+// with the whole wave:
 //   - the completions of one stage come from a (max, +) scan per machine
 //     along the stage's order: job k on machine m finishes at
 //     max(free_m, ready_k) + p_k, and "wait for x, then run p" composes
@@ -16,9 +17,11 @@
 //   - the next stage's order (first in, first out by completion, ties by
 //     this stage's order) merges the machines' lists, each already sorted by
 //     (completion, position) because a machine finishes its jobs in order:
-//     a job's rank is its index in its own list plus, for every other
-//     machine, the number of that machine's entries below it (a binary
-//     search).
+//     with at most two machines by a merge path (each lane finds its share
+//     of the merged order by one binary search on its diagonal, then merges
+//     it), otherwise by rank (a job's index in its own list plus, for every
+//     other machine, the number of that machine's entries below it, each a
+//     binary search).
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
