@@ -134,7 +134,19 @@ def cpu_baseline(w, seconds: float) -> dict:
     return {"value": per_gen * gens / dt, "unit": "decodes/s", "cores": 1, "kind": "oracle",
             "sample": f"oracle GA on the same medium workload: generation 0 ({t_init:.2f} s) then "
                       f"{gens} generations ({per_gen} decodes each) in {dt:.1f} s, one thread",
-            "generations_per_s": gens / dt}
+            "generations_per_s": gens / dt, "host_cpu": host_cpu(), "host_threads": os.cpu_count()}
+
+
+def host_cpu() -> str:
+    """Model name of the host CPU (first entry of /proc/cpuinfo), or ''."""
+    try:
+        with open("/proc/cpuinfo") as fh:
+            for line in fh:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return ""
 
 
 def _finite_or_none(x):
