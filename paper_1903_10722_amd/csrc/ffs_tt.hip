@@ -697,19 +697,22 @@ __global__ void __launch_bounds__(256) k_tt_generation(TtDesc d, int gen, int mo
     }
 }
 
-// Best-ever record of every run after generation `gen`: the minimum
-// (objective, island, slot) of the generation replaces the record if its
-// objective is strictly lower; the generation's keys are reset.
-__global__ void k_tt_fold(TtDesc d, int gen)
+// Best-ever record of every run after generation `gen`, one wave per run:
+// the minimum (objective, island, slot) of the generation replaces the
+// record if its objective is strictly lower; the generation's keys are
+// reset.  Every lane reads the keys and the record and takes the same
+// decision; the wave copies the row, and lane 0 writes the keys and the
+// record after the reads they depend on.
+__global__ void __launch_bounds__(64) k_tt_fold(TtDesc d, int gen)
 {
-    const int run = blockIdx.x * blockDim.x + threadIdx.x;
+    const int run = blockIdx.x, lane = threadIdx.x;
     if (run >= d.runs) return;
     const int par = gen & 1;
+    unsigned long long* gk = d.genkey + (long long)run * d.n_isl * 2 + par;   // island i at gk[2 i]
     long long bo = 0;
     int bi = -1, bs = 0;
     for (int i = 0; i < d.n_isl; ++i) {
-        unsigned long long* gk = d.genkey + ((long long)run * d.n_isl + i) * 2 + par;
-        const unsigned long long v = *gk;
+        const unsigned long long v = gk[2 * i];
         const long long oi = (long long)(v >> 13);
         // every island posts a key each generation; an unset key is skipped
         if (v != ~0ull && (bi < 0 || oi < bo)) {
@@ -717,18 +720,23 @@ __global__ void k_tt_fold(TtDesc d, int gen)
             bi = i;
             bs = (int)(v & 8191u);
         }
-        *gk = ~0ull;
     }
     long long* rec = d.best + (long long)run * 4;
-    if (bi >= 0 && (rec[2] < 0 || bo < rec[0])) {
-        rec[0] = bo;
-        rec[1] = gen;
-        rec[2] = bi;
-        rec[3] = bs;
+    const bool better = bi >= 0 && (rec[2] < 0 || bo < rec[0]);
+    if (better) {
         const uint4* s4 =
             reinterpret_cast<const uint4*>(d.genes[par] + ((long long)run * d.N + island_at(d, bi).off + bs) * d.Lp);
         uint4* d4 = reinterpret_cast<uint4*>(d.best_genes + (long long)run * d.Lp);
-        for (int v = 0; v < d.Lp / 16; ++v) d4[v] = s4[v];
+        for (int v = lane; v < d.Lp / 16; v += 64) d4[v] = s4[v];
+    }
+    if (lane == 0) {
+        for (int i = 0; i < d.n_isl; ++i) gk[2 * i] = ~0ull;
+        if (better) {
+            rec[0] = bo;
+            rec[1] = gen;
+            rec[2] = bi;
+            rec[3] = bs;
+        }
     }
 }
 
@@ -995,7 +1003,7 @@ int launch_gen(ffs_tt_ctx* c, int gen, int mode)
     }
     if (rc != FFS_OK) return rc;
     if (c->timing) TT_HIP(c, hipEventRecord(e1, c->stream));
-    hipLaunchKernelGGL(k_tt_fold, dim3((unsigned)((c->runs + 63) / 64)), dim3(64), 0, c->stream, c->desc, gen);
+    hipLaunchKernelGGL(k_tt_fold, dim3((unsigned)c->runs), dim3(64), 0, c->stream, c->desc, gen);
     TT_HIP(c, hipGetLastError());
     return FFS_OK;
 }
