@@ -1222,20 +1222,23 @@ __global__ void __launch_bounds__(256) k_mig_ring(const InstDesc* __restrict__ i
 }
 
 // Stable sort of one island's slots by makespan (ties keep slot order): a
-// least-significant-bit-first radix sort over the bits of (makespan - island
-// minimum), one bit per pass.  1024 threads hold R = max(1, P/1024) items
-// each in striped order (item i = r * 1024 + thread), so a wave ballot plus
-// per-(r, wave) zero counts give every item's rank among the zeros; a pass is
-// three block barriers, and an island whose makespans span 2^b values needs
-// b passes.  Padding items (i >= size) carry all ones and stay at the end.
+// least-significant-digit-first radix sort over the bits of (makespan -
+// island minimum), two bits per pass.  1024 threads hold R = max(1, P/1024)
+// items each in striped order (item i = r * 1024 + thread); per pass, a wave
+// ballot per digit value and the per-(digit, r, wave) counts, prefixed in
+// that order, give every item its place; a pass is three block barriers, and
+// an island whose makespans span 2^b values needs ceil(b / 2) passes.
+// Padding items (i >= size) carry all ones and stay at the end.
 constexpr int kSortThreads = 1024;
 constexpr int kSortWaves = kSortThreads / 64;
 constexpr int kSortRMax = 16;
+constexpr int kSortDigits = 4;   // two bits per pass
+constexpr int kSortEnt = kSortDigits * kSortRMax * kSortWaves;   // counts per pass, at most
 
 __host__ __device__ inline size_t sort_lds_bytes(int R)
 {
     return (size_t)R * kSortThreads * (sizeof(uint32_t) + sizeof(uint16_t)) +
-           (size_t)2 * kSortRMax * kSortWaves * sizeof(uint32_t) + 64;
+           (size_t)2 * kSortEnt * sizeof(uint32_t) + (size_t)2 * kSortWaves * sizeof(uint32_t);
 }
 
 __global__ void __launch_bounds__(kSortThreads) k_mig_sort(const InstDesc* __restrict__ insts,
@@ -1254,9 +1257,9 @@ __global__ void __launch_bounds__(kSortThreads) k_mig_sort(const InstDesc* __res
     const int t = threadIdx.x, wave = t >> 6, lane = t & 63;
     uint32_t* dbuf = reinterpret_cast<uint32_t*>(ffs_smem);
     uint16_t* sbuf = reinterpret_cast<uint16_t*>(dbuf + P);
-    uint32_t* zcnt = reinterpret_cast<uint32_t*>(sbuf + P);      // [r][wave] zeros, then exclusive prefix
-    uint32_t* zpre = zcnt + kSortRMax * kSortWaves;
-    uint32_t* misc = zpre + kSortRMax * kSortWaves;              // [0..15] wave minima, [16..31] maxima, [32] zeros
+    uint32_t* zcnt = reinterpret_cast<uint32_t*>(sbuf + P);      // [digit][r][wave] counts
+    uint32_t* zpre = zcnt + kSortEnt;                            // their exclusive prefix, same order
+    uint32_t* misc = zpre + kSortEnt;                            // [0..15] wave minima, [16..31] maxima
     const int* mk = L->mk[gen & 1];
 
     uint32_t d[kSortRMax], sl[kSortRMax];
@@ -1297,24 +1300,29 @@ __global__ void __launch_bounds__(kSortThreads) k_mig_sort(const InstDesc* __res
         if (r < R && r * kSortThreads + t < N) d[r] -= mn;
 
     const uint64_t below = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
-    for (int bit = 0; bit < bits; ++bit) {
-        // zeros per (r, wave)
-        uint64_t zm[kSortRMax];
+    const int nent = kSortDigits * R * kSortWaves;
+    for (int bit = 0; bit < bits; bit += 2) {
+        // items of each digit value per (r, wave)
 #pragma unroll
         for (int r = 0; r < kSortRMax; ++r)
             if (r < R) {
-                zm[r] = __ballot(((d[r] >> bit) & 1u) == 0u);
-                if (lane == 0) zcnt[r * kSortWaves + wave] = (uint32_t)__popcll(zm[r]);
+                const uint32_t dg = (d[r] >> bit) & 3u;
+#pragma unroll
+                for (int v = 0; v < kSortDigits; ++v) {
+                    const uint64_t bm = __ballot(dg == (uint32_t)v);
+                    if (lane == 0) zcnt[(v * R + r) * kSortWaves + wave] = (uint32_t)__popcll(bm);
+                }
             }
         __syncthreads();
-        // exclusive prefix over (r, wave) order, by wave 0: four entries per lane
+        // exclusive prefix over (digit, r, wave) order, by wave 0: up to 16
+        // consecutive entries per lane
         if (wave == 0) {
-            const int nent = R * kSortWaves;
-            uint32_t v[4], run = 0;
+            const int per = (nent + 63) >> 6;
+            uint32_t v[kSortEnt / 64], run = 0;
 #pragma unroll
-            for (int e = 0; e < 4; ++e) {
-                const int idx = lane * 4 + e;
-                v[e] = idx < nent ? zcnt[idx] : 0u;
+            for (int e = 0; e < kSortEnt / 64; ++e) {
+                const int idx = lane * per + e;
+                v[e] = (e < per && idx < nent) ? zcnt[idx] : 0u;
                 run += v[e];
             }
             uint32_t incl = run;
@@ -1325,21 +1333,25 @@ __global__ void __launch_bounds__(kSortThreads) k_mig_sort(const InstDesc* __res
             }
             uint32_t ex = incl - run;
 #pragma unroll
-            for (int e = 0; e < 4; ++e) {
-                const int idx = lane * 4 + e;
-                if (idx < nent) zpre[idx] = ex;
+            for (int e = 0; e < kSortEnt / 64; ++e) {
+                const int idx = lane * per + e;
+                if (e < per && idx < nent) zpre[idx] = ex;
                 ex += v[e];
             }
-            if (lane == 63) misc[32] = incl;
         }
         __syncthreads();
-        const uint32_t Z = misc[32];
 #pragma unroll
         for (int r = 0; r < kSortRMax; ++r)
             if (r < R) {
-                const uint32_t i = (uint32_t)(r * kSortThreads + t);
-                const uint32_t zb = zpre[r * kSortWaves + wave] + (uint32_t)__popcll(zm[r] & below);
-                const uint32_t pos = ((d[r] >> bit) & 1u) ? Z + (i - zb) : zb;
+                const uint32_t dg = (d[r] >> bit) & 3u;
+                // the lanes of this wave whose item has the same digit
+                uint64_t m = 0;
+#pragma unroll
+                for (int v = 0; v < kSortDigits; ++v) {
+                    const uint64_t bm = __ballot(dg == (uint32_t)v);
+                    m = (dg == (uint32_t)v) ? bm : m;
+                }
+                const uint32_t pos = zpre[(dg * R + r) * kSortWaves + wave] + (uint32_t)__popcll(m & below);
                 dbuf[pos] = d[r];
                 sbuf[pos] = (uint16_t)sl[r];
             }
