@@ -10,6 +10,8 @@ Functions and the passage of the paper each follows:
   ox               Section 4.2 "recombines two individuals" (Davis order crossover)
   fisher_yates     Section 4.1 "random initialization"
   cell_parents     Section 4.2, neighbourhood of the cellular GA (Fig. 3 reading)
+  swap_mutation    Section 4.2 "undertakes the mutation" (one swap, j != i)
+  pseudo_children  Section 4.1 operator level (a parent mates with its complement)
   migration_policy Section 4.3, equations (1) and (2)
   GA               Sections 4.1-4.3 (one whole island-GA trajectory)
   philox           Salmon et al. SC'11 (the counter-based generator)
@@ -97,6 +99,12 @@ def _load():
     lib.or_ga_step_island.argtypes = [ctypes.c_void_p, ctypes.c_int]
     lib.or_ga_cell_candidate.argtypes = [ctypes.c_void_p, ctypes.c_int, ctypes.c_int, ctypes.c_int, _i32p, _i32p]
     lib.or_ga_set_cell_choices.argtypes = [ctypes.c_void_p, ctypes.c_int, _i32p]
+    lib.or_swap_mutation.argtypes = [ctypes.c_int, _i32p, ctypes.c_uint32, ctypes.c_uint32, ctypes.c_uint32,
+                                     ctypes.c_uint64]
+    lib.or_swap_mutation.restype = None
+    lib.or_pseudo_children.argtypes = [ctypes.c_int, _i32p, ctypes.POINTER(ctypes.c_uint32), ctypes.c_uint64,
+                                       ctypes.c_uint64, _i32p, _i32p]
+    lib.or_pseudo_children.restype = None
     _lib = lib
     return lib
 
@@ -161,6 +169,37 @@ def fisher_yates(n: int, seed: int, inst: int, island: int, slot: int) -> np.nda
     out = np.zeros(n, dtype=np.int32)
     _load().or_fisher_yates(n, seed, inst, island, slot, _ptr(out, _i32p))
     return out
+
+
+def rate_threshold(p: float) -> int:
+    """floor(p * 2^32), with p = 1 meaning "always" (2^32)."""
+    if p <= 0.0:
+        return 0
+    if p >= 1.0:
+        return 1 << 32
+    return int(p * 4294967296.0)
+
+
+def swap_mutation(x, d_flag: int, d_i: int, d_j: int, tm: int) -> np.ndarray:
+    """The swap mutation of one child (Section 4.2) for given draws and a
+    mutation threshold tm (mutate iff d_flag < tm); returns the new row."""
+    out = _i32(x).copy()
+    _load().or_swap_mutation(out.shape[0], _ptr(out, _i32p), d_flag, d_i, d_j, tm)
+    return out
+
+
+def pseudo_children(X, draws, tc: int, tm: int) -> tuple[np.ndarray, np.ndarray]:
+    """The two children of one complementary pair (Section 4.1) from its
+    better member X and the pair's nine draws d0..d8."""
+    X = _i32(X)
+    d = np.ascontiguousarray(np.asarray(draws, dtype=np.uint32))
+    assert d.shape == (9,)
+    n = X.shape[0]
+    c1 = np.zeros(n, dtype=np.int32)
+    c2 = np.zeros(n, dtype=np.int32)
+    _load().or_pseudo_children(n, _ptr(X, _i32p), d.ctypes.data_as(ctypes.POINTER(ctypes.c_uint32)), tc, tm,
+                               _ptr(c1, _i32p), _ptr(c2, _i32p))
+    return c1, c2
 
 
 def cell_parents(rows: int, cols: int, mk, slot: int, sel: int = 0, d6: int = 0, d7: int = 0) -> tuple[int, int]:

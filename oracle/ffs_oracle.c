@@ -375,7 +375,12 @@ void or_ga_destroy(void *h)
     free(g->isl); free(g->m); free(g->p); free(g->best_perm); free(g);
 }
 
-static void swap_mutation(int n, int *x, uint32_t dflag, uint32_t di, uint32_t dj, uint64_t tm)
+/* Swap mutation (Section 4.2 names a mutation step; the operator is our
+ * reading): with probability tm the genes at positions i and j != i trade
+ * places, i uniform in [0, n) from draw di and j = (i + 1 + r) mod n with r
+ * uniform in [0, n - 1) from draw dj, so every other position is equally
+ * likely.  Exported for the tests.                                          */
+void or_swap_mutation(int n, int *x, uint32_t dflag, uint32_t di, uint32_t dj, uint64_t tm)
 {
     if (!((uint64_t)dflag < tm)) return;
     int i = (int)uniform_below(di, (uint32_t)n);
@@ -402,7 +407,7 @@ static void cell_offspring(or_ga_t *g, int island, int s, int sub, int *child, i
     int a = u < v ? u : v, b = u < v ? v : u;
     if (cx) or_ox(n, P1, P2, a, b, child);
     else memcpy(child, P1, sizeof(int) * (size_t)n);
-    swap_mutation(n, child, d[3], d[4], d[5], I->tm);
+    or_swap_mutation(n, child, d[3], d[4], d[5], I->tm);
     if (meta) {
         int mx = (uint64_t)d[3] < I->tm;
         int mi = (int)uniform_below(d[4], (uint32_t)n);
@@ -469,39 +474,55 @@ static void cellular_step(or_ga_t *g, int island)
     g->choice[island] = NULL;
 }
 
-/* one generation of a pseudo island: per pair, the better parent X and its
- * complement Y = reverse(X) mate; the two children replace the pair.       */
+/* The two children of one complementary pair (Section 4.1, operator level:
+ * a parent mates with its complement, and the pseudo GA's children take the
+ * parents' places).  X is the pair's better member, Y = reverse(X) its
+ * complement.  With probability tc (draw d[0]) the children are
+ * C1 = OX(X, Y; a, b) and C2 = OX(Y, X; a, b) with one pair of cut points
+ * from draws d[1], d[2]; otherwise C1 = X and C2 = Y.  C1 then takes a swap
+ * mutation from draws d[3..5] and C2 one from d[6..8].  Exported for the
+ * tests.                                                                    */
+void or_pseudo_children(int n, const int *X, const uint32_t *d, uint64_t tc, uint64_t tm, int *C1, int *C2)
+{
+    int *Y = (int *)malloc(sizeof(int) * (size_t)n);
+    for (int t = 0; t < n; ++t) Y[t] = X[n - 1 - t];
+    if ((uint64_t)d[0] < tc) {
+        int u = (int)uniform_below(d[1], (uint32_t)n), v = (int)uniform_below(d[2], (uint32_t)n);
+        int a = u < v ? u : v, b = u < v ? v : u;
+        or_ox(n, X, Y, a, b, C1);
+        or_ox(n, Y, X, a, b, C2);
+    } else {
+        memcpy(C1, X, sizeof(int) * (size_t)n);
+        memcpy(C2, Y, sizeof(int) * (size_t)n);
+    }
+    or_swap_mutation(n, C1, d[3], d[4], d[5], tm);
+    or_swap_mutation(n, C2, d[6], d[7], d[8], tm);
+    free(Y);
+}
+
+/* one generation of a pseudo island: per pair, the better parent X (lower
+ * makespan, the even slot on ties) and its complement mate; the two
+ * children replace the pair.                                                */
 static void pseudo_step(or_ga_t *g, int island)
 {
     or_island_t *I = &g->isl[island];
     int n = g->n;
     int *ng = (int *)malloc(sizeof(int) * (size_t)I->size * n);
     int *nm = (int *)malloc(sizeof(int) * (size_t)I->size);
-    int *X = (int *)malloc(sizeof(int) * (size_t)n), *Y = (int *)malloc(sizeof(int) * (size_t)n);
+    int *X = (int *)malloc(sizeof(int) * (size_t)n);
     for (int q = 0; q < I->size / 2; ++q) {
         int s0 = 2 * q, s1 = 2 * q + 1;
         int xs = (I->mk[s0] <= I->mk[s1]) ? s0 : s1;
         memcpy(X, I->genes + (size_t)xs * n, sizeof(int) * (size_t)n);
-        for (int t = 0; t < n; ++t) Y[t] = X[n - 1 - t];
         uint32_t d[9];
         for (int t = 0; t < 9; ++t)
             d[t] = or_draw(g->seed, g->inst, (uint32_t)island, (uint32_t)q, 0, (uint32_t)g->gen, OR_PAIR, (uint32_t)t);
         int *C1 = ng + (size_t)s0 * n, *C2 = ng + (size_t)s1 * n;
-        if ((uint64_t)d[0] < I->tc) {
-            int u = (int)uniform_below(d[1], (uint32_t)n), v = (int)uniform_below(d[2], (uint32_t)n);
-            int a = u < v ? u : v, b = u < v ? v : u;
-            or_ox(n, X, Y, a, b, C1);
-            or_ox(n, Y, X, a, b, C2);
-        } else {
-            memcpy(C1, X, sizeof(int) * (size_t)n);
-            memcpy(C2, Y, sizeof(int) * (size_t)n);
-        }
-        swap_mutation(n, C1, d[3], d[4], d[5], I->tm);
-        swap_mutation(n, C2, d[6], d[7], d[8], I->tm);
+        or_pseudo_children(n, X, d, I->tc, I->tm, C1, C2);
         nm[s0] = (int)dec(g, C1);
         nm[s1] = (int)dec(g, C2);
     }
-    free(I->genes); free(I->mk); free(X); free(Y);
+    free(I->genes); free(I->mk); free(X);
     I->genes = ng; I->mk = nm;
 }
 

@@ -152,8 +152,8 @@ void or_tt_complement(int J, int S, const int *M, const int *x, int *y)
 
 /* Mutation: with probability tm, gene i (uniform) moves to another machine
  * of its stage, (old + 1 + r) mod M_s with r uniform in [0, M_s - 1); a stage
- * with one machine is left alone.                                           */
-static void tt_mutate(int J, int S, const int *M, int *x, uint32_t dflag, uint32_t di, uint32_t dr, uint64_t tm)
+ * with one machine is left alone.  Exported for the tests.                  */
+void or_tt_mutate(int J, int S, const int *M, int *x, uint32_t dflag, uint32_t di, uint32_t dr, uint64_t tm)
 {
     (void)J;
     if (!((uint64_t)dflag < tm)) return;
@@ -333,7 +333,7 @@ static void tt_cellular_sweep(tt_ga_t *g, int island)
         } else {
             memcpy(child, P1, sizeof(int) * (size_t)L);
         }
-        tt_mutate(g->J, g->S, g->M, child, d[3], d[4], d[5], I->tm);
+        or_tt_mutate(g->J, g->S, g->M, child, d[3], d[4], d[5], I->tm);
         int64_t co = tt_obj(g, child);
         if (co < I->obj[s]) {
             memcpy(I->genes + (size_t)s * L, child, sizeof(int) * (size_t)L);
@@ -366,7 +366,7 @@ static void tt_cellular_step(tt_ga_t *g, int island)
         } else {
             memcpy(child, P1, sizeof(int) * (size_t)L);
         }
-        tt_mutate(g->J, g->S, g->M, child, d[3], d[4], d[5], I->tm);
+        or_tt_mutate(g->J, g->S, g->M, child, d[3], d[4], d[5], I->tm);
         int64_t co = tt_obj(g, child);
         if (co < I->obj[s]) {
             memcpy(ng + (size_t)s * L, child, sizeof(int) * (size_t)L);
@@ -405,8 +405,8 @@ static void tt_pseudo_step(tt_ga_t *g, int island)
             memcpy(C1, X, sizeof(int) * (size_t)L);
             memcpy(C2, Y, sizeof(int) * (size_t)L);
         }
-        tt_mutate(g->J, g->S, g->M, C1, d[3], d[4], d[5], I->tm);
-        tt_mutate(g->J, g->S, g->M, C2, d[6], d[7], d[8], I->tm);
+        or_tt_mutate(g->J, g->S, g->M, C1, d[3], d[4], d[5], I->tm);
+        or_tt_mutate(g->J, g->S, g->M, C2, d[6], d[7], d[8], I->tm);
         no[s0] = tt_obj(g, C1);
         no[s1] = tt_obj(g, C2);
     }

@@ -13,7 +13,7 @@ What it computes:
     BF16 operands, MSE loss; mlp_layers exposes each layer separately so a
     GPU layer can be checked from the GPU's own BF16 inputs.
   - adam: the Adam update (Kingma & Ba, ICLR 2015) in FP64.
-  - spearman: rank correlation.
+  - spearman: rank correlation on average ranks (ties share their mean rank).
 
 The pre-screen itself is not in the paper: it ranks candidate children of a
 cellular cell (Section 4.2's one-child-per-cell step) so that only the best
@@ -146,9 +146,28 @@ def adam(param, grad, m, v, step: int, lr=1e-3, beta1=0.9, beta2=0.999, eps=1e-8
     return param - lr * mh / (np.sqrt(vh) + eps), m, v
 
 
+def average_ranks(x) -> np.ndarray:
+    """Ranks 1..N of x, tied values sharing the mean of the ranks they span."""
+    x = np.asarray(x)
+    order = np.argsort(x, kind="stable")
+    xs = x[order]
+    ranks = np.empty(len(x), dtype=np.float64)
+    i = 0
+    while i < len(xs):
+        j = i
+        while j + 1 < len(xs) and xs[j + 1] == xs[i]:
+            j += 1
+        ranks[order[i:j + 1]] = 0.5 * (i + j) + 1.0
+        i = j + 1
+    return ranks
+
+
 def spearman(a, b) -> float:
-    ra = np.argsort(np.argsort(a, kind="stable"), kind="stable").astype(np.float64)
-    rb = np.argsort(np.argsort(b, kind="stable"), kind="stable").astype(np.float64)
+    """Spearman's rho: Pearson correlation of the average ranks (ties share
+    their mean rank); NaN when either side is constant."""
+    ra = average_ranks(a)
+    rb = average_ranks(b)
     ra -= ra.mean()
     rb -= rb.mean()
-    return float((ra * rb).sum() / np.sqrt((ra * ra).sum() * (rb * rb).sum()))
+    den = np.sqrt((ra * ra).sum() * (rb * rb).sum())
+    return float((ra * rb).sum() / den) if den > 0 else float("nan")

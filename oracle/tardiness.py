@@ -30,6 +30,9 @@ def _lib():
     lib.or_tt_emax.restype = ctypes.c_int64
     lib.or_tt_two_point.argtypes = [ctypes.c_int, _i32p, _i32p, ctypes.c_int, ctypes.c_int, _i32p]
     lib.or_tt_complement.argtypes = [ctypes.c_int, ctypes.c_int, _i32p, _i32p, _i32p]
+    lib.or_tt_mutate.argtypes = [ctypes.c_int, ctypes.c_int, _i32p, _i32p, ctypes.c_uint32, ctypes.c_uint32,
+                                 ctypes.c_uint32, ctypes.c_uint64]
+    lib.or_tt_mutate.restype = None
     lib.or_tt_random_genes.argtypes = [ctypes.c_int, ctypes.c_int, _i32p, ctypes.c_uint64, ctypes.c_uint64,
                                        ctypes.c_int, ctypes.c_int, _i32p]
     lib.or_tt_migration_policy.argtypes = [ctypes.c_int64, ctypes.c_int64, ctypes.c_int64, ctypes.c_int64,
@@ -103,6 +106,16 @@ def complement(inst, x):
     xx = _i32(x)
     out = np.zeros_like(xx)
     _lib().or_tt_complement(len(xx) // S, S, _ptr(M, _i32p), _ptr(xx, _i32p), _ptr(out, _i32p))
+    return out
+
+
+def mutate(inst, x, d_flag: int, d_i: int, d_r: int, tm: int) -> np.ndarray:
+    """The variant's mutation of one child for given draws (gene i moves to
+    another machine of its stage); returns the new row."""
+    M = _i32(inst["M"])
+    out = _i32(x).copy()
+    J = out.shape[0] // M.shape[0]
+    _lib().or_tt_mutate(J, M.shape[0], _ptr(M, _i32p), _ptr(out, _i32p), d_flag, d_i, d_r, tm)
     return out
 
 

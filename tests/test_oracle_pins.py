@@ -573,3 +573,102 @@ def test_ring_edge_topology_is_the_pair_rule_edge_by_edge():
     zero.migrate()
     for i in range(2):
         assert (two.population(i)[0] == zero.population(i)[0]).all()
+
+
+# --------------------------------------------------------------------------
+# Swap mutation and the pseudo island's complementary mating
+# --------------------------------------------------------------------------
+def test_swap_mutation_worked_example():
+    """Hand-computed positions for fixed draws (Section 4.2 mutation step):
+    catches a j drawn over [0, n) (a no-op swap), the two position draws
+    taking each other's role, or a non-strict flag threshold."""
+    g = gold("swap_mutation_worked_example.json")
+    for c in g["cases"]:
+        got = oracle.swap_mutation(g["x"], c["d_flag"], c["d_i"], c["d_j"], g["tm"])
+        assert got.tolist() == c["child"], c["name"]
+
+
+def test_swap_mutation_moves_exactly_two_genes_to_every_other_position():
+    """When the flag fires exactly two positions change, and over a fine grid
+    of the second draw the partner j covers the n - 1 other positions evenly
+    and never i itself."""
+    rng = np.random.default_rng(11)
+    for n in (2, 3, 8, 37):
+        x = rng.permutation(n).astype(np.int32)
+        for d_i in (0, 1 << 31, (1 << 32) - 1, int(rng.integers(0, 1 << 32))):
+            hits = np.zeros(n, dtype=np.int64)
+            for d_j in range(0, 1 << 32, 1 << 20):
+                y = oracle.swap_mutation(x, 0, d_i, d_j, 1 << 32)
+                diff = np.nonzero(y != x)[0]
+                assert len(diff) == 2 and sorted(y.tolist()) == sorted(x.tolist())
+                i = (d_i * n) >> 32
+                assert i in diff
+                hits[diff[diff != i][0]] += 1
+            others = np.delete(hits, (d_i * n) >> 32)
+            assert hits[(d_i * n) >> 32] == 0
+            assert others.max() - others.min() <= 1 and others.sum() == 4096
+        # no flag, no change
+        assert np.array_equal(oracle.swap_mutation(x, 5, 0, 0, 5), x)
+
+
+def test_pseudo_children_worked_example():
+    """Hand-traced children of one complementary pair (Section 4.1): shared
+    cut points, C1 = OX(X, reverse X), C2 = OX(reverse X, X), C1 mutated by
+    draws 3-5 and C2 by draws 6-8."""
+    g = gold("pseudo_children_worked_example.json")
+    for c in g["cases"]:
+        c1, c2 = oracle.pseudo_children(g["X"], c["draws"], g["tc"], g["tm"])
+        assert c1.tolist() == c["c1"] and c2.tolist() == c["c2"], c["name"]
+    # the crossed children are not each other's reversal: a reading that
+    # built C2 as reverse(C1) fails here
+    c = g["cases"][1]
+    assert c["c2"] != c["c1"][::-1]
+
+
+def _pseudo_pair_ga(genes, pc, pm, seed=3):
+    m, p = inputs.make_instance(8, 3, 1, 3, seed=seed)
+    mk = oracle.decode_many(m, p, genes).astype(np.int32)
+    ga = oracle.GA(m, p, [inputs.pseudo(2, pc, pm)], interval=0, seed=seed)
+    ga.set_population(0, genes, mk)
+    return m, p, mk, ga
+
+
+def test_pseudo_pair_mates_its_better_member():
+    """The pair's better member by (makespan, slot) is X: without operators
+    the pair becomes (X, reverse X); on equal makespans the even slot is X."""
+    rng = np.random.default_rng(4)
+    m, p = inputs.make_instance(8, 3, 1, 3, seed=3)
+    while True:
+        A, B = rng.permutation(8), rng.permutation(8)
+        ma, mb = oracle.decode(m, p, A), oracle.decode(m, p, B)
+        if mb < ma:
+            break
+    _, _, _, ga = _pseudo_pair_ga(np.stack([A, B]), 0.0, 0.0)
+    ga.evolve(1)
+    genes, mk = ga.population(0)
+    assert genes[0].tolist() == B.tolist() and genes[1].tolist() == B[::-1].tolist()
+    assert mk.tolist() == [mb, oracle.decode(m, p, B[::-1])]
+    # equal makespans: the even slot is X
+    while True:
+        C, D = rng.permutation(8), rng.permutation(8)
+        if oracle.decode(m, p, C) == oracle.decode(m, p, D) and C.tolist() != D.tolist():
+            break
+    _, _, _, ga = _pseudo_pair_ga(np.stack([C, D]), 0.0, 0.0)
+    ga.evolve(1)
+    genes = ga.population(0)[0]
+    assert genes[0].tolist() == C.tolist() and genes[1].tolist() == C[::-1].tolist()
+
+
+def test_pseudo_step_takes_the_pair_stream():
+    """With crossover and mutation always on, the pair's children are the
+    pseudo_children of X under draws 0-8 of the pair's PAIR stream (purpose 5,
+    slot = pair index, generation 1)."""
+    rng = np.random.default_rng(6)
+    genes = np.stack([rng.permutation(8) for _ in range(2)]).astype(np.int32)
+    _, _, mk, ga = _pseudo_pair_ga(genes, 1.0, 1.0, seed=9)
+    ga.evolve(1)
+    X = genes[0] if mk[0] <= mk[1] else genes[1]
+    d = [oracle.draw(9, 0, 0, 0, 0, 1, 5, t) for t in range(9)]
+    c1, c2 = oracle.pseudo_children(X, d, 1 << 32, 1 << 32)
+    got = ga.population(0)[0]
+    assert got[0].tolist() == c1.tolist() and got[1].tolist() == c2.tolist()

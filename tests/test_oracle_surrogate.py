@@ -147,3 +147,18 @@ def test_replayed_choices_change_only_the_chosen_streams():
             assert genes1[s].tolist() == cands[s].tolist() and mk1[s] == c
         else:
             assert genes1[s].tolist() == genes0[s].tolist() and mk1[s] == mk0[s]
+
+
+def test_spearman_on_tied_data_matches_scipy():
+    """Tied values share their mean rank, as in scipy's spearmanr; a
+    position-ordered (ordinal) ranking of ties would differ here."""
+    from scipy.stats import spearmanr
+    rng = np.random.default_rng(7)
+    for _ in range(20):
+        a = rng.integers(0, 4, size=60).astype(np.float64)      # many ties
+        b = a + rng.integers(0, 3, size=60)
+        assert abs(sg.spearman(a, b) - spearmanr(a, b).correlation) < 1e-12
+    # by hand: a = [1, 1, 2], b = [1, 2, 3]: ranks (1.5, 1.5, 3) and (1, 2, 3)
+    # give rho = 1.5 / sqrt(1.5 * 2) = sqrt(3) / 2
+    assert abs(sg.spearman([1, 1, 2], [1, 2, 3]) - np.sqrt(3) / 2) < 1e-15
+    assert np.isnan(sg.spearman([2, 2, 2], [1, 2, 3]))

@@ -212,3 +212,41 @@ def test_line_sweep_spreads_the_best_in_one_generation():
         assert got == want_best, (sweep, sorted(got))
         for s in got:
             assert np.array_equal(g[s], genes[0])
+
+
+def test_mutation_worked_example():
+    """Hand-computed gene moves of the variant's mutation (reading T4): the
+    gene always goes to another machine of its stage, and a one-machine
+    stage is left alone."""
+    with open(os.path.join(os.path.dirname(__file__), "golden", "tt_mutation_worked_example.json")) as f:
+        g = json.load(f)
+    inst = dict(M=np.array(g["M"], dtype=np.int32))
+    for c in g["cases"]:
+        got = tt.mutate(inst, g["x"], c["d_flag"], c["d_i"], c["d_r"], g["tm"])
+        assert got.tolist() == c["child"], c["name"]
+    s = g["single_machine"]
+    got = tt.mutate(dict(M=np.array(s["M"], dtype=np.int32)), s["x"], s["d_flag"], s["d_i"], s["d_r"], 1 << 32)
+    assert got.tolist() == s["child"]
+
+
+def test_mutation_changes_one_gene_to_every_other_machine():
+    """When the flag fires, exactly one gene changes, to a machine of its
+    stage other than the old one, and over a fine grid of the machine draw
+    every other machine is reached evenly."""
+    M = np.array([2, 3, 4, 6], dtype=np.int32)
+    inst = dict(M=M)
+    rng = np.random.default_rng(2)
+    J = 5
+    x = np.concatenate([rng.integers(0, M) for _ in range(J)]).astype(np.int32)
+    for i in range(J * len(M)):
+        d_i = -(-(i << 32) // (J * len(M)))      # smallest draw that selects gene i
+        ms = int(M[i % len(M)])
+        hits = np.zeros(ms, dtype=np.int64)
+        for d_r in range(0, 1 << 32, 1 << 22):
+            y = tt.mutate(inst, x, 0, d_i, d_r, 1 << 32)
+            diff = np.nonzero(y != x)[0]
+            assert diff.tolist() == [i]
+            assert 0 <= y[i] < ms and y[i] != x[i]
+            hits[y[i]] += 1
+        others = np.delete(hits, x[i])
+        assert hits[x[i]] == 0 and others.max() - others.min() <= 1
