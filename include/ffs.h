@@ -160,6 +160,14 @@ int ffs_bind_workspace(ffs_ctx *ctx, void *device_ptr, size_t bytes);
 int ffs_evaluate(ffs_ctx *ctx, int32_t inst, const int32_t *perms, int32_t count,
                  int32_t *out_makespans);
 
+/* ffs_evaluate with host pointers: perms int32 [count * n_jobs] and
+ * out_makespans int32 [count] in host memory.  Rows are copied through a
+ * 4 MiB staging region of the workspace in chunks (pageable copies on the
+ * context's stream), so the figure it gives includes the host transfers.
+ * Same validation and status as ffs_evaluate.  (syncs)                      */
+int ffs_evaluate_host(ffs_ctx *ctx, int32_t inst, const int32_t *perms, int32_t count,
+                      int32_t *out_makespans);
+
 /* Run `generations` generations of every instance.  Per generation: every
  * cellular cell and pseudo pair produces its children from generation g-1
  * (synchronous update), the best-ever record is updated, and when
@@ -193,6 +201,25 @@ int ffs_migration_counters(ffs_ctx *ctx, int32_t inst, int64_t *migrations, int6
  * the summed milliseconds and the launch count since enabling.  (syncs)     */
 int ffs_set_timing(ffs_ctx *ctx, int32_t enable);
 int ffs_kernel_time(ffs_ctx *ctx, double *total_ms, int64_t *launches);
+
+/* ---- checkpoint / restore --------------------------------------------------
+ * A checkpoint is a host byte image of the whole context at its current
+ * generation: the generation count, every island's genes and makespans, the
+ * best-ever records with their permutations, the migration counters and,
+ * for a pre-screened instance, the network's FP32 parameters, both Adam
+ * moments and the step count, the replay ring and the cells' candidate
+ * choices.  It begins with a fingerprint of the instances (sizes, machines,
+ * processing times, island specs, GA configs, seeds).  ffs_checkpoint_load
+ * accepts it only on a bound context created with the same instances in the
+ * same order (tile shape and graph use may differ); evolving from there
+ * gives exactly the trajectory the saved context would have followed
+ * (Section 4's GA is a deterministic function of this state and the seeds).
+ *   size: bytes of the image; save: host buffer of at least that size;
+ *   load: FFS_EINVAL when the image is not one, is truncated, or was taken
+ *   from other instances (the context is then unchanged).  (syncs)          */
+int ffs_checkpoint_size(ffs_ctx *ctx, size_t *bytes);
+int ffs_checkpoint_save(ffs_ctx *ctx, void *host, size_t bytes);
+int ffs_checkpoint_load(ffs_ctx *ctx, const void *host, size_t bytes);
 
 /* ---- learned pre-screen (instances with surrogate_k > 1) ------------------
  * Parameters: one FP32 vector of 394753 values, W1 [512][256] (row = output

@@ -25,6 +25,7 @@ EXPORTS = [
     "ffs_migration_counters", "ffs_set_graphs", "ffs_set_timing", "ffs_kernel_time",
     "ffs_surrogate_params", "ffs_surrogate_set_params", "ffs_mlp_forward", "ffs_mlp_gradients",
     "ffs_mlp_train_step", "ffs_surrogate_candidates", "ffs_surrogate_choices", "ffs_surrogate_ring",
+    "ffs_evaluate_host", "ffs_checkpoint_size", "ffs_checkpoint_save", "ffs_checkpoint_load",
 ]
 
 N_PARAMS = 394753
@@ -79,6 +80,10 @@ def load_library():
     lib.ffs_workspace_size.argtypes = [P, ctypes.POINTER(ctypes.c_size_t)]
     lib.ffs_bind_workspace.argtypes = [P, P, ctypes.c_size_t]
     lib.ffs_evaluate.argtypes = [P, i32, P, i32, P]
+    lib.ffs_evaluate_host.argtypes = [P, i32, pi32, i32, pi32]
+    lib.ffs_checkpoint_size.argtypes = [P, ctypes.POINTER(ctypes.c_size_t)]
+    lib.ffs_checkpoint_save.argtypes = [P, P, ctypes.c_size_t]
+    lib.ffs_checkpoint_load.argtypes = [P, P, ctypes.c_size_t]
     lib.ffs_evolve.argtypes = [P, i32]
     lib.ffs_migrate.argtypes = [P, i32]
     lib.ffs_best.argtypes = [P, i32, pi32, pi32, pi32]
@@ -201,6 +206,27 @@ class Context:
         if check:
             self._check(rc)
         return out if check else (out, rc)
+
+    def evaluate_host(self, inst: int, perms) -> tuple[np.ndarray, int]:
+        """Makespans (numpy int32) of host rows through the host-pointer entry
+        point; returns (makespans, status)."""
+        a = _i32(perms)
+        out = np.zeros(a.shape[0], dtype=np.int32)
+        rc = self.lib.ffs_evaluate_host(self._h, inst, _p32(a), a.shape[0], _p32(out))
+        return out, rc
+
+    def checkpoint(self) -> bytes:
+        """Byte image of the whole context at its current generation."""
+        n = ctypes.c_size_t()
+        self._check(self.lib.ffs_checkpoint_size(self._h, ctypes.byref(n)))
+        buf = ctypes.create_string_buffer(n.value)
+        self._check(self.lib.ffs_checkpoint_save(self._h, buf, n))
+        return buf.raw
+
+    def restore(self, image: bytes):
+        """Load a checkpoint taken from a context with the same instances."""
+        buf = ctypes.create_string_buffer(bytes(image), len(image))
+        self._check(self.lib.ffs_checkpoint_load(self._h, buf, ctypes.c_size_t(len(image))))
 
     def evolve(self, generations: int):
         self._check(self.lib.ffs_evolve(self._h, int(generations)))

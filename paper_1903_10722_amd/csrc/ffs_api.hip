@@ -27,7 +27,7 @@ struct HostIsland {
     ffs_island_spec spec;
     int size;
     int cell_base;
-    size_t off_genes[2], off_mk[2], off_genkey, off_minmax, off_sorted;
+    size_t off_genes[2], off_mk[2], off_genkey, off_minmax, off_sorted, off_sortbest;
 };
 
 struct HostInstance {
@@ -97,6 +97,7 @@ int round_mmax(int m)
 size_t al256(size_t x) { return (x + 255) & ~(size_t)255; }
 
 constexpr int kBatch = 4096;    // training minibatch of the pre-screen
+constexpr size_t kStageBytes = (size_t)4 << 20;   // staging of ffs_evaluate_host
 constexpr int kRing = 65536;    // replay ring entries
 constexpr float kLr = 1e-3f, kBeta1 = 0.9f, kBeta2 = 0.999f, kEps = 1e-8f;
 
@@ -121,6 +122,7 @@ struct ffs_ctx {
     std::string err;
     // layout
     size_t off_ctl = 0, off_insts = 0, off_isls = 0, off_work = 0, off_pairs = 0, off_counts = 0, total = 0;
+    size_t off_stage = 0;            // host-pointer decode: staged rows and results
     int max_work = 0;
     int n_isl = 0, n_work = 0, n_pairs = 0, max_size = 0, max_edges = 0, n_cls = 1;
     std::vector<int> cls_w0;         // work range of LDS class k: [cls_w0[k], cls_w0[k+1])
@@ -264,6 +266,9 @@ void layout(ffs_ctx* c)
     for (auto& w : c->work) c->cls_w0[c->inst[w.inst].cls + 1] += 1;
     for (int k = 0; k < c->n_cls; ++k) c->cls_w0[k + 1] += c->cls_w0[k];
     for (auto& I : c->inst) c->cls_lds[I.cls] = std::max(c->cls_lds[I.cls], I.lds);
+    // the first class's launch carries the best-ever workgroup, whose scratch
+    // is dynamic LDS too
+    if (c->n_cls > 0) c->cls_lds[0] = std::max(c->cls_lds[0], fold_lds_bytes(64 * c->wpb));
 
     c->off_ctl = take(sizeof(Control));
     c->off_insts = take(sizeof(InstDesc) * c->inst.size());
@@ -276,6 +281,7 @@ void layout(ffs_ctx* c)
     c->off_work = take(sizeof(WorkItem) * std::max<size_t>(1, max_work));
     c->max_work = (int)max_work;
     c->off_counts = take(sizeof(int) * (max_work + 16));
+    c->off_stage = take(kStageBytes);
     c->off_pairs = take(sizeof(PairDesc) * std::max<size_t>(1, c->pairs.size()));
     c->lds_gen = 0;
     for (auto& I : c->inst) {
@@ -291,9 +297,11 @@ void layout(ffs_ctx* c)
             L.off_genkey = take(16);
             L.off_minmax = take(16);
             L.off_sorted = take((size_t)L.size * sizeof(int));
+            L.off_sortbest = take(sizeof(int));
         }
         c->lds_gen = std::max(c->lds_gen, I.lds);
     }
+    c->lds_gen = std::max(c->lds_gen, fold_lds_bytes(64 * c->wpb));
     int R = 1;
     while (R * kSortThreads < c->max_size) R <<= 1;
     c->lds_sort = sort_lds_bytes(R);
@@ -634,6 +642,123 @@ int surrogate_score(ffs_ctx* c, float* Tout)
                        at<float>(c, c->o_yall), c->surr_K, at<int>(c, c->o_choice), c->surr_Nc);
 }
 
+// Decode `count` device rows of `perms` (int32 [count][n]) into out (int32 [count]).
+int launch_eval(ffs_ctx* c, int inst, const int32_t* perms, int count, int32_t* out)
+{
+    const auto& I = c->inst[inst];
+    const InstDesc* di = reinterpret_cast<const InstDesc*>(c->ws + c->off_insts) + inst;
+    Control* ctl = reinterpret_cast<Control*>(c->ws + c->off_ctl);
+    const int per_block = c->wpb * I.G;
+    const int blocks = (count + per_block - 1) / per_block;
+    const size_t lds = align16((size_t)I.S * ((size_t)I.n_pad * c->ptb + 4)) + (size_t)c->wpb * wave_lds_bytes(I.G, I.n_pad);
+    void* args[] = {(void*)&di, (void*)&perms, (void*)&count, (void*)&out, (void*)&ctl};
+    HIP_TRY(c, hipLaunchKernel(c->keval, dim3(blocks), dim3(64 * c->wpb), args, lds, c->stream));
+    return FFS_OK;
+}
+
+// Waits for the decodes and turns the control block's flags into a status
+// (clearing the invalid-row flag for the next call).
+int eval_status(ffs_ctx* c, int inst)
+{
+    Control h;
+    int rc = read_ctl(c, &h);
+    if (rc) return rc;
+    if (h.err & 2) return fail(c, FFS_EDEVICE, "decode kernel exceeded its step bound");
+    if (h.err & 1) {
+        h.err &= ~1;
+        HIP_TRY(c, hipMemcpyAsync(c->ws + c->off_ctl + offsetof(Control, err), &h.err, sizeof(int),
+                                  hipMemcpyHostToDevice, c->stream));
+        HIP_TRY(c, hipStreamSynchronize(c->stream));
+        return fail(c, FFS_EINVAL, "some rows are not permutations of 0..%d (makespan -1)", c->inst[inst].n - 1);
+    }
+    return FFS_OK;
+}
+
+// ---- checkpoint image --------------------------------------------------------
+// A flat byte string: header, then per instance the best-ever record, its
+// permutation (n_pad uint16), the migration counters, and per island the
+// genes (size * n_pad uint16) and makespans (size int32) of the current
+// generation's buffers; then, with a pre-screen, the Adam step count, the
+// FP32 parameters, both moments, the replay ring and the cells' choices.
+constexpr uint64_t kCkptMagic = 0x3154504B43534646ull;   // "FFSCKPT1"
+
+struct CkptHeader {
+    uint64_t magic, fingerprint, bytes;
+    int32_t generation, n_inst;
+};
+
+uint64_t fnv(uint64_t h, const void* p, size_t n)
+{
+    const unsigned char* b = static_cast<const unsigned char*>(p);
+    for (size_t i = 0; i < n; ++i) {
+        h ^= b[i];
+        h *= 0x100000001B3ull;
+    }
+    return h;
+}
+
+// Fingerprint of everything that defines the trajectory (not the tile shape).
+uint64_t fingerprint(const ffs_ctx* c)
+{
+    uint64_t h = 0xCBF29CE484222325ull;
+    for (const auto& I : c->inst) {
+        h = fnv(h, &I.n, sizeof I.n);
+        h = fnv(h, &I.S, sizeof I.S);
+        h = fnv(h, I.m.data(), I.m.size() * sizeof(int));
+        h = fnv(h, I.p.data(), I.p.size() * sizeof(int));
+        for (const auto& L : I.isl) {
+            const ffs_island_spec& s = L.spec;
+            const int32_t v[5] = {s.kind, s.rows, s.cols, L.size, s.selection};
+            h = fnv(h, v, sizeof v);
+            h = fnv(h, &s.p_c, sizeof s.p_c);
+            h = fnv(h, &s.p_m, sizeof s.p_m);
+        }
+        const int32_t cv[4] = {I.cfg.migration_interval, I.cfg.topology, I.cfg.surrogate_k, I.cfg.surrogate_warmup};
+        h = fnv(h, cv, sizeof cv);
+        h = fnv(h, &I.cfg.theta, sizeof I.cfg.theta);
+        h = fnv(h, &I.seed, sizeof I.seed);
+    }
+    return h;
+}
+
+size_t ckpt_bytes(const ffs_ctx* c)
+{
+    size_t b = sizeof(CkptHeader);
+    for (const auto& I : c->inst) {
+        b += 4 * sizeof(int32_t) + (size_t)I.n_pad * 2 + 2 * sizeof(int64_t);
+        for (const auto& L : I.isl) b += (size_t)L.size * I.n_pad * 2 + (size_t)L.size * 4;
+    }
+    if (c->surr >= 0)
+        b += sizeof(int64_t) + (size_t)3 * kParams * 4 + (size_t)kRing * kFeat * 2 + (size_t)kRing * 4 +
+             (size_t)c->surr_cells * 4;
+    return b;
+}
+
+// The (device offset, bytes) pieces of the image after the header, in order.
+std::vector<std::pair<size_t, size_t>> ckpt_pieces(const ffs_ctx* c)
+{
+    std::vector<std::pair<size_t, size_t>> v;
+    const int par = c->gen & 1;
+    for (const auto& I : c->inst) {
+        v.emplace_back(I.off_best_rec, 4 * sizeof(int32_t));
+        v.emplace_back(I.off_best_perm, (size_t)I.n_pad * 2);
+        v.emplace_back(I.off_counters, 2 * sizeof(int64_t));
+        for (const auto& L : I.isl) {
+            v.emplace_back(L.off_genes[par], (size_t)L.size * I.n_pad * 2);
+            v.emplace_back(L.off_mk[par], (size_t)L.size * 4);
+        }
+    }
+    if (c->surr >= 0) {
+        v.emplace_back(c->o_w, (size_t)kParams * 4);
+        v.emplace_back(c->o_m, (size_t)kParams * 4);
+        v.emplace_back(c->o_v, (size_t)kParams * 4);
+        v.emplace_back(c->o_ringX, (size_t)kRing * kFeat * 2);
+        v.emplace_back(c->o_ringT, (size_t)kRing * 4);
+        v.emplace_back(c->o_choice, (size_t)c->surr_cells * 4);
+    }
+    return v;
+}
+
 bool migration_due(const ffs_ctx* c, int g)
 {
     for (auto& I : c->inst)
@@ -895,6 +1020,7 @@ int ffs_bind_workspace(ffs_ctx* c, void* dptr, size_t bytes)
             e.genkey = reinterpret_cast<unsigned long long*>(c->ws + L.off_genkey);
             e.minmax = reinterpret_cast<unsigned long long*>(c->ws + L.off_minmax);
             e.sorted = reinterpret_cast<int*>(c->ws + L.off_sorted);
+            e.sortbest = reinterpret_cast<int*>(c->ws + L.off_sortbest);
             e.tc = rate_threshold(L.spec.p_c);
             e.tm = rate_threshold(L.spec.p_m);
             e.kind = L.spec.kind;
@@ -977,27 +1103,34 @@ int ffs_evaluate(ffs_ctx* c, int32_t inst, const int32_t* perms, int32_t count, 
     if (count < 0) return fail(c, FFS_EINVAL, "count must be >= 0");
     if (count == 0) return FFS_OK;
     if (!perms || !out) return fail(c, FFS_EINVAL, "null buffer");
-    const auto& I = c->inst[inst];
-    const InstDesc* di = reinterpret_cast<const InstDesc*>(c->ws + c->off_insts) + inst;
-    Control* ctl = reinterpret_cast<Control*>(c->ws + c->off_ctl);
-    const int per_block = c->wpb * I.G;
-    const int blocks = (count + per_block - 1) / per_block;
-    const size_t lds = align16((size_t)I.S * ((size_t)I.n_pad * c->ptb + 4)) + (size_t)c->wpb * wave_lds_bytes(I.G, I.n_pad);
-    void* args[] = {(void*)&di, (void*)&perms, (void*)&count, (void*)&out, (void*)&ctl};
-    HIP_TRY(c, hipLaunchKernel(c->keval, dim3(blocks), dim3(64 * c->wpb), args, lds, c->stream));
-    Control h;
-    rc = read_ctl(c, &h);
+    rc = launch_eval(c, inst, perms, count, out);
     if (rc) return rc;
-    if (h.err & 2) return fail(c, FFS_EDEVICE, "decode kernel exceeded its step bound");
-    if (h.err & 1) {
-        // clear the flag for the next call (small host-to-device copy)
-        h.err &= ~1;
-        HIP_TRY(c, hipMemcpyAsync(c->ws + c->off_ctl + offsetof(Control, err), &h.err, sizeof(int),
-                                  hipMemcpyHostToDevice, c->stream));
-        HIP_TRY(c, hipStreamSynchronize(c->stream));
-        return fail(c, FFS_EINVAL, "some rows are not permutations of 0..%d (makespan -1)", I.n - 1);
+    return eval_status(c, inst);
+}
+
+int ffs_evaluate_host(ffs_ctx* c, int32_t inst, const int32_t* perms, int32_t count, int32_t* out)
+{
+    int rc = check_bound(c);
+    if (rc) return rc;
+    if (inst < 0 || inst >= (int)c->inst.size()) return fail(c, FFS_EINVAL, "no instance %d", inst);
+    if (count < 0) return fail(c, FFS_EINVAL, "count must be >= 0");
+    if (count == 0) return FFS_OK;
+    if (!perms || !out) return fail(c, FFS_EINVAL, "null buffer");
+    const int n = c->inst[inst].n;
+    // rows per chunk: n int32 in, one int32 out, within the staging region
+    const size_t row_bytes = (size_t)n * 4 + 4;
+    const int chunk = (int)std::min<size_t>((size_t)count, (kStageBytes - 256) / row_bytes);
+    int32_t* dperm = reinterpret_cast<int32_t*>(c->ws + c->off_stage);
+    int32_t* dout = reinterpret_cast<int32_t*>(c->ws + c->off_stage + al256((size_t)chunk * n * 4));
+    for (int r0 = 0; r0 < count; r0 += chunk) {
+        const int rows = std::min(chunk, count - r0);
+        HIP_TRY(c, hipMemcpyAsync(dperm, perms + (size_t)r0 * n, (size_t)rows * n * 4, hipMemcpyHostToDevice,
+                                  c->stream));
+        rc = launch_eval(c, inst, dperm, rows, dout);
+        if (rc) return rc;
+        HIP_TRY(c, hipMemcpyAsync(out + r0, dout, (size_t)rows * 4, hipMemcpyDeviceToHost, c->stream));
     }
-    return FFS_OK;
+    return eval_status(c, inst);
 }
 
 int ffs_evolve(ffs_ctx* c, int32_t generations)
@@ -1287,6 +1420,96 @@ int ffs_surrogate_ring(ffs_ctx* c, int32_t inst, int32_t first, int32_t count, u
     if (t_host)
         HIP_TRY(c, hipMemcpyAsync(t_host, c->ws + c->o_ringT + (size_t)first * 4, (size_t)count * 4,
                                   hipMemcpyDeviceToHost, c->stream));
+    HIP_TRY(c, hipStreamSynchronize(c->stream));
+    return FFS_OK;
+}
+
+int ffs_checkpoint_size(ffs_ctx* c, size_t* bytes)
+{
+    int rc = check_bound(c);
+    if (rc) return rc;
+    if (!bytes) return fail(c, FFS_EINVAL, "null argument");
+    *bytes = ckpt_bytes(c);
+    return FFS_OK;
+}
+
+int ffs_checkpoint_save(ffs_ctx* c, void* host, size_t bytes)
+{
+    int rc = check_bound(c);
+    if (rc) return rc;
+    if (!host) return fail(c, FFS_EINVAL, "null buffer");
+    const size_t need = ckpt_bytes(c);
+    if (bytes < need) return fail(c, FFS_EINVAL, "checkpoint buffer too small: %zu < %zu", bytes, need);
+    // the records must include the current generation
+    rc = flush_best(c);
+    if (rc) return rc;
+    unsigned char* out = static_cast<unsigned char*>(host);
+    CkptHeader h;
+    memset(&h, 0, sizeof h);
+    h.magic = kCkptMagic;
+    h.fingerprint = fingerprint(c);
+    h.bytes = need;
+    h.generation = c->gen;
+    h.n_inst = (int32_t)c->inst.size();
+    memcpy(out, &h, sizeof h);
+    size_t pos = sizeof h;
+    for (const auto& pc : ckpt_pieces(c)) {
+        HIP_TRY(c, hipMemcpyAsync(out + pos, c->ws + pc.first, pc.second, hipMemcpyDeviceToHost, c->stream));
+        pos += pc.second;
+    }
+    if (c->surr >= 0) {
+        const int64_t st = c->adam_steps;
+        memcpy(out + pos, &st, sizeof st);
+    }
+    return check_faults(c);
+}
+
+int ffs_checkpoint_load(ffs_ctx* c, const void* host, size_t bytes)
+{
+    int rc = check_bound(c);
+    if (rc) return rc;
+    if (!host) return fail(c, FFS_EINVAL, "null buffer");
+    const size_t need = ckpt_bytes(c);
+    CkptHeader h;
+    if (bytes < sizeof h) return fail(c, FFS_EINVAL, "checkpoint too short");
+    memcpy(&h, host, sizeof h);
+    if (h.magic != kCkptMagic) return fail(c, FFS_EINVAL, "not a checkpoint image");
+    if (h.fingerprint != fingerprint(c) || h.n_inst != (int32_t)c->inst.size())
+        return fail(c, FFS_EINVAL, "checkpoint was taken from other instances");
+    if (h.bytes != need || bytes < need) return fail(c, FFS_EINVAL, "checkpoint size %zu, expected %zu", bytes, need);
+    if (h.generation < 0) return fail(c, FFS_EINVAL, "bad generation in checkpoint");
+    HIP_TRY(c, hipStreamSynchronize(c->stream));
+    c->gen = h.generation;
+    const unsigned char* in = static_cast<const unsigned char*>(host);
+    size_t pos = sizeof h;
+    for (const auto& pc : ckpt_pieces(c)) {
+        HIP_TRY(c, hipMemcpyAsync(c->ws + pc.first, in + pos, pc.second, hipMemcpyHostToDevice, c->stream));
+        pos += pc.second;
+    }
+    if (c->surr >= 0) {
+        int64_t st;
+        memcpy(&st, in + pos, sizeof st);
+        c->adam_steps = st;
+        hipLaunchKernelGGL(k_to_bf16, dim3((kParams + 255) / 256), dim3(256), 0, c->stream, at<const float>(c, c->o_w),
+                           at<uint16_t>(c, c->o_wb), kParams);
+        HIP_TRY(c, hipGetLastError());
+    }
+    // generation bookkeeping restarts at the loaded generation: no launches
+    // counted, records already hold it, island minima empty
+    std::vector<int> zeros(c->max_work + 16, 0);
+    HIP_TRY(c, hipMemcpyAsync(c->ws + c->off_counts, zeros.data(), zeros.size() * sizeof(int), hipMemcpyHostToDevice,
+                              c->stream));
+    Control ctl;
+    HIP_TRY(c, hipMemcpyAsync(&ctl, c->ws + c->off_ctl, sizeof ctl, hipMemcpyDeviceToHost, c->stream));
+    HIP_TRY(c, hipStreamSynchronize(c->stream));
+    ctl.base = c->gen;
+    ctl.best_gen = c->gen;
+    ctl.err = 0;
+    HIP_TRY(c, hipMemcpyAsync(c->ws + c->off_ctl, &ctl, sizeof ctl, hipMemcpyHostToDevice, c->stream));
+    const unsigned long long gk[2] = {~0ull, ~0ull};
+    for (const auto& I : c->inst)
+        for (const auto& L : I.isl)
+            HIP_TRY(c, hipMemcpyAsync(c->ws + L.off_genkey, gk, sizeof gk, hipMemcpyHostToDevice, c->stream));
     HIP_TRY(c, hipStreamSynchronize(c->stream));
     return FFS_OK;
 }

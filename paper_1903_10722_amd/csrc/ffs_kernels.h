@@ -59,6 +59,7 @@ struct IslandDesc {
     unsigned long long* genkey;  // [2]: min of (makespan << 32 | slot), by generation parity
     unsigned long long* minmax;  // [2] min / max keys (ring migration)
     int* sorted;                 // [size] slots by (makespan, slot) (migration)
+    int* sortbest;               // [1] island minimum makespan when `sorted` was built
     unsigned long long tc, tm;   // crossover / mutation thresholds (< tc, < tm)
     int kind, rows, cols, size;
     int inst;
@@ -736,7 +737,9 @@ __device__ __forceinline__ void features_group(const uint16_t* A, const PT* pT, 
 // island; a strictly better makespan replaces the record and copies the
 // permutation from generation g's population.  Resets the islands' keys of
 // g's parity for generation g + 2.  Run by one workgroup; s_tmp holds
-// 3 * blockDim.x ints.
+// 3 * blockDim.x ints (fold_lds_bytes).
+__host__ __device__ inline size_t fold_lds_bytes(int threads) { return (size_t)3 * sizeof(int) * threads; }
+
 __device__ void fold_best(const InstDesc* __restrict__ insts, const IslandDesc* __restrict__ isls, int n_inst,
                           int g, Control* ctl, int* s_tmp)
 {
@@ -1293,6 +1296,9 @@ __global__ void __launch_bounds__(kSortThreads) k_mig_sort(const InstDesc* __res
         mn = a < mn ? a : mn;
         mx = b > mx ? b : mx;
     }
+    // the island's best makespan, read by the migration decision (the rows
+    // that the migration rewrites cannot change it afterwards)
+    if (t == 0) L->sortbest[0] = (int)mn;
     const uint32_t span = mx - mn;   // N >= 1, so mn <= mx
     const int bits = span == 0u ? 0 : 32 - __clz((int)span);
 #pragma unroll
@@ -1372,7 +1378,10 @@ __global__ void __launch_bounds__(kSortThreads) k_mig_sort(const InstDesc* __res
 }
 
 // adaptive penetration rule of equations (1)-(2) on one island pair, and the
-// copy of the r-th best emigrant over the r-th worst immigrant
+// copy of the r-th best emigrant over the r-th worst immigrant.  Every block
+// of the pair takes the decision from the bests that k_mig_sort recorded
+// before any row moved, so all blocks agree whatever their order (when every
+// immigrant slot is replaced, the immigrant's best row itself is rewritten).
 constexpr int kMigRows = 32;
 
 __global__ void __launch_bounds__(256) k_mig_adapt(const InstDesc* __restrict__ insts,
@@ -1387,7 +1396,7 @@ __global__ void __launch_bounds__(256) k_mig_adapt(const InstDesc* __restrict__ 
     const IslandDesc* A = isls + pd.a;
     const IslandDesc* B = isls + pd.b;
     const int par = gen & 1;
-    const long long ba = A->mk[par][A->sorted[0]], bb = B->mk[par][B->sorted[0]];
+    const long long ba = A->sortbest[0], bb = B->sortbest[0];
     long long fa = I->E - ba, fb = I->E - bb;
     if (fa < 0) fa = 0;
     if (fb < 0) fb = 0;

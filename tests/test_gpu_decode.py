@@ -120,3 +120,26 @@ def test_instances_outside_limits_are_refused():
     with pytest.raises(FFSError):
         ctx.evolve(1)                                                      # not bound
     ctx.close()
+
+
+def test_host_pointer_decode_matches_device_decode():
+    """ffs_evaluate_host on host rows, in several staging chunks (1500 rows
+    of 1000 jobs exceed the 4 MiB staging region), equals the device-pointer
+    entry point and the oracle; invalid rows give -1 and FFS_EINVAL."""
+    ensure_built()
+    from paper_1903_10722_amd.binding import FFS_EINVAL, FFS_OK
+    w = _inst(1000, 20, 2, 6, seed=31)
+    perms = inputs.random_perms(1500, 1000, seed=7)
+    say("[decode] host pointers, 1500 rows of 1000 jobs")
+    ctx = make_ctx([w])
+    got, rc = ctx.evaluate_host(0, perms)
+    assert rc == FFS_OK
+    assert np.array_equal(got, ctx.evaluate(0, perms).cpu().numpy())
+    idx = np.array([0, 1, 700, 1048, 1049, 1050, 1499])
+    assert np.array_equal(got[idx], oracle.decode_many(w["m"], w["p"], perms[idx]))
+    bad = perms[:10].copy()
+    bad[4, 0] = bad[4, 1]
+    out, rc = ctx.evaluate_host(0, bad)
+    assert rc == FFS_EINVAL and out[4] == -1
+    assert np.array_equal(np.delete(out, 4), np.delete(got[:10], 4))
+    ctx.close()

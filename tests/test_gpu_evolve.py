@@ -272,31 +272,126 @@ def test_tile_change_after_bind_and_autotuner():
     ctx.close()
 
 
+def _parallel(fn, items, workers=None):
+    """Run independent oracle calls on worker threads (the C oracle releases
+    the GIL inside ctypes calls; every item has its own oracle object)."""
+    import os
+    from concurrent.futures import ThreadPoolExecutor
+    workers = workers or max(1, min(16, os.cpu_count() or 1))
+    with ThreadPoolExecutor(max_workers=workers) as ex:
+        return list(ex.map(fn, items))
+
+
+@pytest.mark.timeout(900)
 def test_batched_full_size_256_instances():
     """The uneven batch at full size: 256 instances (n in {20..500}, S in
     {5,10,20}, grids 32x32 .. 128x128) in one context, migration every 10.
-    After 10 generations (one epoch, graph-replayed) the 12 cheapest instances
-    match their oracle runs exactly; for 8 others, sampled individuals are
-    valid permutations whose stored makespans equal the oracle's decode."""
+    The GPU state after 9 generations is loaded into one oracle run per
+    instance; generation 10 and its migration epoch are then compared exactly
+    on every island of every instance."""
     ensure_built()
     ws = inputs.batched_workloads(count=256, batch_seed=7)
-    say("[evolve] batched full size, 256 instances")
+    say("[evolve] batched full size, 256 instances, all compared at generation 10")
     ctx = make_ctx(ws)
-    ctx.evolve(10)
-    cost = [w["p"].shape[0] * w["p"].shape[1] * w["islands"][0]["size"] for w in ws]
-    order = np.argsort(cost)
-    for i in order[:12]:
-        ga = oracle_ga(ws[i], inst=int(i))
-        ga.evolve(10)
-        assert_same_state(ctx, ga, int(i), 2, f"instance {i} n={ws[i]['p'].shape}")
-        assert ctx.best(int(i))["makespan"] == ga.best()["makespan"]
-    rng = np.random.default_rng(0)
-    for i in order[-8:]:
-        w = ws[int(i)]
+    ctx.evolve(9)
+    states = [[ctx.population(i, isl) for isl in range(2)] for i in range(len(ws))]
+    ctx.evolve(1)
+    assert ctx.generation == 10
+
+    import threading
+    done = [0]
+    lock = threading.Lock()
+
+    def oracle_gen10(i):
+        ga = oracle_ga(ws[i], inst=i)
         for isl in range(2):
-            genes, mk = ctx.population(int(i), isl)
-            rows = rng.choice(len(mk), 6, replace=False)
-            for r in rows:
-                assert sorted(genes[r].tolist()) == list(range(w["p"].shape[0]))
-            assert np.array_equal(mk[rows], oracle.decode_many(w["m"], w["p"], genes[rows]))
+            ga.set_population(isl, *states[i][isl])
+        ga.set_generation(9)
+        ga.evolve(1)
+        out = [ga.population(isl) for isl in range(2)]
+        del ga
+        with lock:
+            done[0] += 1
+            if done[0] % 32 == 0:
+                say(f"[evolve] batched: oracle done for {done[0]} of {len(ws)} instances")
+        return out
+
+    want = _parallel(oracle_gen10, range(len(ws)))
+    say("[evolve] batched: oracle generation 10 done")
+    for i in range(len(ws)):
+        for isl in range(2):
+            g1, m1 = ctx.population(i, isl)
+            g2, m2 = want[i][isl]
+            assert np.array_equal(m1, m2), f"instance {i} island {isl}: makespans differ"
+            assert np.array_equal(g1, g2), f"instance {i} island {isl}: genes differ"
+    ctx.close()
+
+
+@pytest.mark.timeout(300)
+def test_medium_full_trajectory_every_epoch():
+    """The benchmarked medium workload (n=100, S=5, 64x64 + 4096, migration
+    every 20) over its whole 500 generations, compared with the oracle at the
+    end of every migration epoch, with the best-ever record and counters."""
+    ensure_built()
+    w = inputs.workload("medium", seed=1)
+    say("[evolve] medium full size, 500 generations")
+    ctx = make_ctx([w])
+    ga = oracle_ga(w)
+    for e in range(25):
+        ctx.evolve(20)
+        ga.evolve(20)
+        assert_same_state(ctx, ga, 0, 2, f"generation {ctx.generation}")
+        b1, b2 = ctx.best(0), ga.best()
+        assert (b1["makespan"], b1["generation"]) == (b2["makespan"], b2["generation"])
+        assert b1["perm"].tolist() == b2["perm"].tolist()
+    assert ctx.generation == 500
+    assert ctx.migration_counters(0) == ga.counters()
+    ctx.close()
+
+
+@pytest.mark.timeout(600)
+def test_large_full_size_epoch_all_islands():
+    """The large workload at full size (8 cellular 128x128 + 8 pseudo 16384,
+    n=500, S=10, ring-then-adaptive every 20): the GPU state after 19
+    generations is loaded into the oracle; generation 20 with its migration
+    epoch (the ring over 16 islands, then the adaptive rule on each pair,
+    sorting 16384 slots per island) is compared on all 16 islands, and so is
+    one more forced epoch."""
+    ensure_built()
+    w = inputs.workload("large", seed=1)
+    say("[evolve] large full size, generation 20 epoch on 16 islands")
+    ctx = make_ctx([w])
+    ga = oracle_ga(w)
+    ctx.evolve(19)
+    for isl in range(16):
+        ga.set_population(isl, *ctx.population(0, isl))
+    ga.set_generation(19)
+    ctx.evolve(1)
+    ga.evolve(1)
+    say("[evolve] large: oracle generation 20 done")
+    assert_same_state(ctx, ga, 0, 16, "generation 20")
+    ctx.migrate(0)
+    ga.migrate()
+    assert_same_state(ctx, ga, 0, 16, "forced epoch")
+    ctx.close()
+
+
+def test_best_record_with_eight_waves_and_wide_stages():
+    """Forty stages leave one chromosome per wave, so a workgroup's LDS is
+    smaller than the best-ever fold's scratch at eight waves per workgroup;
+    the best record (makespan, generation, permutation) must still match."""
+    ensure_built()
+    m, p = inputs.make_instance(20, 40, 1, 3, seed=12)
+    isl = [inputs.cellular(3, 4, 0.9, 0.2), inputs.pseudo(12, 0.75, 0.1)]
+    w = dict(m=m, p=p, islands=isl, interval=4)
+    say("[evolve] n=20 S=40, 8 waves per workgroup")
+    ctx = make_ctx([w], waves_per_block=8)
+    ga = oracle_ga(w)
+    for g in (1, 3, 6, 10):
+        ctx.evolve(g)
+        ga.evolve(g)
+        assert_same_state(ctx, ga, 0, 2, f"generation {ctx.generation}")
+        b1, b2 = ctx.best(0), ga.best()
+        assert (b1["makespan"], b1["generation"]) == (b2["makespan"], b2["generation"])
+        assert b1["perm"].tolist() == b2["perm"].tolist()
     ctx.close()
