@@ -104,15 +104,18 @@ def test_forward_layers_match_fp64():
     torch.cuda.synchronize()
 
 
-def test_gradients_layers_match_fp64_and_adam_step():
+@pytest.mark.parametrize("M", [512, 4096])
+def test_gradients_layers_match_fp64_and_adam_step(M):
+    """Layer-wise backward and one Adam step; M = 4096 is the minibatch of
+    the online training step (the split-K weight-gradient GEMMs then sum 32
+    partial products)."""
     ensure_built()
     import torch
     w = _small(seed=2)
-    say("[surrogate] backward layer-wise + Adam")
+    say(f"[surrogate] backward layer-wise + Adam, {M} rows")
     ctx = _ctx(w)
     v0, P = _params(ctx)
     W2, w3 = _bf(P["W2"]), _bf(P["w3"])
-    M = 512
     X = _rand_features(M, 5)
     Xf = sg.bf16_to_f32(X).astype(np.float64)
     t = np.random.default_rng(6).random(M).astype(np.float32)
@@ -257,4 +260,49 @@ def test_trained_prescreen_picks_better_children():
     assert rho_within > 0.1
     assert gain > 0.0
     assert chosen.mean() < ex.mean()
+    ctx.close()
+
+
+@pytest.mark.timeout(600)
+def test_surrogate_workload_size_features_and_replay():
+    """The pre-screen at its own workload size (n=1000, S=20, m in [2,6],
+    64x64 + 4096, k=8): features and exact targets of sampled cells'
+    candidates are bit-exact at generation 0, and two screened generations
+    (after one warm-up generation) replay exactly on the oracle, with the
+    replay ring's rows of sampled cells."""
+    ensure_built()
+    w = inputs.workload("surrogate", seed=1)
+    say("[surrogate] workload size n=1000 S=20 64x64 k=8")
+    ctx = _ctx(w, k=8, warmup=1)
+    ga = oracle.GA(w["m"], w["p"], w["islands"], interval=w["interval"], seed=11)
+    LB = sg.lower_bound(w["m"], w["p"])
+    res = ctx.surrogate_candidates(exact=True, features=True)
+    genes0, mk0 = ga.population(0)
+    cells = list(range(0, 4096, 171)) + [4095]
+    for cell in cells:
+        for c in range(8):
+            child, meta = ga.cell_candidate(0, cell, c)
+            f = sg.features(w["m"], w["p"], child, int(mk0[meta[0]]), int(mk0[meta[1]]), meta)
+            assert np.array_equal(res["features"][cell, c], f), (cell, c)
+            assert res["exact"][cell, c] == sg.target(oracle.decode(w["m"], w["p"], child), LB), (cell, c)
+    assert (res["choice"] == np.argmin(res["pred"], axis=1)).all()
+    say("[surrogate] workload size: generation-0 candidates match")
+    for g in (1, 2, 3):
+        prev_genes, prev_mk = ga.population(0)
+        ctx.evolve(1)
+        ch = ctx.surrogate_choices() if g > 1 else np.zeros(4096, dtype=np.int32)
+        if g > 1:
+            ga.set_cell_choices(0, ch)
+        ga.evolve(1)
+        assert_same_state(ctx, ga, 0, 2, f"generation {g}")
+        X, t = ctx.surrogate_ring((g - 1) * 4096, 4096)
+        tmp = oracle.GA(w["m"], w["p"], w["islands"], interval=w["interval"], seed=11)
+        tmp.set_population(0, prev_genes, prev_mk)
+        tmp.set_generation(g - 1)
+        for cell in cells[:8]:
+            child, meta = tmp.cell_candidate(0, cell, int(ch[cell]))
+            f = sg.features(w["m"], w["p"], child, int(prev_mk[meta[0]]), int(prev_mk[meta[1]]), meta)
+            assert np.array_equal(X[cell], f), (g, cell)
+            assert t[cell] == sg.target(oracle.decode(w["m"], w["p"], child), LB)
+        say(f"[surrogate] workload size: generation {g} replayed")
     ctx.close()
