@@ -48,6 +48,8 @@ def parse():
     ap.add_argument("--prescreen-k", type=int, default=0,
                     help="run the timed steps with the learned pre-screen (k candidates per cell)")
     ap.add_argument("--waves-per-block", type=int, default=None)
+    ap.add_argument("--mapping", type=int, default=-1, choices=[-1, 0, 1],
+                    help="decode mapping: -1 automatic, 0 one lane per stage, 1 one lane per chromosome")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=12.0)
     ap.add_argument("--surrogate-seconds", type=float, default=8.0,
@@ -65,7 +67,7 @@ def parse():
     return ap.parse_args()
 
 
-KERNEL_SOURCES = ("ffs_kernels.h", "philox.h")
+KERNEL_SOURCES = ("ffs_kernels.h", "ffs_lane.h", "philox.h")
 TT_KERNEL_SOURCES = ("ffs_tt.hip", "philox.h")   # the paper-faithful variant's kernels
 
 
@@ -489,7 +491,7 @@ def main():
     m = w["m"]
     I = w["interval"]
     decodes_per_gen = sum(sum(x["size"] for x in v["islands"]) for v in ws)
-    ctx = Context(device=0, waves_per_block=args.waves_per_block)
+    ctx = Context(device=0, waves_per_block=args.waves_per_block, mapping=args.mapping)
     for v in ws:
         ctx.add_instance(v["m"], v["p"], v["islands"], interval=I, theta=v["theta"], topology=v["topology"], seed=101,
                          surrogate_k=args.prescreen_k, surrogate_warmup=5)
@@ -497,6 +499,7 @@ def main():
     ctx.bind()
     t_bind = time.perf_counter() - t_bind
     stream = ctx.stream
+    kernel = "k_generation_lane" if ctx.mapping() == 1 else "k_generation"
 
     for _ in range(args.warmup):
         ctx.evolve(I)
@@ -528,7 +531,7 @@ def main():
         # back to back as in the timed region: a context of the same instances
         # without migration replays graphs whose every node is a generation
         # launch; HIP events bracket the replays on the library's stream
-        ctx2 = Context(device=0, waves_per_block=args.waves_per_block)
+        ctx2 = Context(device=0, waves_per_block=args.waves_per_block, mapping=args.mapping)
         for v in ws:
             ctx2.add_instance(v["m"], v["p"], v["islands"], interval=0, theta=v["theta"], topology=v["topology"],
                               seed=101)
@@ -575,8 +578,8 @@ def main():
         "wall_s_timed": wall,
         "bind_and_generation0_s": t_bind,
         "roofline": {"bound": "alu", "achieved": achieved, "peak": PEAK_INT_TOPS, "unit": "TOP/s",
-                     "frac": achieved / PEAK_INT_TOPS, "traffic": recorded_traffic("k_generation", args.workload),
-                     "kernel": "k_generation", "avg_launch_us": avg_s * 1e6, "launches": launches, "timing": timing,
+                     "frac": achieved / PEAK_INT_TOPS, "traffic": recorded_traffic(kernel, args.workload),
+                     "kernel": kernel, "avg_launch_us": avg_s * 1e6, "launches": launches, "timing": timing,
                      "ops_per_launch": ops_per_launch},
     }
     if not args.no_cpu_baseline:

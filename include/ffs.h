@@ -136,6 +136,22 @@ int ffs_create_instance(ffs_ctx *ctx, int32_t n_jobs, int32_t n_stages,
  * workgroups; FFS_EUNSUPPORTED if the tile does not fit in LDS).            */
 int ffs_set_waves_per_block(ffs_ctx *ctx, int32_t waves);
 
+/* Lane mapping of the decode (Section 4.2: fitness evaluations are
+ * independent, so they can be spread over the GPU in any arrangement).
+ *   0: per stage -- a group of n_stages lanes decodes one chromosome, one
+ *      lane per stage, jobs handed from stage to stage between lanes;
+ *   1: per lane -- one lane decodes one chromosome through all stages;
+ *  -1: automatic (the default): per lane when every instance fits it and the
+ *      context holds at least 131072 individuals (ffs_evaluate: at least
+ *      65536 rows), per stage otherwise.
+ * The per-lane mapping needs at most 8 machines per stage, a sum of machine
+ * counts <= 160 and no pre-screen; otherwise per stage is used whatever the
+ * request.  Results never depend on the mapping.  May be called before or
+ * after ffs_bind_workspace (after: waits for the stream and re-plans).
+ * ffs_get_mapping reports the mapping the generation launches use (0 or 1). */
+int ffs_set_mapping(ffs_ctx *ctx, int32_t mapping);
+int ffs_get_mapping(const ffs_ctx *ctx, int32_t *used);
+
 /* ffs_evolve replays whole migration epochs (or chunks of 16 generations
  * when nothing migrates) from one captured HIP graph when enable != 0 (the
  * default), the stream is not the null stream, timing is off, and every

@@ -26,6 +26,7 @@ EXPORTS = [
     "ffs_surrogate_params", "ffs_surrogate_set_params", "ffs_mlp_forward", "ffs_mlp_gradients",
     "ffs_mlp_train_step", "ffs_surrogate_candidates", "ffs_surrogate_choices", "ffs_surrogate_ring",
     "ffs_evaluate_host", "ffs_checkpoint_size", "ffs_checkpoint_save", "ffs_checkpoint_load",
+    "ffs_set_mapping", "ffs_get_mapping",
 ]
 
 N_PARAMS = 394753
@@ -77,6 +78,8 @@ def load_library():
     lib.ffs_create_instance.argtypes = [P, i32, i32, pi32, pi32, ctypes.POINTER(IslandSpec), i32,
                                         ctypes.POINTER(GAConfig), u64, pi32]
     lib.ffs_set_waves_per_block.argtypes = [P, i32]
+    lib.ffs_set_mapping.argtypes = [P, i32]
+    lib.ffs_get_mapping.argtypes = [P, pi32]
     lib.ffs_workspace_size.argtypes = [P, ctypes.POINTER(ctypes.c_size_t)]
     lib.ffs_bind_workspace.argtypes = [P, P, ctypes.c_size_t]
     lib.ffs_evaluate.argtypes = [P, i32, P, i32, P]
@@ -124,7 +127,8 @@ class Context:
     Usage: add_instance(...) for every instance, then bind(), then evolve /
     evaluate / best / population."""
 
-    def __init__(self, device: int = 0, stream=None, waves_per_block: int | None = None):
+    def __init__(self, device: int = 0, stream=None, waves_per_block: int | None = None,
+                 mapping: int | None = None):
         import torch
         self._torch = torch
         self.lib = load_library()
@@ -139,6 +143,8 @@ class Context:
         self.instances = []
         if waves_per_block is not None:
             self._check(self.lib.ffs_set_waves_per_block(self._h, waves_per_block))
+        if mapping is not None:
+            self._check(self.lib.ffs_set_mapping(self._h, mapping))
 
     def _check(self, rc: int, h="self"):
         if rc != FFS_OK:
@@ -264,6 +270,16 @@ class Context:
 
     def set_waves_per_block(self, waves: int):
         self._check(self.lib.ffs_set_waves_per_block(self._h, int(waves)))
+
+    def set_mapping(self, mapping: int):
+        """-1 automatic, 0 one lane per stage, 1 one lane per chromosome (ffs_set_mapping)."""
+        self._check(self.lib.ffs_set_mapping(self._h, int(mapping)))
+
+    def mapping(self) -> int:
+        """Mapping the generation launches use: 0 per stage, 1 per lane."""
+        v = ctypes.c_int32()
+        self._check(self.lib.ffs_get_mapping(self._h, ctypes.byref(v)))
+        return v.value
 
     def set_graphs(self, enable: bool):
         self._check(self.lib.ffs_set_graphs(self._h, 1 if enable else 0))

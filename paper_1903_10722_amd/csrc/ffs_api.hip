@@ -18,6 +18,7 @@
 
 #include "ffs.h"
 #include "ffs_kernels.h"
+#include "ffs_lane.h"
 
 using namespace flowshop;
 
@@ -45,6 +46,9 @@ struct HostInstance {
     int edge0 = 0, n_edges = 0;   // topology 2: this instance's ring edges in the pair list
     int isl_base = 0;
     size_t lds = 0;               // LDS bytes of one generation workgroup
+    int gop = 1;                  // lane mapping: operator groups per wave
+    size_t lane_wlds = 0, lane_wlds_eval = 0;   // lane mapping: LDS bytes per wave
+    bool lane_ok = false;         // the lane mapping can run this instance
     int lds_bucket = 0, cls = 0;  // its LDS class
 };
 
@@ -57,6 +61,10 @@ template <int M, typename PT>
 void* eval_ptr() { return reinterpret_cast<void*>(&k_evaluate<M, PT>); }
 template <int M, typename PT>
 void* cand_ptr() { return reinterpret_cast<void*>(&k_candidates<M, PT>); }
+template <int M, typename PT>
+void* gen_lane_ptr() { return reinterpret_cast<void*>(&k_generation_lane<M, PT>); }
+template <int M, typename PT>
+void* eval_lane_ptr() { return reinterpret_cast<void*>(&k_evaluate_lane<M, PT>); }
 
 const int kMmaxList[] = {2, 3, 4, 5, 6, 8, 16};
 
@@ -87,6 +95,31 @@ void* pick_eval(int mm, int ptb)
     return nullptr;
 }
 
+// Lane-mapping kernels exist for machine counts up to 8.
+void* pick_gen_lane(int mm, int ptb)
+{
+#define FFS_CASE(M)                                                          \
+    if (mm == M) return ptb == 1 ? gen_lane_ptr<M, uint8_t>() : gen_lane_ptr<M, uint16_t>();
+    FFS_CASE(2) FFS_CASE(3) FFS_CASE(4) FFS_CASE(5) FFS_CASE(6) FFS_CASE(8)
+#undef FFS_CASE
+    return nullptr;
+}
+
+void* pick_eval_lane(int mm, int ptb)
+{
+#define FFS_CASE(M)                                                          \
+    if (mm == M) return ptb == 1 ? eval_lane_ptr<M, uint8_t>() : eval_lane_ptr<M, uint16_t>();
+    FFS_CASE(2) FFS_CASE(3) FFS_CASE(4) FFS_CASE(5) FFS_CASE(6) FFS_CASE(8)
+#undef FFS_CASE
+    return nullptr;
+}
+
+// Below this many individuals in a context the lane mapping leaves most
+// SIMDs idle (one wave per 64 individuals), and the per-stage lane mapping
+// of k_generation is chosen when the mapping is automatic.
+constexpr long long kLaneAutoMin = 131072;
+constexpr int kLaneEvalAutoMin = 65536;
+
 int round_mmax(int m)
 {
     for (int v : kMmaxList)
@@ -115,6 +148,8 @@ struct ffs_ctx {
     int device = 0;
     std::vector<HostInstance> inst;
     int wpb = 4;
+    int mapping = -1;            // requested decode mapping: -1 automatic, 0 per stage, 1 per lane
+    bool lane = false;           // generation launches use the lane mapping
     bool bound = false;
     char* ws = nullptr;
     size_t ws_bytes = 0;
@@ -197,13 +232,23 @@ void layout(ffs_ctx* c)
     }
     c->mm = round_mmax(mmax);
     c->ptb = (maxP <= 255) ? 1 : 2;
+    {
+        bool ok = c->mm <= 8;
+        long long total = 0;
+        for (auto& I : c->inst) {
+            ok = ok && I.lane_ok && I.cfg.surrogate_k <= 1;
+            for (auto& L : I.isl) total += L.size;
+        }
+        c->lane = ok && (c->mapping == 1 || (c->mapping < 0 && total >= kLaneAutoMin));
+    }
     // LDS classes: instances whose workgroups need LDS within the same
     // half-octave bucket (8 KB * sqrt(2)^b) share a launch sized for the
     // class, so small instances are not held to the occupancy of the
     // largest one
     std::vector<int> buckets;
     for (auto& I : c->inst) {
-        I.lds = align16((size_t)I.S * ((size_t)I.n_pad * c->ptb + 4)) + (size_t)c->wpb * wave_lds_bytes(I.G, I.n_pad);
+        I.lds = align16((size_t)I.S * ((size_t)I.n_pad * c->ptb + 4)) +
+                (size_t)c->wpb * (c->lane ? I.lane_wlds : wave_lds_bytes(I.G, I.n_pad));
         int b = 0;
         while ((size_t)(8192.0 * std::pow(1.41421356, (double)b)) < I.lds) ++b;
         I.lds_bucket = b;
@@ -220,7 +265,7 @@ void layout(ffs_ctx* c)
     int isl_base = 0;
     for (size_t ii = 0; ii < c->inst.size(); ++ii) {
         auto& I = c->inst[ii];
-        const int chunk = c->wpb * I.G;
+        const int chunk = c->wpb * (c->lane ? kWave : I.G);
         for (size_t x = 0; x < I.isl.size(); ++x) {
             for (int s0 = 0; s0 < I.isl[x].size; s0 += chunk) {
                 WorkItem w;
@@ -489,6 +534,8 @@ int apply_tile(ffs_ctx* c)
     layout(c);
     if (c->lds_gen > (size_t)max_lds)
         return fail(c, FFS_EUNSUPPORTED, "tile of %d waves needs %zu bytes of LDS (limit %d)", c->wpb, c->lds_gen, max_lds);
+    c->kgen = c->lane ? pick_gen_lane(c->mm, c->ptb) : pick_gen(c->mm, c->ptb);
+    if (!c->kgen) return fail(c, FFS_EUNSUPPORTED, "no kernel for %d machines", c->mm);
     HIP_TRY(c, hipFuncSetAttribute(c->kgen, hipFuncAttributeMaxDynamicSharedMemorySize, (int)c->lds_gen));
     if (c->n_work)
         HIP_TRY(c, hipMemcpy(c->ws + c->off_work, c->work.data(), sizeof(WorkItem) * c->work.size(),
@@ -648,11 +695,14 @@ int launch_eval(ffs_ctx* c, int inst, const int32_t* perms, int count, int32_t* 
     const auto& I = c->inst[inst];
     const InstDesc* di = reinterpret_cast<const InstDesc*>(c->ws + c->off_insts) + inst;
     Control* ctl = reinterpret_cast<Control*>(c->ws + c->off_ctl);
-    const int per_block = c->wpb * I.G;
+    void* kl = I.lane_ok ? pick_eval_lane(c->mm, c->ptb) : nullptr;
+    const bool lane = kl && (c->mapping == 1 || (c->mapping < 0 && count >= kLaneEvalAutoMin));
+    const int per_block = c->wpb * (lane ? kWave : I.G);
     const int blocks = (count + per_block - 1) / per_block;
-    const size_t lds = align16((size_t)I.S * ((size_t)I.n_pad * c->ptb + 4)) + (size_t)c->wpb * wave_lds_bytes(I.G, I.n_pad);
+    const size_t lds = align16((size_t)I.S * ((size_t)I.n_pad * c->ptb + 4)) +
+                       (size_t)c->wpb * (lane ? I.lane_wlds_eval : wave_lds_bytes(I.G, I.n_pad));
     void* args[] = {(void*)&di, (void*)&perms, (void*)&count, (void*)&out, (void*)&ctl};
-    HIP_TRY(c, hipLaunchKernel(c->keval, dim3(blocks), dim3(64 * c->wpb), args, lds, c->stream));
+    HIP_TRY(c, hipLaunchKernel(lane ? kl : c->keval, dim3(blocks), dim3(64 * c->wpb), args, lds, c->stream));
     return FFS_OK;
 }
 
@@ -888,6 +938,13 @@ int ffs_create_instance(ffs_ctx* c, int32_t n, int32_t S, const int32_t* machine
         I.LB = std::max(I.LB, (I.Pk[k] + I.m[k] - 1) / I.m[k]);
         I.msum += I.m[k];
     }
+    // lane mapping: operator groups per wave so that their rows stay within
+    // 16 KB; the decode keeps msum keys per lane in LDS
+    I.gop = 8;
+    while (I.gop > 1 && (size_t)I.gop * group_stride(I.n_pad) * 2 > 16384) I.gop >>= 1;
+    I.lane_wlds = lane_gen_wave_lds(I.gop, I.n_pad, I.msum);
+    I.lane_wlds_eval = lane_eval_wave_lds(n, I.msum);
+    I.lane_ok = I.msum <= kLaneMaxMsum && I.mmax <= 8;
     I.n_cells = 0;
     for (auto& L : I.isl) {
         L.cell_base = (L.spec.kind == 0) ? I.n_cells : -1;
@@ -928,6 +985,33 @@ int ffs_set_waves_per_block(ffs_ctx* c, int32_t waves)
     return FFS_OK;
 }
 
+int ffs_set_mapping(ffs_ctx* c, int32_t mapping)
+{
+    if (!c) return FFS_EINVAL;
+    if (mapping < -1 || mapping > 1) return fail(c, FFS_EINVAL, "mapping must be -1, 0 or 1");
+    if (!c->bound) {
+        c->mapping = mapping;
+        return FFS_OK;
+    }
+    HIP_TRY(c, hipStreamSynchronize(c->stream));
+    const int old = c->mapping;
+    c->mapping = mapping;
+    int rc = apply_tile(c);
+    if (rc) {
+        c->mapping = old;
+        (void)apply_tile(c);
+        return rc;
+    }
+    return FFS_OK;
+}
+
+int ffs_get_mapping(const ffs_ctx* c, int32_t* used)
+{
+    if (!c || !used) return FFS_EINVAL;
+    *used = c->lane ? 1 : 0;
+    return FFS_OK;
+}
+
 int ffs_workspace_size(const ffs_ctx* cc, size_t* bytes)
 {
     ffs_ctx* c = const_cast<ffs_ctx*>(cc);
@@ -957,11 +1041,13 @@ int ffs_bind_workspace(ffs_ctx* c, void* dptr, size_t bytes)
         return fail(c, FFS_EUNSUPPORTED, "instance needs %zu bytes of LDS per workgroup (limit %d)", c->lds_gen, max_lds);
     if (c->lds_sort > (size_t)max_lds)
         return fail(c, FFS_EUNSUPPORTED, "island sort needs %zu bytes of LDS (limit %d)", c->lds_sort, max_lds);
-    c->kgen = pick_gen(c->mm, c->ptb);
+    c->kgen = c->lane ? pick_gen_lane(c->mm, c->ptb) : pick_gen(c->mm, c->ptb);
     c->keval = pick_eval(c->mm, c->ptb);
     if (!c->kgen || !c->keval) return fail(c, FFS_EUNSUPPORTED, "no kernel for %d machines", c->mm);
     HIP_TRY(c, hipFuncSetAttribute(c->kgen, hipFuncAttributeMaxDynamicSharedMemorySize, (int)c->lds_gen));
     HIP_TRY(c, hipFuncSetAttribute(c->keval, hipFuncAttributeMaxDynamicSharedMemorySize, max_lds));
+    if (void* kl = pick_eval_lane(c->mm, c->ptb))
+        HIP_TRY(c, hipFuncSetAttribute(kl, hipFuncAttributeMaxDynamicSharedMemorySize, max_lds));
     HIP_TRY(c, hipFuncSetAttribute(reinterpret_cast<const void*>(&k_mig_sort),
                                    hipFuncAttributeMaxDynamicSharedMemorySize, (int)c->lds_sort));
     c->ws = reinterpret_cast<char*>(dptr);
@@ -998,6 +1084,9 @@ int ffs_bind_workspace(ffs_ctx* c, void* dptr, size_t bytes)
         }
         d.LB = (int)I.LB;
         d.msum = I.msum;
+        d.gop = I.gop;
+        d.lane_wlds = (int)I.lane_wlds;
+        d.lane_wlds_eval = (int)I.lane_wlds_eval;
         d.n_cells = I.n_cells;
         d.surr_k = (c->surr == (int)ii) ? c->surr_K : 0;
         d.surr_warmup = I.cfg.surrogate_warmup;

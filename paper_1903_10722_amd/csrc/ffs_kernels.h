@@ -49,6 +49,8 @@ struct InstDesc {
     uint16_t* ring_X;            // [ring_size][256] features of decoded children
     float* ring_T;               // [ring_size] (C - LB) / LB
     int LB, msum;
+    int gop;                     // lane mapping: operator groups per wave
+    int lane_wlds, lane_wlds_eval;   // lane mapping: LDS bytes per wave (generation, ffs_evaluate)
     int mach[kMaxStages];
     int Pk[kMaxStages];          // sum over jobs of p[j][k]
 };
@@ -409,7 +411,8 @@ __device__ __forceinline__ void build_ap(uint32_t* AP, const uint16_t* A, const 
 // b+1, ..., n-1, 0, ..., a-1 with the genes not in the segment.  Lane k of
 // the group owns the cyclic offsets [kC, kC + C) of P2 (C = ceil(n / S)):
 // it counts the genes it keeps, an exclusive scan over the group's lanes
-// gives its first destination, and a second pass writes them.
+// gives its first destination, and a second pass writes them.  With LEAN
+// only the two-pass path below is compiled (fewest registers).
 __device__ __forceinline__ uint32_t wrap_sub(uint32_t x, uint32_t n)
 {
     const uint32_t y = x - n;   // x < 2n: x mod n
@@ -432,13 +435,14 @@ __device__ __forceinline__ int group_exclusive_scan(int v, int k, int S)
     return incl - v;
 }
 
+template <bool LEAN = false>
 __device__ __forceinline__ void ox_group(uint16_t* A, const uint16_t* B, uint16_t* V, int n, int a, int b,
                                          bool doit, int k, int S, int g)
 {
     const uint32_t un = (uint32_t)n, ua = (uint32_t)a, ub = (uint32_t)b;
     const int C = (n + S - 1) / S;
     const int o0 = k * C, o1 = (o0 + C < n) ? o0 + C : n;
-    if (C <= kOxReg) {
+    if (!LEAN && C <= kOxReg) {
         // lane k: positions [o0, o1) of parent 1 and cyclic offsets [o0, o1) of parent 2
         uint32_t x1[kOxReg], x2[kOxReg];
 #pragma unroll
@@ -475,7 +479,7 @@ __device__ __forceinline__ void ox_group(uint16_t* A, const uint16_t* B, uint16_
         wave_sync();
         return;
     }
-    if (C <= kOxMid) {
+    if (!LEAN && C <= kOxMid) {
         // P2's genes held in registers between the count and the write
         constexpr int U = 8;
         if (doit) {
@@ -591,6 +595,7 @@ struct CellMeta {
 // (sub 0 is the plain GA's stream): parents = the two best of (self, N, E,
 // S, W) by (makespan, that order) in generation gen-1, then order crossover
 // and swap mutation on the group's LDS rows.  A receives the child.
+template <bool LEAN = false>
 __device__ __forceinline__ CellMeta cellular_offspring(const InstDesc* I, const IslandDesc* L, int slot, uint32_t sub,
                                                    int gen, int cur, uint16_t* A, uint16_t* B, uint16_t* V, int k,
                                                    int S, int g, bool active)
@@ -670,7 +675,7 @@ __device__ __forceinline__ CellMeta cellular_offspring(const InstDesc* I, const 
     const uint16_t* gp = L->genes[cur];
     if (active) rows_g2l(A, gp + (size_t)bs * n_pad, B, gp + (size_t)ss * n_pad, n_pad, k, S);
     wave_sync();
-    ox_group(A, B, V, n, a, b, cx && active, k, S, g);
+    ox_group<LEAN>(A, B, V, n, a, b, cx && active, k, S, g);
     swap_genes(A, mx && active && k == 0, mi, mj);
     CellMeta meta;
     meta.mk1 = bv;
@@ -729,6 +734,104 @@ __device__ __forceinline__ void features_group(const uint16_t* A, const PT* pT, 
         }
         out[e] = f32_to_bf16(v);
     }
+}
+
+// The chromosome of `slot` at generation `gen`, built in row A of a group of
+// S lanes (lane k) with B and V as scratch: generation 0 (mode 1) draws it;
+// a cellular cell gets the child of its neighbourhood's two best from
+// candidate stream `sub`; a pseudo slot gets its pair's complementary child.
+template <bool LEAN = false>
+__device__ __forceinline__ CellMeta make_child(const InstDesc* I, const IslandDesc* L, int slot, uint32_t sub,
+                                               int gen, int cur, int mode, uint16_t* A, uint16_t* B, uint16_t* V,
+                                               int k, int S, int g, bool active)
+{
+    const int n = I->n, n_pad = I->n_pad;
+    const uint64_t seed = I->seed, iid = (uint64_t)I->inst_id;
+    const uint32_t isl_local = (uint32_t)L->local;
+    CellMeta meta{};
+    if (mode == 1) {
+        // generation 0: Fisher-Yates from the INIT stream; a pseudo pair is a
+        // permutation (even slot) and its reversal (odd slot).
+        const int fy_slot = (L->kind == 0) ? slot : (slot >> 1);
+        const bool rev = (L->kind == 1) && (slot & 1);
+        uint32_t* D = reinterpret_cast<uint32_t*>(B);   // B..V: n_pad words >= n - 1
+        const int nblk = (n - 1 + 7) / 8;
+        if (active) {
+            for (int blk = k; blk < nblk; blk += S) {
+                const Block4 bb = stream_block(seed, iid, isl_local, (uint32_t)fy_slot, 0, 0, kInit, (uint32_t)blk);
+#pragma unroll
+                for (int d = 0; d < 8; ++d) {
+                    const int idx = blk * 8 + d;
+                    if (idx < n - 1) D[idx] = draw32(bb, d);
+                }
+            }
+            for (int t = k; t < n; t += S) A[t] = (uint16_t)t;
+        }
+        wave_sync();
+        if (active && k == 0) {
+            for (int i = n - 1; i >= 1; --i) {
+                const int j = (int)below(D[n - 1 - i], (uint32_t)(i + 1));
+                const uint16_t x = A[i], y = A[j];
+                A[i] = y;
+                A[j] = x;
+            }
+        }
+        wave_sync();
+        if (active && rev) {
+            for (int t = k; t < n / 2; t += S) {
+                const uint16_t x = A[t], y = A[n - 1 - t];
+                A[t] = y;
+                A[n - 1 - t] = x;
+            }
+        }
+        wave_sync();
+    } else if (L->kind == 0) {
+        meta = cellular_offspring<LEAN>(I, L, slot, sub, gen, cur, A, B, V, k, S, g, active);
+    } else {
+        // pseudo: X = better of the pair, Y = reverse(X); even slot gets
+        // OX(X, Y), odd slot OX(Y, X), with shared cut points.
+        const auto* mkp = as_global(L->mk[cur]);
+        const int q = slot >> 1;
+        const bool odd = slot & 1;
+        const int xs = (mkp[2 * q] <= mkp[2 * q + 1]) ? 2 * q : 2 * q + 1;
+        const Block4 b0 = stream_block(seed, iid, isl_local, (uint32_t)q, 0, (uint32_t)gen, kPair, 0);
+        const Block4 b1 = stream_block(seed, iid, isl_local, (uint32_t)q, 0, (uint32_t)gen, kPair, 1);
+        const bool cx = (uint64_t)draw32(b0, 0) < L->tc;
+        const int u = (int)below(draw32(b0, 1), (uint32_t)n), w = (int)below(draw32(b0, 2), (uint32_t)n);
+        const int a = u < w ? u : w, b = u < w ? w : u;
+        const uint32_t dm = odd ? draw32(b0, 6) : draw32(b0, 3);
+        const uint32_t di = odd ? draw32(b0, 7) : draw32(b0, 4);
+        const uint32_t dj = odd ? draw32(b1, 0) : draw32(b0, 5);
+        const bool mx = (uint64_t)dm < L->tm;
+        const int mi = (int)below(di, (uint32_t)n);
+        int mj = mi + 1 + (int)below(dj, (uint32_t)(n - 1));
+        if (mj >= n) mj -= n;
+        if (active) row_g2l(V, L->genes[cur] + (size_t)xs * n_pad, n_pad, k, S);
+        wave_sync();
+        if (active) {
+            constexpr int U = 4;
+            for (int t0 = k; t0 < n; t0 += U * S) {
+                uint16_t x[U], xr[U];
+#pragma unroll
+                for (int u = 0; u < U; ++u) {
+                    const int t = t0 + u * S < n ? t0 + u * S : n - 1;
+                    x[u] = V[t];
+                    xr[u] = V[n - 1 - t];
+                }
+#pragma unroll
+                for (int u = 0; u < U; ++u) {
+                    const int t = t0 + u * S < n ? t0 + u * S : n - 1;
+                    A[t] = odd ? xr[u] : x[u];
+                    B[t] = odd ? x[u] : xr[u];
+                }
+            }
+        }
+        wave_sync();
+        ox_group<LEAN>(A, B, V, n, a, b, cx && active, k, S, g);
+        swap_genes(A, mx && active && k == 0, mi, mj);
+    }
+
+    return meta;
 }
 
 // ---- best-ever records ------------------------------------------------------
@@ -861,93 +964,10 @@ __global__ void __launch_bounds__(512) k_generation(const InstDesc* __restrict__
     uint16_t* V = B + n_pad;
     const int slot = wi.slot0 + (active ? local : 0);
     const PT* prow_next = pT + (size_t)(k + 1 < S ? k + 1 : S - 1) * pt_stride<PT>(n_pad);
-    const uint64_t seed = I->seed, iid = (uint64_t)I->inst_id;
-    const uint32_t isl_local = (uint32_t)L->local;
 
-    CellMeta meta{};
-    if (mode == 1) {
-        // generation 0: Fisher-Yates from the INIT stream; a pseudo pair is a
-        // permutation (even slot) and its reversal (odd slot).
-        const int fy_slot = (L->kind == 0) ? slot : (slot >> 1);
-        const bool rev = (L->kind == 1) && (slot & 1);
-        uint32_t* D = reinterpret_cast<uint32_t*>(B);   // B..V: n_pad words >= n - 1
-        const int nblk = (n - 1 + 7) / 8;
-        if (active) {
-            for (int blk = k; blk < nblk; blk += S) {
-                const Block4 bb = stream_block(seed, iid, isl_local, (uint32_t)fy_slot, 0, 0, kInit, (uint32_t)blk);
-#pragma unroll
-                for (int d = 0; d < 8; ++d) {
-                    const int idx = blk * 8 + d;
-                    if (idx < n - 1) D[idx] = draw32(bb, d);
-                }
-            }
-            for (int t = k; t < n; t += S) A[t] = (uint16_t)t;
-        }
-        wave_sync();
-        if (active && k == 0) {
-            for (int i = n - 1; i >= 1; --i) {
-                const int j = (int)below(D[n - 1 - i], (uint32_t)(i + 1));
-                const uint16_t x = A[i], y = A[j];
-                A[i] = y;
-                A[j] = x;
-            }
-        }
-        wave_sync();
-        if (active && rev) {
-            for (int t = k; t < n / 2; t += S) {
-                const uint16_t x = A[t], y = A[n - 1 - t];
-                A[t] = y;
-                A[n - 1 - t] = x;
-            }
-        }
-        wave_sync();
-    } else if (L->kind == 0) {
-        const bool screened = I->surr_k > 1 && gen > I->surr_warmup;
-        const uint32_t sub = screened ? (uint32_t)I->surr_choice[L->cell_base + slot] : 0u;
-        meta = cellular_offspring(I, L, slot, sub, gen, cur, A, B, V, k, S, g, active);
-    } else {
-        // pseudo: X = better of the pair, Y = reverse(X); even slot gets
-        // OX(X, Y), odd slot OX(Y, X), with shared cut points.
-        const auto* mkp = as_global(L->mk[cur]);
-        const int q = slot >> 1;
-        const bool odd = slot & 1;
-        const int xs = (mkp[2 * q] <= mkp[2 * q + 1]) ? 2 * q : 2 * q + 1;
-        const Block4 b0 = stream_block(seed, iid, isl_local, (uint32_t)q, 0, (uint32_t)gen, kPair, 0);
-        const Block4 b1 = stream_block(seed, iid, isl_local, (uint32_t)q, 0, (uint32_t)gen, kPair, 1);
-        const bool cx = (uint64_t)draw32(b0, 0) < L->tc;
-        const int u = (int)below(draw32(b0, 1), (uint32_t)n), w = (int)below(draw32(b0, 2), (uint32_t)n);
-        const int a = u < w ? u : w, b = u < w ? w : u;
-        const uint32_t dm = odd ? draw32(b0, 6) : draw32(b0, 3);
-        const uint32_t di = odd ? draw32(b0, 7) : draw32(b0, 4);
-        const uint32_t dj = odd ? draw32(b1, 0) : draw32(b0, 5);
-        const bool mx = (uint64_t)dm < L->tm;
-        const int mi = (int)below(di, (uint32_t)n);
-        int mj = mi + 1 + (int)below(dj, (uint32_t)(n - 1));
-        if (mj >= n) mj -= n;
-        if (active) row_g2l(V, L->genes[cur] + (size_t)xs * n_pad, n_pad, k, S);
-        wave_sync();
-        if (active) {
-            constexpr int U = 4;
-            for (int t0 = k; t0 < n; t0 += U * S) {
-                uint16_t x[U], xr[U];
-#pragma unroll
-                for (int u = 0; u < U; ++u) {
-                    const int t = t0 + u * S < n ? t0 + u * S : n - 1;
-                    x[u] = V[t];
-                    xr[u] = V[n - 1 - t];
-                }
-#pragma unroll
-                for (int u = 0; u < U; ++u) {
-                    const int t = t0 + u * S < n ? t0 + u * S : n - 1;
-                    A[t] = odd ? xr[u] : x[u];
-                    B[t] = odd ? x[u] : xr[u];
-                }
-            }
-        }
-        wave_sync();
-        ox_group(A, B, V, n, a, b, cx && active, k, S, g);
-        swap_genes(A, mx && active && k == 0, mi, mj);
-    }
+    const bool screened = mode == 0 && L->kind == 0 && I->surr_k > 1 && gen > I->surr_warmup;
+    const uint32_t sub = screened ? (uint32_t)I->surr_choice[L->cell_base + slot] : 0u;
+    const CellMeta meta = make_child(I, L, slot, sub, gen, cur, mode, A, B, V, k, S, g, active);
 
     uint32_t* AP = reinterpret_cast<uint32_t*>(B);   // B..V: n_pad words
     build_ap<PT>(AP, A, pT, n, jb, k, S, active);

@@ -1,0 +1,408 @@
+// ffs_lane.h -- lane-per-chromosome mapping of the decode and of the
+// generation step, for populations large enough to fill the chip with it.
+//
+// The decode (the list-scheduling rule of include/ffs.h over the Section 3
+// problem) runs one chromosome per lane.  A lane walks every stage itself,
+// so the stage that runs is the same on all 64 lanes of a wave: the
+// insertion network of a stage has exactly m_k entries (a branch on the
+// wave-uniform m_k), and nothing moves between lanes.
+//
+// Slots.  Stage k dispatches its n jobs at slots off_k .. off_k + n - 1
+// (off_k = m_0 + ... + m_{k-1}); the key it removes at a dispatch (the
+// machine's previous job, completion << jb | job) is written back to the
+// slot it read, so the slot sequence of stage k's writes is its release
+// order.  The first m_k of them are the machines' initial empty entries;
+// after its last dispatch the stage writes its remaining entries, in order,
+// to slots off_k + n .. off_k + n + m_k - 1.  Stage k + 1 therefore reads
+// exactly its input order at slots off_{k+1} .. off_{k+1} + n - 1.
+// Entries of one stage leave in (completion, dispatch order) order -- the
+// first-in-first-out rule at the next stage -- because a newly dispatched
+// job is inserted after every entry whose completion is not later than its
+// own.
+//
+// Windows.  The slots are processed in windows of kLaneD held in registers:
+// for each window, stage 0, 1, ..., S-1 in turn transform the window in
+// place.  A stage's m_k sorted keys stay in LDS between windows.  Windows
+// that lie inside a stage's dispatch range run unguarded; the first and
+// last windows of a stage run with per-slot (wave-uniform) guards.
+//
+// The generation kernel of this mapping builds each wave's 64 children with
+// the operators of ffs_kernels.h on groups of lanes (W = 64 / gop lanes per
+// group), writes them to the next generation's rows, decodes them one per
+// lane from there, then writes back the parent's row of every cellular cell
+// whose child is not strictly better.
+#pragma once
+#include "ffs_kernels.h"
+
+namespace flowshop {
+
+constexpr int kLaneD = 16;           // slots per window
+constexpr int kLaneMaxMsum = 160;    // machine entries per lane (sum over stages) kept in LDS
+
+// LDS of one wave of the lane generation kernel: the operators' rows of
+// `gop` groups, later reused for the decode state (64 lanes x msum keys).
+__host__ __device__ inline size_t lane_gen_wave_lds(int gop, int n_pad, int msum)
+{
+    const size_t ops = (size_t)gop * group_stride(n_pad) * 2;
+    const size_t st = (size_t)64 * msum * 4;
+    return align16(ops > st ? ops : st);
+}
+
+// LDS of one wave of the lane decode of caller-supplied rows: the per-lane
+// bit sets of the validity check, later reused for the decode state.
+__host__ __device__ inline size_t lane_eval_wave_lds(int n, int msum)
+{
+    const size_t st = (size_t)64 * msum * 4;
+    const size_t seen = (size_t)64 * ((n + 31) / 32) * 4;
+    return align16(st > seen ? st : seen);
+}
+
+// One stage over one window.  r[i] holds slot lo + i: a key
+// (completion << jb | job) from the previous stage, or a gene at stage 0
+// (completion 0).  With GUARD, slot i dispatches only if bit i of `act` is
+// set, and if bit i of `fl` is set it receives the list's first entry,
+// which leaves the list (the flush after the last dispatch); job indices
+// are clamped to n - 1 for the table read.
+template <int M, bool GUARD, typename PT>
+__device__ __forceinline__ void lane_stage(uint32_t (&r)[kLaneD], uint32_t (&key)[M], const PT* prow,
+                                           uint32_t jb, uint32_t jmask, uint32_t act, uint32_t fl, uint32_t nmax)
+{
+    uint32_t jj[kLaneD], pj[kLaneD];
+#pragma unroll
+    for (int i = 0; i < kLaneD; ++i) {
+        const uint32_t j = r[i] & jmask;
+        jj[i] = GUARD ? (j < nmax ? j : nmax) : j;
+    }
+#pragma unroll
+    for (int i = 0; i < kLaneD; ++i) pj[i] = (uint32_t)prow[jj[i]];
+#pragma unroll
+    for (int i = 0; i < kLaneD; ++i) {
+        if (!GUARD || ((act >> i) & 1u)) {
+            const uint32_t o = key[0];
+            const uint32_t f = o >> jb, rd = r[i] >> jb;
+            const uint32_t c = (f > rd ? f : rd) + pj[i];
+            const uint32_t nk = (c << jb) | jj[i];
+            if (M == 1) {
+                key[0] = nk;
+            } else {
+                // drop entry 0, insert nk after every entry with completion <= c
+                const uint32_t thr = (c + 1u) << jb;
+                uint32_t nkey[M];
+                bool prev = true;
+#pragma unroll
+                for (int q = 0; q + 1 < M; ++q) {
+                    const bool lt = key[q + 1] < thr;
+                    nkey[q] = lt ? key[q + 1] : (prev ? nk : key[q]);
+                    prev = lt;
+                }
+                nkey[M - 1] = prev ? nk : key[M - 1];
+#pragma unroll
+                for (int q = 0; q < M; ++q) key[q] = nkey[q];
+            }
+            r[i] = o;
+        } else if (GUARD && ((fl >> i) & 1u)) {
+            r[i] = key[0];
+#pragma unroll
+            for (int q = 0; q + 1 < M; ++q) key[q] = key[q + 1];
+        }
+    }
+}
+
+// Stage k (m_k = M) over window [lo, lo + kLaneD): its dispatch slots are
+// [d0, d0 + n), its flush slots [d0 + n, d0 + n + M) unless it is the last
+// stage.  Keys live at st[q * 64] (q < M) between windows (during a flush
+// that spans two windows, the entries not yet written, first at q = 0).  Returns the
+// makespan on the last window of the last stage, else 0.
+template <int M, typename PT>
+__device__ __forceinline__ uint32_t lane_stage_window(uint32_t (&r)[kLaneD], uint32_t* st, const PT* prow, int lo,
+                                                      int d0, int n, bool last, uint32_t jb, uint32_t jmask)
+{
+    const int d1 = d0 + n, end = last ? d1 : d1 + M;
+    uint32_t key[M];
+    if (d0 >= lo) {
+#pragma unroll
+        for (int q = 0; q < M; ++q) key[q] = 0u;
+    } else {
+#pragma unroll
+        for (int q = 0; q < M; ++q) key[q] = st[q * 64];
+    }
+    if (d0 <= lo && lo + kLaneD <= d1) {
+        lane_stage<M, false, PT>(r, key, prow, jb, jmask, 0u, 0u, 0u);
+    } else {
+        const int a0 = d0 > lo ? d0 - lo : 0, a1 = (d1 < lo + kLaneD ? d1 : lo + kLaneD) - lo;
+        const uint32_t act = (a1 > a0) ? ((0xFFFFFFFFu >> (32 - (a1 - a0))) << a0) : 0u;
+        uint32_t fl = 0u;
+        if (!last) {
+            const int f0 = (d1 > lo ? d1 : lo) - lo, f1 = (end < lo + kLaneD ? end : lo + kLaneD) - lo;
+            fl = (f1 > f0) ? ((0xFFFFFFFFu >> (32 - (f1 - f0))) << f0) : 0u;
+        }
+        lane_stage<M, true, PT>(r, key, prow, jb, jmask, act, fl, (uint32_t)(n - 1));
+    }
+    if (end <= lo + kLaneD) return last ? (key[M - 1] >> jb) : 0u;
+#pragma unroll
+    for (int q = 0; q < M; ++q) st[q * 64] = key[q];
+    return 0u;
+}
+
+// Genes of slots [lo, lo + kLaneD) of a row (positions past the row's end
+// read the row's padding; the guards never dispatch them).
+struct GenesU16 {
+    const uint16_t* row;   // n_pad entries, 64-byte aligned
+    __device__ __forceinline__ void load(int lo, uint32_t (&g)[kLaneD]) const
+    {
+        const auto* v = as_global(reinterpret_cast<const u32x4*>(row + lo));
+        const u32x4 a = v[0], b = v[1];
+        const uint32_t w[8] = {a.x, a.y, a.z, a.w, b.x, b.y, b.z, b.w};
+#pragma unroll
+        for (int i = 0; i < 8; ++i) {
+            g[2 * i] = w[i] & 0xFFFFu;
+            g[2 * i + 1] = w[i] >> 16;
+        }
+    }
+};
+
+// Caller-supplied int32 rows of exactly n entries: values outside [0, n)
+// become 0 (the row is reported invalid separately).
+struct GenesI32 {
+    const int* row;
+    int n;
+    __device__ __forceinline__ void load(int lo, uint32_t (&g)[kLaneD]) const
+    {
+        const auto* p = as_global(row);
+#pragma unroll
+        for (int i = 0; i < kLaneD; ++i) {
+            const int t = lo + i;
+            const int x = p[t < n ? t : n - 1];
+            g[i] = ((unsigned)x < (unsigned)n) ? (uint32_t)x : 0u;
+        }
+    }
+};
+
+// Makespan of one chromosome per lane.  pT is the LDS table (row stride
+// pts), mach the stage machine counts, st this wave's LDS state (msum keys
+// per lane, lane-interleaved).
+template <int MMAX, typename PT, typename Src>
+__device__ uint32_t lane_decode(const Src& src, const PT* pT, int pts, const int* mach, int S, int n, int jb,
+                                uint32_t* st, int lane)
+{
+    const uint32_t ujb = (uint32_t)jb, jmask = (1u << jb) - 1u;
+    int off_last = 0;
+    for (int k = 0; k + 1 < S; ++k) off_last += mach[k];
+    const int nwin = (off_last + n + kLaneD - 1) / kLaneD;
+    uint32_t cmax = 0u;
+    uint32_t gnext[kLaneD];
+    src.load(0, gnext);
+    for (int w = 0; w < nwin; ++w) {
+        const int lo = w * kLaneD;
+        uint32_t r[kLaneD];
+#pragma unroll
+        for (int i = 0; i < kLaneD; ++i) r[i] = gnext[i];
+        if (lo + kLaneD < n) src.load(lo + kLaneD, gnext);
+        int off = 0;
+        for (int k = 0; k < S; ++k) {
+            const int M = mach[k];
+            const bool last = (k == S - 1);
+            const int end = off + n + (last ? 0 : M);
+            if (off >= lo + kLaneD) break;   // this and later stages start after the window
+            if (end > lo) {
+                const PT* prow = pT + (size_t)k * pts;
+                uint32_t* sk = st + (size_t)off * 64 + lane;
+                uint32_t cm = 0u;
+                switch (M) {
+#define FFS_LANE_CASE(MM)                                                                       \
+    case MM:                                                                                    \
+        if (MM <= MMAX) cm = lane_stage_window<(MM <= MMAX ? MM : 1), PT>(r, sk, prow, lo, off, n, last, ujb, jmask); \
+        break;
+                    FFS_LANE_CASE(1) FFS_LANE_CASE(2) FFS_LANE_CASE(3) FFS_LANE_CASE(4)
+                    FFS_LANE_CASE(5) FFS_LANE_CASE(6) FFS_LANE_CASE(7) FFS_LANE_CASE(8)
+#undef FFS_LANE_CASE
+                    default: break;
+                }
+                cmax = last ? (cm > cmax ? cm : cmax) : cmax;
+            }
+            off += M;
+        }
+    }
+    return cmax;
+}
+
+// ---- one generation (mode 0) or generation 0 (mode 1), lane mapping --------
+// Work item = up to 64 * waves chromosomes of one island; wave w takes 64 of
+// them.  Same generation bookkeeping, best-ever workgroup and XCD placement
+// as k_generation.
+template <int MMAX, typename PT>
+__global__ void __launch_bounds__(512) k_generation_lane(const InstDesc* __restrict__ insts,
+                                                         const IslandDesc* __restrict__ isls,
+                                                         const WorkItem* __restrict__ work, Control* ctl, int n_inst,
+                                                         int mode, int cnt_off, int has_extra)
+{
+    __shared__ int s_gen;
+    if (threadIdx.x == 0) {
+        int gg = 0;
+        if (mode == 0) {
+            int* cnt = ctl->counts + cnt_off + blockIdx.x;
+            const int t = *cnt;
+            *cnt = t + 1;
+            gg = ctl->base + 1 + t;
+        }
+        s_gen = gg;
+    }
+    if (has_extra && blockIdx.x == gridDim.x - 1) {
+        __syncthreads();
+        const int prev = s_gen - 1;
+        if (ctl->best_gen < prev) fold_best(insts, isls, n_inst, prev, ctl, reinterpret_cast<int*>(ffs_smem));
+        return;
+    }
+    const int nw = (int)gridDim.x - has_extra;
+    int widx = (int)blockIdx.x;
+    if (nw <= 256) {
+        const int per = (nw + 7) / 8, full = nw - 8 * (per - 1);
+        const int xcd = widx & 7, rnk = widx >> 3;
+        widx = (xcd < full) ? xcd * per + rnk : full * per + (xcd - full) * (per - 1) + rnk;
+    }
+    const WorkItem wi = work[widx];
+    const InstDesc* I = insts + wi.inst;
+    const IslandDesc* L = isls + wi.island;
+    const int n = I->n, S = I->S, n_pad = I->n_pad, jb = I->jb;
+    const int gop = I->gop, W = kWave / gop;
+
+    PT* pT = reinterpret_cast<PT*>(ffs_smem);
+    stage_pt<PT>(pT, I->pT, S, n_pad);
+    __syncthreads();
+    const int gen = s_gen;
+    const int cur = (gen + 1) & 1, nxt = gen & 1;
+
+    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    unsigned char* wbase = ffs_smem + pt_lds_bytes<PT>(S, n_pad) + (size_t)wave * I->lane_wlds;
+    const int w0 = wave * kWave;
+    const int wcount = wi.count - w0 < 0 ? 0 : (wi.count - w0 > kWave ? kWave : wi.count - w0);
+    const int sbase = wi.slot0 + w0;
+
+    // children, a group of W lanes per child, into the next generation's rows
+    {
+        const int g = lane / W, k = lane - g * W;
+        uint16_t* A = reinterpret_cast<uint16_t*>(wbase) + (size_t)g * group_stride(n_pad);
+        uint16_t* B = A + n_pad;
+        uint16_t* V = B + n_pad;
+        for (int r0 = 0; r0 < wcount; r0 += gop) {
+            const bool active = r0 + g < wcount;
+            const int slot = sbase + (active ? r0 + g : 0);
+            make_child<true>(I, L, slot, 0u, gen, cur, mode, A, B, V, k, W, g, active);
+            if (active) row_l2g(L->genes[nxt] + (size_t)slot * n_pad, A, n_pad, k, W);
+            wave_sync();
+        }
+    }
+    // the rows just written are read back by other lanes of this wave
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
+
+    const bool active = lane < wcount;
+    const int slot = sbase + (active ? lane : 0);
+    unsigned long long wkey = ~0ull;
+    if (wcount > 0) {
+        const GenesU16 src{L->genes[nxt] + (size_t)slot * n_pad};
+        const uint32_t cm = lane_decode<MMAX, PT>(src, pT, pt_stride<PT>(n_pad), I->mach, S, n, jb,
+                                                  reinterpret_cast<uint32_t*>(wbase), lane);
+        bool keep_old = false;
+        if (active) {
+            int mk_new = (int)cm;
+            if (mode == 0 && L->kind == 0) {
+                const int mk_old = as_global(L->mk[cur])[slot];
+                keep_old = !((int)cm < mk_old);
+                mk_new = keep_old ? mk_old : (int)cm;
+            }
+            L->mk[nxt][slot] = mk_new;
+            wkey = ((unsigned long long)(unsigned)mk_new << 32) | (unsigned)slot;
+        }
+        // cells that keep their individual get the parent's row back, four
+        // rows at a time by the whole wave
+        unsigned long long km = __ballot(keep_old);
+        const int nv = n_pad >> 3;
+        const u32x4* s4 = reinterpret_cast<const u32x4*>(L->genes[cur]);
+        u32x4* d4 = reinterpret_cast<u32x4*>(L->genes[nxt]);
+        while (km) {
+            int rows[4];
+            int cnt = 0;
+#pragma unroll
+            for (int t = 0; t < 4; ++t) {
+                rows[t] = -1;
+                if (km) {
+                    rows[t] = sbase + (int)__builtin_ctzll(km);
+                    km &= km - 1ull;
+                    ++cnt;
+                }
+            }
+            for (int v0 = lane; v0 < nv; v0 += kWave) {
+                u32x4 x[4];
+#pragma unroll
+                for (int t = 0; t < 4; ++t)
+                    if (rows[t] >= 0) x[t] = as_global(s4)[(size_t)rows[t] * nv + v0];
+#pragma unroll
+                for (int t = 0; t < 4; ++t)
+                    if (rows[t] >= 0) as_global(d4)[(size_t)rows[t] * nv + v0] = x[t];
+            }
+            (void)cnt;
+        }
+    }
+#pragma unroll
+    for (int offx = 32; offx > 0; offx >>= 1) {
+        const unsigned long long o = __shfl_xor(wkey, offx, 64);
+        wkey = o < wkey ? o : wkey;
+    }
+    __shared__ unsigned long long s_wmin[8];
+    if (lane == 0) s_wmin[wave] = wkey;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        unsigned long long mn = ~0ull;
+        for (int x = 0; x < (int)(blockDim.x >> 6); ++x) mn = s_wmin[x] < mn ? s_wmin[x] : mn;
+        if (mn != ~0ull) atomicMin(L->genkey + (gen & 1), mn);
+    }
+}
+
+// ---- decode of caller-supplied permutations, lane mapping ------------------
+// One row per lane.  A row is invalid if a value lies outside [0, n) or
+// repeats (per-lane bit set in LDS); its makespan is then -1 and bit 0 of
+// the control block's error word is set.
+template <int MMAX, typename PT>
+__global__ void __launch_bounds__(512) k_evaluate_lane(const InstDesc* __restrict__ I, const int* __restrict__ perms,
+                                                       int count, int* __restrict__ out, Control* ctl)
+{
+    const int n = I->n, S = I->S, n_pad = I->n_pad, jb = I->jb;
+    PT* pT = reinterpret_cast<PT*>(ffs_smem);
+    stage_pt<PT>(pT, I->pT, S, n_pad);
+    __syncthreads();
+    const int wpb = blockDim.x >> 6;
+    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    uint32_t* wbase = reinterpret_cast<uint32_t*>(ffs_smem + pt_lds_bytes<PT>(S, n_pad) +
+                                                  (size_t)wave * I->lane_wlds_eval);
+    const long long base = ((long long)blockIdx.x * wpb + wave) * kWave;
+    if (base >= count) return;
+    const long long idx = base + lane;
+    const bool active = idx < count;
+    const int* row = perms + (active ? idx : base) * (long long)n;
+    // validity: each value in range and seen once
+    const int nwords = (n + 31) >> 5;
+    for (int q = 0; q < nwords; ++q) wbase[q * 64 + lane] = 0u;
+    bool bad = false;
+    {
+        const auto* p = as_global(row);
+        for (int t = 0; t < n; ++t) {
+            const int x = p[t];
+            if ((unsigned)x >= (unsigned)n) {
+                bad = true;
+            } else {
+                const uint32_t bit = 1u << (x & 31);
+                const uint32_t old = atomicOr(&wbase[(x >> 5) * 64 + lane], bit);
+                bad |= (old & bit) != 0u;
+            }
+        }
+    }
+    wave_sync();
+    const GenesI32 src{row, n};
+    const uint32_t cm = lane_decode<MMAX, PT>(src, pT, pt_stride<PT>(n_pad), I->mach, S, n, jb, wbase, lane);
+    if (active) out[idx] = bad ? -1 : (int)cm;
+    if (active && bad) atomicOr(&ctl->err, 1);
+}
+
+}  // namespace flowshop

@@ -17,10 +17,10 @@ def ensure_built():
         build_library()
 
 
-def make_ctx(workloads, waves_per_block=None, seed=101):
+def make_ctx(workloads, waves_per_block=None, seed=101, mapping=None):
     """One context holding every workload (instance i gets RNG instance id i)."""
     from paper_1903_10722_amd import Context
-    ctx = Context(device=0, waves_per_block=waves_per_block)
+    ctx = Context(device=0, waves_per_block=waves_per_block, mapping=mapping)
     for w in workloads:
         ctx.add_instance(w["m"], w["p"], w["islands"], interval=w["interval"], theta=w.get("theta", 1.0),
                          topology=w.get("topology", 0), seed=w.get("seed", seed))

@@ -1,0 +1,220 @@
+"""GPU parity of the lane mapping (one lane decodes one chromosome through
+every stage; ffs_set_mapping(1)) against the oracle, and its agreement
+with the per-stage mapping.
+
+Decode: bit-exact makespans at every workload shape and at the edge cases
+(one job, one stage, single-machine stages, processing times above 255,
+rows shorter than a window, a flush that spans two windows), and rows
+that are not permutations.  Generation loop: whole trajectories of the
+tiny workload, the scaled medium and large ones and uneven batched
+instances, every tile width, a mapping switched mid-run."""
+import numpy as np
+import pytest
+
+import oracle
+from gpu_util import assert_same_state, ensure_built, make_ctx, oracle_ga, say
+from paper_1903_10722_amd import inputs
+from paper_1903_10722_amd.binding import FFSError
+
+pytestmark = pytest.mark.gpu
+
+SMALL_ISLANDS = [inputs.cellular(3, 3, 0.9, 0.1), inputs.pseudo(2, 0.75, 0.0)]
+
+
+def _inst(n, S, m_lo, m_hi, seed, machines=None, p_hi=99):
+    m, p = inputs.make_instance(n, S, m_lo, m_hi, p_hi=p_hi, seed=seed, machines=machines)
+    return dict(m=m, p=p, islands=SMALL_ISLANDS, interval=0)
+
+
+SHAPES = [
+    # name, n, S, m_lo, m_hi, machines, p_hi, count, checked
+    ("tiny", 20, 3, 2, 2, [2, 2, 2], 99, 3001, 3001),
+    ("medium", 100, 5, 1, 5, None, 99, 4099, 1500),
+    ("large", 500, 10, 3, 5, None, 99, 1031, 300),
+    ("surrogate", 1000, 20, 2, 6, None, 99, 517, 60),
+    ("batched_n20_S20", 20, 20, 1, 5, None, 99, 777, 777),
+    ("batched_n500_S5", 500, 5, 1, 5, None, 99, 613, 200),
+    ("batched_n200_S10", 200, 10, 1, 5, None, 99, 611, 200),
+    ("one_job", 1, 4, 1, 3, None, 99, 70, 70),
+    ("one_stage", 37, 1, 3, 3, [3], 99, 300, 300),
+    ("single_machines", 40, 6, 1, 1, [1] * 6, 99, 300, 300),
+    ("eight_machines", 50, 3, 1, 8, [8, 1, 7], 99, 300, 300),
+    ("wide_p", 60, 4, 1, 4, None, 5000, 300, 300),
+    ("short_rows", 5, 7, 1, 4, None, 99, 200, 200),
+    ("flush_spans_windows", 17, 3, 5, 8, [8, 7, 6], 99, 300, 300),
+    ("many_stages", 12, 40, 1, 3, None, 99, 150, 150),
+    ("long_rows", 2000, 3, 1, 4, None, 20, 130, 20),
+]
+
+
+@pytest.mark.parametrize("shape", SHAPES, ids=[s[0] for s in SHAPES])
+def test_lane_decode_parity(shape):
+    ensure_built()
+    name, n, S, lo, hi, machines, p_hi, count, checked = shape
+    w = _inst(n, S, lo, hi, seed=13 + n + S, machines=machines, p_hi=p_hi)
+    assert int(w["m"].sum()) <= 160 and int(w["m"].max()) <= 8
+    say(f"[lane] decode shape={name} n={n} S={S} m={w['m'].tolist()} count={count}")
+    ctx = make_ctx([w], mapping=1)
+    perms = inputs.random_perms(count, n, seed=7 + n)
+    got = ctx.evaluate(0, perms).cpu().numpy()
+    rng = np.random.default_rng(2)
+    idx = np.arange(count) if checked >= count else np.sort(rng.choice(count, checked, replace=False))
+    idx = np.union1d(idx, [0, count - 1])
+    want = oracle.decode_many(w["m"], w["p"], perms[idx])
+    assert np.array_equal(got[idx], want), f"first mismatch at row {idx[np.argmax(got[idx] != want)]}"
+    ctx.close()
+
+
+def test_lane_decode_rejects_non_permutations():
+    """Out-of-range values and repeated values give -1 on their rows only."""
+    ensure_built()
+    w = _inst(30, 4, 1, 4, seed=5)
+    ctx = make_ctx([w], mapping=1)
+    perms = inputs.random_perms(200, 30, seed=3)
+    perms[7, 4] = 30
+    perms[50, 0] = -1
+    perms[51, 3] = perms[51, 9]
+    perms[199, 29] = perms[199, 0]
+    from paper_1903_10722_amd.binding import FFS_EINVAL
+    say("[lane] invalid rows")
+    with pytest.raises(FFSError):
+        ctx.evaluate(0, perms)
+    out, rc = ctx.evaluate(0, perms, check=False)
+    assert rc == FFS_EINVAL
+    got = out.cpu().numpy()
+    bad = [7, 50, 51, 199]
+    assert (got[bad] == -1).all()
+    ok = np.setdiff1d(np.arange(200), bad)
+    assert np.array_equal(got[ok], oracle.decode_many(w["m"], w["p"], perms[ok]))
+    # the flag is cleared: a clean call succeeds
+    clean = inputs.random_perms(64, 30, seed=4)
+    assert np.array_equal(ctx.evaluate(0, clean).cpu().numpy(), oracle.decode_many(w["m"], w["p"], clean))
+    ctx.close()
+
+
+@pytest.mark.parametrize("inst_seed", [1, 2])
+def test_lane_tiny_trajectory(inst_seed):
+    """Tiny workload (8x8 cellular + 64 pseudo, n=20, S=3) on the lane
+    mapping: 100 generations, migration every 10, compared after every chunk
+    with the best-ever record."""
+    ensure_built()
+    w = inputs.workload("tiny", seed=inst_seed)
+    say(f"[lane] tiny inst_seed={inst_seed}")
+    ctx = make_ctx([w], mapping=1)
+    assert ctx.mapping() == 1
+    ga = oracle_ga(w)
+    assert_same_state(ctx, ga, 0, 2, "generation 0")
+    done = 0
+    for chunk in [1, 4, 5, 10, 20, 60]:
+        ctx.evolve(chunk)
+        ga.evolve(chunk)
+        done += chunk
+        assert_same_state(ctx, ga, 0, 2, f"generation {done}")
+        b1, b2 = ctx.best(0), ga.best()
+        assert (b1["makespan"], b1["generation"]) == (b2["makespan"], b2["generation"])
+        assert b1["perm"].tolist() == b2["perm"].tolist()
+    assert ctx.migration_counters(0) == ga.counters()
+    ctx.close()
+
+
+def test_lane_medium_scaled_trajectory():
+    """Medium instance (n=100, S=5, m in [1,5]) on 32x32 + 1024 islands,
+    60 generations with adaptive migration every 20, lane mapping."""
+    ensure_built()
+    w = inputs.workload("medium", seed=1, scale=2)
+    say("[lane] medium scale=2")
+    ctx = make_ctx([w], mapping=1)
+    ga = oracle_ga(w)
+    for g in (19, 1, 20, 20):
+        ctx.evolve(g)
+        ga.evolve(g)
+        assert_same_state(ctx, ga, 0, 2, f"generation {ctx.generation}")
+    assert ctx.best(0)["makespan"] == ga.best()["makespan"]
+    assert ctx.migration_counters(0) == ga.counters()
+    ctx.close()
+
+
+def test_lane_sixteen_islands_and_long_rows():
+    """Large instance (n=500, S=10) on 16 islands of 64 with ring-then-
+    adaptive migration, and the n=1000, S=20 instance on 8x8 + 64: 40
+    generations each on the lane mapping, compared at every epoch."""
+    ensure_built()
+    for w, nis in ((inputs.workload("large", seed=1, scale=16), 16),
+                   (inputs.workload("surrogate", seed=2, scale=8), 2)):
+        say(f"[lane] n={w['p'].shape[0]} S={w['p'].shape[1]} islands={nis}")
+        ctx = make_ctx([w], mapping=1)
+        ga = oracle_ga(w)
+        for g in (20, 20):
+            ctx.evolve(g)
+            ga.evolve(g)
+            assert_same_state(ctx, ga, 0, nis, f"generation {ctx.generation}")
+        assert ctx.best(0)["makespan"] == ga.best()["makespan"]
+        ctx.close()
+
+
+def test_lane_batched_uneven_instances():
+    """Eight uneven batched instances (n up to 500, S up to 20, grids shrunk
+    eightfold) in one lane-mapped context, 20 generations with migration
+    every 10, each compared with its oracle run."""
+    ensure_built()
+    ws = inputs.batched_workloads(count=8, batch_seed=7, scale=8)
+    say("[lane] batched 8 instances")
+    ctx = make_ctx(ws, mapping=1)
+    assert ctx.mapping() == 1
+    ctx.evolve(20)
+    for i, w in enumerate(ws):
+        ga = oracle_ga(w, inst=i)
+        ga.evolve(20)
+        assert_same_state(ctx, ga, i, 2, f"instance {i} n={w['p'].shape}")
+        assert ctx.best(i)["makespan"] == ga.best()["makespan"]
+    ctx.close()
+
+
+def test_lane_tiles_and_mapping_switch_agree():
+    """Medium instance on 16x16 + 256: the per-stage mapping and the lane
+    mapping at 1, 2, 4 and 8 waves per workgroup give the same trajectory,
+    and so does a run that switches mapping after bind."""
+    ensure_built()
+    w = inputs.workload("medium", seed=3, scale=4)
+    ref = None
+    for mapping, wpb in ((0, 4), (1, 1), (1, 2), (1, 4), (1, 8)):
+        say(f"[lane] mapping={mapping} waves_per_block={wpb}")
+        ctx = make_ctx([w], mapping=mapping, waves_per_block=wpb)
+        assert ctx.mapping() == mapping
+        ctx.evolve(25)
+        state = [ctx.population(0, i) for i in range(2)]
+        best = ctx.best(0)
+        ctx.close()
+        if ref is None:
+            ref = (state, best)
+            continue
+        for i in range(2):
+            assert np.array_equal(state[i][0], ref[0][i][0]) and np.array_equal(state[i][1], ref[0][i][1])
+        assert best["makespan"] == ref[1]["makespan"] and best["perm"].tolist() == ref[1]["perm"].tolist()
+    ctx = make_ctx([w], mapping=0)
+    ctx.evolve(9)
+    ctx.set_mapping(1)
+    assert ctx.mapping() == 1
+    ctx.evolve(16)
+    for i in range(2):
+        g, m = ctx.population(0, i)
+        assert np.array_equal(g, ref[0][i][0]) and np.array_equal(m, ref[0][i][1])
+    ctx.close()
+
+
+def test_automatic_mapping_choice():
+    """Automatic mapping: per lane for the large workload's 262144
+    individuals, per stage for the medium one's 8192 and whenever a stage
+    has more than 8 machines."""
+    ensure_built()
+    big = inputs.workload("large", seed=1)
+    ctx = make_ctx([big])
+    assert ctx.mapping() == 1
+    ctx.close()
+    ctx = make_ctx([inputs.workload("medium", seed=1)])
+    assert ctx.mapping() == 0
+    ctx.close()
+    w = _inst(50, 3, 1, 16, seed=3, machines=[16, 1, 7])
+    ctx = make_ctx([w], mapping=1)
+    assert ctx.mapping() == 0
+    ctx.close()
