@@ -1,15 +1,17 @@
 """Benchmark of the island-GA hot path on one MI355X.
 
-Workload: the medium flexible-flow-shop configuration -- n=100 jobs, 5 stages,
-machines per stage uniform in [1,5], processing times uniform in [1,99]; one
-64x64 cellular island (crossover 0.9, swap mutation 0.1) and one pseudo island
-of 4096 (crossover 0.75), adaptive migration every 20 generations.
+Headline workload: the large flexible-flow-shop configuration -- n=500 jobs,
+10 stages, machines per stage uniform in [3,5], processing times uniform in
+[1,99]; 8 cellular islands of 128x128 (crossover 0.9, swap mutation 0.1) and
+8 pseudo islands of 16384 (crossover 0.75), ring-then-adaptive migration every
+20 generations -- the largest configuration that fits one GPU.
 
-A step is one migration epoch: 20 generations of both islands (8192 exact
+A step is one migration epoch: 20 generations of every island (262144 exact
 makespan decodes per generation, neighbourhood selection, order crossover,
 swap mutation, replacement, complementary-pair mating, best-ever update) plus
 the migration epoch that closes it.  The population is resident in HBM when
-the timed region starts.  Prints one JSON line.
+the timed region starts.  The medium workload (n=100, S=5, 64x64 + 4096) is
+measured the same way and reported beside it.  Prints one JSON line.
 """
 from __future__ import annotations
 
@@ -43,8 +45,10 @@ def parse():
     ap.add_argument("--steps", type=int, default=100)
     ap.add_argument("--warmup", type=int, default=5)
     ap.add_argument("--seed", type=int, default=1)
-    ap.add_argument("--workload", default="medium", choices=["medium", "tiny", "large", "surrogate", "batched"],
-                    help="workload of the timed steps (the reported metric is quoted on medium)")
+    ap.add_argument("--workload", default="large", choices=["medium", "tiny", "large", "surrogate", "batched"],
+                    help="workload of the timed steps (default: the large workload, the largest single-GPU one)")
+    ap.add_argument("--secondary", default="medium", choices=["", "medium", "tiny", "large", "surrogate", "batched"],
+                    help="a second workload measured the same way and reported beside the headline ('' = none)")
     ap.add_argument("--prescreen-k", type=int, default=0,
                     help="run the timed steps with the learned pre-screen (k candidates per cell)")
     ap.add_argument("--waves-per-block", type=int, default=None)
@@ -118,25 +122,59 @@ def calibrate_copy(mib: int):
                       "bytes_written": mib * 1024 * 1024, "launches": 5}), flush=True)
 
 
-def cpu_baseline(w, seconds: float) -> dict:
-    """The oracle (single-threaded C) on the same workload: initialisation,
-    then whole generations until about `seconds` of CPU time."""
-    import oracle
-    t0 = time.perf_counter()
-    ga = oracle.GA(w["m"], w["p"], w["islands"], interval=w["interval"], theta=w["theta"],
-                   topology=w["topology"], seed=101)
-    t_init = time.perf_counter() - t0
-    per_gen = sum(x["size"] for x in w["islands"])
-    gens = 0
-    t1 = time.perf_counter()
-    while time.perf_counter() - t1 < seconds:
+# Island sides of the oracle's sample are divided by this factor (the same
+# instance, operators and schedule, fewer individuals per generation), so
+# that a generation of the single-threaded oracle takes about a second.
+CPU_SCALE = {"tiny": 1, "medium": 1, "large": 4, "surrogate": 2, "batched": 8}
+
+_CPU_CHILD = r"""
+import json, os, sys, time
+sys.path.insert(0, sys.argv[1])
+import oracle
+from paper_1903_10722_amd import inputs
+name, seed, scale, seconds = sys.argv[2], int(sys.argv[3]), int(sys.argv[4]), float(sys.argv[5])
+ws = inputs.batched_workloads(count=256, batch_seed=7, scale=scale) if name == "batched" else \
+     [inputs.workload(name, seed=seed, scale=scale)]
+t0 = time.perf_counter()
+gas = [oracle.GA(w["m"], w["p"], w["islands"], interval=w["interval"], theta=w["theta"],
+                 topology=w["topology"], seed=101, inst=i) for i, w in enumerate(ws)]
+t_init = time.perf_counter() - t0
+per_gen = sum(sum(x["size"] for x in w["islands"]) for w in ws)
+gens = 0
+t1 = time.perf_counter()
+while time.perf_counter() - t1 < seconds:
+    for ga in gas:
         ga.evolve(1)
-        gens += 1
-    dt = time.perf_counter() - t1
-    return {"value": per_gen * gens / dt, "unit": "decodes/s", "cores": 1, "kind": "oracle",
-            "sample": f"oracle GA on the same medium workload: generation 0 ({t_init:.2f} s) then "
-                      f"{gens} generations ({per_gen} decodes each) in {dt:.1f} s, one thread",
-            "generations_per_s": gens / dt, "host_cpu": host_cpu(), "host_threads": os.cpu_count()}
+    gens += 1
+dt = time.perf_counter() - t1
+print(json.dumps({"per_gen": per_gen, "gens": gens, "seconds": dt, "init_s": t_init,
+                  "affinity": sorted(os.sched_getaffinity(0))}))
+"""
+
+
+def cpu_baseline(name: str, seed: int, seconds: float) -> dict:
+    """The oracle (single-threaded C) on a bounded sample of the same
+    workload: the same instance(s) with island sides divided by CPU_SCALE,
+    generation 0 then whole generations for about `seconds`, in a child
+    process pinned to one host core (taskset)."""
+    import subprocess
+    core = min(os.sched_getaffinity(0))
+    scale = CPU_SCALE[name]
+    args = [sys.executable, "-c", _CPU_CHILD, ROOT, name, str(seed), str(scale), str(seconds)]
+    try:
+        res = subprocess.run(["taskset", "-c", str(core)] + args, capture_output=True, text=True, check=True)
+        pinned = "taskset -c %d" % core
+    except (OSError, subprocess.CalledProcessError):
+        res = subprocess.run(args, capture_output=True, text=True, check=True)
+        pinned = "not pinned (taskset unavailable)"
+    r = json.loads(res.stdout.strip().splitlines()[-1])
+    sides = "full size" if scale == 1 else f"island sides / {scale}"
+    return {"value": r["per_gen"] * r["gens"] / r["seconds"], "unit": "decodes/s", "cores": 1, "kind": "oracle",
+            "sample": f"oracle GA on the {name} workload ({sides}, {r['per_gen']} individuals per generation): "
+                      f"generation 0 ({r['init_s']:.2f} s) then {r['gens']} generations in {r['seconds']:.1f} s, "
+                      f"one thread, {pinned}",
+            "generations_per_s": r["gens"] / r["seconds"], "host_cpu": host_cpu(),
+            "host_threads": len(os.sched_getaffinity(0)), "affinity": r["affinity"]}
 
 
 def host_cpu() -> str:
@@ -474,20 +512,58 @@ def main():
     if args.calibrate_copy_mib:
         calibrate_copy(args.calibrate_copy_mib)
         return
-    import torch
+    import torch  # noqa: F401
 
-    from paper_1903_10722_amd import Context, inputs
     from paper_1903_10722_amd.binding import library_path
     if not os.path.exists(library_path()):
         from paper_1903_10722_amd.build import build_library
         build_library()
 
-    if args.workload == "batched":
+    head = measure(args.workload, args.seed, args.steps, args.warmup, args)
+    out = {
+        "metric": "makespan decodes/sec and generations/sec at 1 GPU; best makespan at fixed time budget",
+        "value": head["value"],
+        "unit": "decodes/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": head["ms_per_step"],
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "int32",
+        "data": "synthetic",
+        "config": head["config"],
+        "generations_per_s": head["generations_per_s"],
+        "best_makespan": head["best_makespan"],
+        "best_found_generation": head["best_found_generation"],
+        "generations_run": head["generations_run"],
+        "wall_s_timed": head["wall_s_timed"],
+        "bind_and_generation0_s": head["bind_and_generation0_s"],
+        "roofline": head["roofline"],
+    }
+    if not args.no_cpu_baseline:
+        out["cpu_baseline"] = cpu_baseline(args.workload, args.seed, args.cpu_seconds)
+    if args.secondary and args.secondary != args.workload:
+        sec = measure(args.secondary, args.seed, max(1, min(args.steps, 25)), min(args.warmup, 2), args)
+        out["secondary"] = {args.secondary: {k: sec[k] for k in ("value", "ms_per_step", "generations_per_s",
+                                                                  "config", "roofline", "best_makespan")}}
+    if args.surrogate_seconds > 0:
+        out["best_makespan_at_fixed_budget"] = surrogate_compare(args.surrogate_seconds)
+    print(json.dumps(out), flush=True)
+
+
+def measure(name: str, seed: int, steps: int, warmup: int, args) -> dict:
+    """Time `steps` migration epochs of workload `name` (after `warmup`
+    epochs) and the generation kernel's average launch."""
+    import torch
+
+    from paper_1903_10722_amd import Context, inputs
+    if name == "batched":
         ws = inputs.batched_workloads(count=256, batch_seed=7)
     else:
-        ws = [inputs.workload(args.workload, seed=args.seed)]
+        ws = [inputs.workload(name, seed=seed)]
     w = ws[0]
-    n, S = w["p"].shape
     m = w["m"]
     I = w["interval"]
     decodes_per_gen = sum(sum(x["size"] for x in v["islands"]) for v in ws)
@@ -501,33 +577,36 @@ def main():
     stream = ctx.stream
     kernel = "k_generation_lane" if ctx.mapping() == 1 else "k_generation"
 
-    for _ in range(args.warmup):
+    for _ in range(warmup):
         ctx.evolve(I)
     torch.cuda.synchronize()
     e0 = torch.cuda.Event(enable_timing=True)
     e1 = torch.cuda.Event(enable_timing=True)
     t0 = time.perf_counter()
     e0.record(stream)
-    for _ in range(args.steps):
+    for _ in range(steps):
         ctx.evolve(I)
     e1.record(stream)
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
     ms = e0.elapsed_time(e1)
-    gens = I * args.steps
+    gens = I * steps
     decodes = decodes_per_gen * gens
     best = ctx.best(0)
+    generations_run = ctx.generation
 
     # dominant kernel (the generation kernel): its average launch duration
     if args.prescreen_k:
         # the pre-screened path runs eagerly: HIP events around every launch
         ctx.set_timing(True)
-        for _ in range(max(1, min(args.steps, 25))):
+        for _ in range(max(1, min(steps, 25))):
             ctx.evolve(I)
         k_ms, launches = ctx.kernel_time()
         ctx.set_timing(False)
         timing = "HIP events around each launch (eager launches)"
+        ctx.close()
     else:
+        ctx.close()
         # back to back as in the timed region: a context of the same instances
         # without migration replays graphs whose every node is a generation
         # launch; HIP events bracket the replays on the library's stream
@@ -539,7 +618,7 @@ def main():
         L = 16
         ctx2.evolve(L)
         torch.cuda.synchronize()
-        epochs = max(1, min(args.steps, 25))
+        epochs = max(1, min(steps, 25))
         k0 = torch.cuda.Event(enable_timing=True)
         k1 = torch.cuda.Event(enable_timing=True)
         k0.record(ctx2.stream)
@@ -553,41 +632,25 @@ def main():
     ops_per_launch = sum(int(v["p"].shape[0]) * int(sum(int(x) + 6 for x in v["m"])) *
                          sum(x["size"] for x in v["islands"]) for v in ws)
     achieved = ops_per_launch / avg_s / 1e12
-
-    out = {
-        "metric": "makespan decodes/sec and generations/sec at 1 GPU; best makespan at fixed time budget",
+    return {
         "value": decodes / (ms / 1e3),
-        "unit": "decodes/s",
-        "n_gpus": 1,
-        "steps": args.steps,
-        "warmup": args.warmup,
-        "ms_per_step": ms / args.steps,
-        "higher_is_better": True,
-        "scaling": "weak",
-        "vs_baseline": None,
-        "dtype": "int32",
-        "data": "synthetic",
-        "config": {"workload": WORKLOADS[args.workload] + ("" if not args.prescreen_k else
-                                                          f"; learned pre-screen k={args.prescreen_k}"),
+        "ms_per_step": ms / steps,
+        "config": {"workload": WORKLOADS[name] + ("" if not args.prescreen_k else
+                                                  f"; learned pre-screen k={args.prescreen_k}"),
                    "machines": [int(x) for x in m] if len(ws) == 1 else "per instance",
-                   "decodes_per_generation": decodes_per_gen, "generations_per_step": I},
+                   "decodes_per_generation": decodes_per_gen, "generations_per_step": I,
+                   "mapping": "per lane" if kernel == "k_generation_lane" else "per stage"},
         "generations_per_s": gens / (ms / 1e3),
         "best_makespan": best["makespan"],
         "best_found_generation": best["generation"],
-        "generations_run": ctx.generation,
+        "generations_run": generations_run,
         "wall_s_timed": wall,
         "bind_and_generation0_s": t_bind,
         "roofline": {"bound": "alu", "achieved": achieved, "peak": PEAK_INT_TOPS, "unit": "TOP/s",
-                     "frac": achieved / PEAK_INT_TOPS, "traffic": recorded_traffic(kernel, args.workload),
+                     "frac": achieved / PEAK_INT_TOPS, "traffic": recorded_traffic(kernel, name),
                      "kernel": kernel, "avg_launch_us": avg_s * 1e6, "launches": launches, "timing": timing,
                      "ops_per_launch": ops_per_launch},
     }
-    if not args.no_cpu_baseline:
-        out["cpu_baseline"] = cpu_baseline(w, args.cpu_seconds)
-    if args.surrogate_seconds > 0:
-        out["best_makespan_at_fixed_budget"] = surrogate_compare(args.surrogate_seconds)
-    ctx.close()
-    print(json.dumps(out), flush=True)
 
 
 if __name__ == "__main__":

@@ -68,3 +68,14 @@ def test_non_finite_numbers_become_null():
 
 def test_host_cpu_is_text():
     assert isinstance(bench.host_cpu(), str)
+
+
+def test_cpu_baseline_runs_the_oracle_on_one_core():
+    """The CPU baseline times the oracle in a child process pinned to one
+    core, on the named workload (tiny here, briefly)."""
+    import oracle
+    oracle.build()
+    r = bench.cpu_baseline("tiny", 1, 0.5)
+    assert r["kind"] == "oracle" and r["cores"] == 1 and r["unit"] == "decodes/s"
+    assert r["value"] > 0 and len(r["affinity"]) == 1
+    assert "tiny workload" in r["sample"]
