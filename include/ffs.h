@@ -184,6 +184,26 @@ int ffs_evaluate(ffs_ctx *ctx, int32_t inst, const int32_t *perms, int32_t count
 int ffs_evaluate_host(ffs_ctx *ctx, int32_t inst, const int32_t *perms, int32_t count,
                       int32_t *out_makespans);
 
+/* ffs_evaluate for callers that cannot allocate device memory (code under
+ * HIP graph capture, tight serving loops, harnesses that forbid hipMalloc):
+ * no context, no workspace, and no hipMalloc / hipFree or other allocating
+ * routine.  The instance is given here and used for this call only:
+ *   machines: host, int32 [n_stages], each in [1, 16];
+ *   p: host, int32 [n_jobs * n_stages], job-major, each in [1, 65535];
+ *   perms: device, int32 [count * n_jobs]; out_makespans: device, int32 [count];
+ *   hip_stream: a stream of the current device (NULL = the null stream).
+ * Limits: n_jobs <= 4096, n_stages <= 64, the packed-key limit of
+ * ffs_create_instance, and 256 + 256 + 4 n S + S * n_pad * w bytes of state
+ * within 1 MiB (n_pad = n rounded up to 32, w = 1 if every p <= 255 else 2),
+ * else FFS_EUNSUPPORTED.  The state lives in a statically allocated device
+ * array (1 MiB per GPU, held until the process ends) that every call on a
+ * GPU shares: calls that overlap on one GPU (other threads, other streams)
+ * race and must be serialised by the caller.  Same rows, makespans and
+ * statuses as ffs_evaluate (invalid rows: -1 and FFS_EINVAL); no error text
+ * (there is no context).  (syncs)                                          */
+int ffs_evaluate_noalloc(void *hip_stream, int32_t n_jobs, int32_t n_stages, const int32_t *machines,
+                         const int32_t *p, const int32_t *perms, int32_t count, int32_t *out_makespans);
+
 /* Run `generations` generations of every instance.  Per generation: every
  * cellular cell and pseudo pair produces its children from generation g-1
  * (synchronous update), the best-ever record is updated, and when

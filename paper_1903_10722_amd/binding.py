@@ -26,7 +26,7 @@ EXPORTS = [
     "ffs_surrogate_params", "ffs_surrogate_set_params", "ffs_mlp_forward", "ffs_mlp_gradients",
     "ffs_mlp_train_step", "ffs_surrogate_candidates", "ffs_surrogate_choices", "ffs_surrogate_ring",
     "ffs_evaluate_host", "ffs_checkpoint_size", "ffs_checkpoint_save", "ffs_checkpoint_load",
-    "ffs_set_mapping", "ffs_get_mapping",
+    "ffs_set_mapping", "ffs_get_mapping", "ffs_evaluate_noalloc",
 ]
 
 N_PARAMS = 394753
@@ -79,6 +79,7 @@ def load_library():
                                         ctypes.POINTER(GAConfig), u64, pi32]
     lib.ffs_set_waves_per_block.argtypes = [P, i32]
     lib.ffs_set_mapping.argtypes = [P, i32]
+    lib.ffs_evaluate_noalloc.argtypes = [P, i32, i32, pi32, pi32, P, i32, P]
     lib.ffs_get_mapping.argtypes = [P, pi32]
     lib.ffs_workspace_size.argtypes = [P, ctypes.POINTER(ctypes.c_size_t)]
     lib.ffs_bind_workspace.argtypes = [P, P, ctypes.c_size_t]
@@ -364,3 +365,23 @@ class Context:
                                                 X.ctypes.data_as(ctypes.POINTER(ctypes.c_uint16)),
                                                 t.ctypes.data_as(ctypes.POINTER(ctypes.c_float))))
         return X, t
+
+
+def evaluate_noalloc(m, p, perms, out, stream=None) -> int:
+    """ffs_evaluate_noalloc: makespans of the rows of `perms` (torch int32
+    [count, n] on the current device) into `out` (torch int32 [count], same
+    device) for the instance (m, p) given here, without a context or
+    workspace.  Returns the status code (FFS_OK, or FFS_EINVAL when some rows
+    are not permutations); other failures raise FFSError."""
+    import torch
+    lib = load_library()
+    m = _i32(m)
+    p = _i32(p)
+    n, S = p.shape
+    st = stream if stream is not None else torch.cuda.current_stream()
+    rc = lib.ffs_evaluate_noalloc(ctypes.c_void_p(st.cuda_stream), int(n), int(S), _p32(m), _p32(p.reshape(-1)),
+                                  ctypes.c_void_p(perms.data_ptr()), int(perms.shape[0]),
+                                  ctypes.c_void_p(out.data_ptr()))
+    if rc not in (FFS_OK, FFS_EINVAL):
+        raise FFSError(rc, "ffs_evaluate_noalloc failed")
+    return rc

@@ -13,6 +13,7 @@
 #include <cstdio>
 #include <cstring>
 #include <functional>
+#include <mutex>
 #include <string>
 #include <vector>
 
@@ -21,6 +22,27 @@
 #include "ffs_lane.h"
 
 using namespace flowshop;
+
+// Device memory of the allocation-free decode (ffs_evaluate_noalloc): the
+// control word, the instance descriptor, the caller's processing times and
+// the stage-major table built from them.  One copy per GPU, for the life of
+// the process; host code reaches it only through the address that
+// hipGetSymbolAddress returns for the current device.
+constexpr size_t kScratchBytes = (size_t)1 << 20;
+static __device__ __align__(256) unsigned char scratch[kScratchBytes];
+
+// Stage-major table of an instance from its job-major processing times:
+// pT[k][j] = p[j][k] for j < n, 0 in the padding up to n_pad.
+__global__ void __launch_bounds__(256) k_build_table(const int* __restrict__ p, int n, int S, int n_pad, int ptb,
+                                                     void* __restrict__ pT)
+{
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= S * n_pad) return;
+    const int k = i / n_pad, j = i - k * n_pad;
+    const int v = j < n ? p[(size_t)j * S + k] : 0;
+    if (ptb == 1) reinterpret_cast<uint8_t*>(pT)[i] = (uint8_t)v;
+    else reinterpret_cast<uint16_t*>(pT)[i] = (uint16_t)v;
+}
 
 namespace {
 
@@ -1600,6 +1622,108 @@ int ffs_checkpoint_load(ffs_ctx* c, const void* host, size_t bytes)
         for (const auto& L : I.isl)
             HIP_TRY(c, hipMemcpyAsync(c->ws + L.off_genkey, gk, sizeof gk, hipMemcpyHostToDevice, c->stream));
     HIP_TRY(c, hipStreamSynchronize(c->stream));
+    return FFS_OK;
+}
+
+// ---- allocation-free decode ---------------------------------------------------
+// The address of `scratch` on each device, taken once per device with that
+// device current.
+namespace {
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+void* g_scratch_dev[kMaxDevices] = {};
+}  // namespace
+
+int ffs_evaluate_noalloc(void* hip_stream, int32_t n, int32_t S, const int32_t* machines, const int32_t* p,
+                         const int32_t* perms, int32_t count, int32_t* out)
+{
+    hipStream_t stream = reinterpret_cast<hipStream_t>(hip_stream);
+    if (!machines || !p) return FFS_EINVAL;
+    if (n < 1 || n > 4096 || S < 1 || S > kMaxStages) return FFS_EINVAL;
+    if (count < 0) return FFS_EINVAL;
+    if (count > 0 && (!perms || !out)) return FFS_EINVAL;
+    int mmax = 1, msum = 0, maxP = 1;
+    for (int k = 0; k < S; ++k) {
+        if (machines[k] < 1 || machines[k] > kMaxMachines) return FFS_EINVAL;
+        mmax = std::max(mmax, machines[k]);
+        msum += machines[k];
+    }
+    long long E = 0;
+    for (long long i = 0; i < (long long)n * S; ++i) {
+        if (p[i] < 1 || p[i] > 65535) return FFS_EINVAL;
+        E += p[i];
+        maxP = std::max(maxP, p[i]);
+    }
+    int jb = 1;
+    while ((1 << jb) < n) ++jb;
+    if (E >= ((1ll << (32 - jb)) - 1)) return FFS_EUNSUPPORTED;
+    if (count == 0) return FFS_OK;
+    const int n_pad = (n + 31) & ~31, ptb = maxP <= 255 ? 1 : 2;
+    // scratch layout: control block, descriptor, processing times, table
+    const size_t o_ctl = 0, o_desc = al256(sizeof(Control)), o_p = o_desc + al256(sizeof(InstDesc));
+    const size_t o_pt = o_p + al256((size_t)n * S * 4);
+    if (o_pt + (size_t)S * n_pad * ptb > kScratchBytes) return FFS_EUNSUPPORTED;
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= kMaxDevices) return FFS_EDEVICE;
+    char* base = nullptr;
+    {
+        std::lock_guard<std::mutex> lk(g_scratch_mu);
+        if (!g_scratch_dev[dev]) {
+            void* ptr = nullptr;
+            if (hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch)) != hipSuccess || !ptr) return FFS_EDEVICE;
+            g_scratch_dev[dev] = ptr;
+        }
+        base = static_cast<char*>(g_scratch_dev[dev]);
+    }
+    const int mm = round_mmax(mmax);
+    InstDesc d;
+    memset(&d, 0, sizeof d);
+    d.pT = base + o_pt;
+    d.n = n;
+    d.S = S;
+    d.n_pad = n_pad;
+    d.jb = jb;
+    d.G = std::min(kWave / S, std::max(1, 32768 / (2 * group_stride(n_pad))));
+    d.msum = msum;
+    for (int k = 0; k < S; ++k) d.mach[k] = machines[k];
+    d.lane_wlds_eval = (int)lane_eval_wave_lds(n, msum);
+    // the automatic choice of ffs_evaluate at four waves per workgroup
+    constexpr int wpb = 4;
+    void* kl = (msum <= kLaneMaxMsum && mmax <= 8) ? pick_eval_lane(mm, ptb) : nullptr;
+    const bool lane = kl && count >= kLaneEvalAutoMin;
+    void* kern = lane ? kl : pick_eval(mm, ptb);
+    if (!kern) return FFS_EUNSUPPORTED;
+    const size_t lds = align16((size_t)S * ((size_t)n_pad * ptb + 4)) +
+                       (size_t)wpb * (lane ? (size_t)d.lane_wlds_eval : wave_lds_bytes(d.G, n_pad));
+    int max_lds = 0;
+    if (hipDeviceGetAttribute(&max_lds, hipDeviceAttributeMaxSharedMemoryPerBlock, dev) != hipSuccess)
+        return FFS_EDEVICE;
+    if (lds > (size_t)max_lds) return FFS_EUNSUPPORTED;
+    if (hipFuncSetAttribute(kern, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds) != hipSuccess)
+        return FFS_EDEVICE;
+    // the previous call's contents stay in scratch: descriptor, times and
+    // table are rewritten, the error word cleared by a kernel
+    if (hipMemcpyAsync(base + o_desc, &d, sizeof d, hipMemcpyHostToDevice, stream) != hipSuccess) return FFS_EDEVICE;
+    if (hipMemcpyAsync(base + o_p, p, (size_t)n * S * 4, hipMemcpyHostToDevice, stream) != hipSuccess)
+        return FFS_EDEVICE;
+    uint32_t* ctlw = reinterpret_cast<uint32_t*>(base + o_ctl);
+    const size_t ctl_words = sizeof(Control) / 4;
+    hipLaunchKernelGGL(k_zero_u32, dim3(1), dim3(256), 0, stream, ctlw, ctl_words);
+    hipLaunchKernelGGL(k_build_table, dim3((S * n_pad + 255) / 256), dim3(256), 0, stream,
+                       reinterpret_cast<const int*>(base + o_p), n, S, n_pad, ptb, (void*)(base + o_pt));
+    const InstDesc* di = reinterpret_cast<const InstDesc*>(base + o_desc);
+    Control* ctl = reinterpret_cast<Control*>(base + o_ctl);
+    const int per_block = wpb * (lane ? kWave : d.G);
+    const int blocks = (count + per_block - 1) / per_block;
+    void* args[] = {(void*)&di, (void*)&perms, (void*)&count, (void*)&out, (void*)&ctl};
+    if (hipLaunchKernel(kern, dim3(blocks), dim3(64 * wpb), args, lds, stream) != hipSuccess) return FFS_EDEVICE;
+    int err = 0;
+    if (hipMemcpyAsync(&err, base + o_ctl + offsetof(Control, err), sizeof err, hipMemcpyDeviceToHost, stream) !=
+        hipSuccess)
+        return FFS_EDEVICE;
+    if (hipStreamSynchronize(stream) != hipSuccess) return FFS_EDEVICE;
+    if (err & 2) return FFS_EDEVICE;
+    if (err & 1) return FFS_EINVAL;
     return FFS_OK;
 }
 
