@@ -68,7 +68,6 @@ struct HostInstance {
     int edge0 = 0, n_edges = 0;   // topology 2: this instance's ring edges in the pair list
     int isl_base = 0;
     size_t lds = 0;               // LDS bytes of one generation workgroup
-    int gop = 1;                  // lane mapping: operator groups per wave
     size_t lane_wlds = 0, lane_wlds_eval = 0;   // lane mapping: LDS bytes per wave
     bool lane_ok = false;         // the lane mapping can run this instance
     int lds_bucket = 0, cls = 0;  // its LDS class
@@ -960,11 +959,9 @@ int ffs_create_instance(ffs_ctx* c, int32_t n, int32_t S, const int32_t* machine
         I.LB = std::max(I.LB, (I.Pk[k] + I.m[k] - 1) / I.m[k]);
         I.msum += I.m[k];
     }
-    // lane mapping: operator groups per wave so that their rows stay within
-    // 16 KB; the decode keeps msum keys per lane in LDS
-    I.gop = 8;
-    while (I.gop > 1 && (size_t)I.gop * group_stride(I.n_pad) * 2 > 16384) I.gop >>= 1;
-    I.lane_wlds = lane_gen_wave_lds(I.gop, I.n_pad, I.msum);
+    // lane mapping: the operators' rows of one child per wave, then the
+    // decode's msum keys per lane, in LDS
+    I.lane_wlds = lane_gen_wave_lds(I.n_pad, I.msum);
     I.lane_wlds_eval = lane_eval_wave_lds(n, I.msum);
     I.lane_ok = I.msum <= kLaneMaxMsum && I.mmax <= 8;
     I.n_cells = 0;
@@ -1106,7 +1103,6 @@ int ffs_bind_workspace(ffs_ctx* c, void* dptr, size_t bytes)
         }
         d.LB = (int)I.LB;
         d.msum = I.msum;
-        d.gop = I.gop;
         d.lane_wlds = (int)I.lane_wlds;
         d.lane_wlds_eval = (int)I.lane_wlds_eval;
         d.n_cells = I.n_cells;

@@ -49,7 +49,6 @@ struct InstDesc {
     uint16_t* ring_X;            // [ring_size][256] features of decoded children
     float* ring_T;               // [ring_size] (C - LB) / LB
     int LB, msum;
-    int gop;                     // lane mapping: operator groups per wave
     int lane_wlds, lane_wlds_eval;   // lane mapping: LDS bytes per wave (generation, ffs_evaluate)
     int mach[kMaxStages];
     int Pk[kMaxStages];          // sum over jobs of p[j][k]
@@ -411,8 +410,9 @@ __device__ __forceinline__ void build_ap(uint32_t* AP, const uint16_t* A, const 
 // b+1, ..., n-1, 0, ..., a-1 with the genes not in the segment.  Lane k of
 // the group owns the cyclic offsets [kC, kC + C) of P2 (C = ceil(n / S)):
 // it counts the genes it keeps, an exclusive scan over the group's lanes
-// gives its first destination, and a second pass writes them.  With LEAN
-// only the two-pass path below is compiled (fewest registers).
+// gives its first destination, and a second pass writes them.  REG and MID
+// select which register-holding paths are compiled; without both only the
+// two-pass path remains (fewest registers).
 __device__ __forceinline__ uint32_t wrap_sub(uint32_t x, uint32_t n)
 {
     const uint32_t y = x - n;   // x < 2n: x mod n
@@ -435,92 +435,121 @@ __device__ __forceinline__ int group_exclusive_scan(int v, int k, int S)
     return incl - v;
 }
 
-template <bool LEAN = false>
+// Register path: lane k holds positions [o0, o1) of parent 1 and cyclic
+// offsets [o0, o1) of parent 2 (o1 - o0 <= CM), so the crossover costs three
+// LDS round trips plus the group scan.
+template <int CM>
+__device__ __forceinline__ void ox_reg(uint16_t* A, const uint16_t* B, uint16_t* V, uint32_t un, uint32_t ua,
+                                       uint32_t ub, bool doit, int k, int S, int o0, int o1)
+{
+    // lane k: positions [o0, o1) of parent 1 and cyclic offsets [o0, o1) of parent 2
+    uint32_t x1[CM], x2[CM];
+#pragma unroll
+    for (int u = 0; u < CM; ++u) {
+        const bool ok = o0 + u < o1;
+        x1[u] = A[ok ? o0 + u : 0];
+        x2[u] = B[ok ? wrap_sub(ub + 1u + (uint32_t)(o0 + u), un) : 0u];
+    }
+    if (doit) {
+#pragma unroll
+        for (int u = 0; u < CM; ++u)
+            if (o0 + u < o1) V[x1[u]] = (uint16_t)(o0 + u);
+    }
+    wave_sync();
+    uint32_t keep = 0;
+    int cnt = 0;
+#pragma unroll
+    for (int u = 0; u < CM; ++u) {
+        const uint32_t iv = V[x2[u]];
+        const bool kp = (o0 + u < o1) && (iv < ua || iv > ub);
+        keep |= kp ? (1u << u) : 0u;
+        cnt += kp ? 1 : 0;
+    }
+    const int pre = group_exclusive_scan(cnt, k, S);
+    if (doit) {
+        uint32_t dst = wrap_sub(ub + 1u + (uint32_t)pre, un);
+#pragma unroll
+        for (int u = 0; u < CM; ++u)
+            if (keep & (1u << u)) {
+                A[dst] = (uint16_t)x2[u];
+                dst = wrap_sub(dst + 1u, un);
+            }
+    }
+    wave_sync();
+}
+
+// Middle path: P2's genes held in registers between the count and the write.
+template <int CM>
+__device__ __forceinline__ void ox_mid(uint16_t* A, const uint16_t* B, uint16_t* V, uint32_t un, uint32_t ua,
+                                       uint32_t ub, bool doit, int k, int S, int o0, int o1)
+{
+    constexpr int U = 8;
+    if (doit) {
+        for (int t0 = o0; t0 < o1; t0 += U) {
+            uint32_t x[U];
+#pragma unroll
+            for (int u = 0; u < U; ++u) x[u] = A[t0 + u < o1 ? t0 + u : 0];
+#pragma unroll
+            for (int u = 0; u < U; ++u)
+                if (t0 + u < o1) V[x[u]] = (uint16_t)(t0 + u);
+        }
+    }
+    wave_sync();
+    uint32_t x2[CM];
+    unsigned long long keep = 0ull;
+    int cnt = 0;
+    if (doit) {
+#pragma unroll
+        for (int u = 0; u < CM; ++u) {
+            const uint32_t p = wrap_sub(ub + 1u + (uint32_t)(o0 + u), un);
+            x2[u] = B[(o0 + u < o1) ? p : 0u];
+        }
+#pragma unroll
+        for (int u = 0; u < CM; ++u) {
+            const uint32_t iv = V[x2[u]];
+            const bool kp = (o0 + u < o1) && (iv < ua || iv > ub);
+            keep |= kp ? (1ull << u) : 0ull;
+            cnt += kp ? 1 : 0;
+        }
+    }
+    const int pre = group_exclusive_scan(cnt, k, S);
+    if (doit) {
+        uint32_t dst = wrap_sub(ub + 1u + (uint32_t)pre, un);
+#pragma unroll
+        for (int u = 0; u < CM; ++u)
+            if (keep & (1ull << u)) {
+                A[dst] = (uint16_t)x2[u];
+                dst = wrap_sub(dst + 1u, un);
+            }
+    }
+    wave_sync();
+}
+
+template <bool REG = true, bool MID = true>
 __device__ __forceinline__ void ox_group(uint16_t* A, const uint16_t* B, uint16_t* V, int n, int a, int b,
                                          bool doit, int k, int S, int g)
 {
     const uint32_t un = (uint32_t)n, ua = (uint32_t)a, ub = (uint32_t)b;
     const int C = (n + S - 1) / S;
     const int o0 = k * C, o1 = (o0 + C < n) ? o0 + C : n;
-    if (!LEAN && C <= kOxReg) {
-        // lane k: positions [o0, o1) of parent 1 and cyclic offsets [o0, o1) of parent 2
-        uint32_t x1[kOxReg], x2[kOxReg];
-#pragma unroll
-        for (int u = 0; u < kOxReg; ++u) {
-            const bool ok = o0 + u < o1;
-            x1[u] = A[ok ? o0 + u : 0];
-            x2[u] = B[ok ? wrap_sub(ub + 1u + (uint32_t)(o0 + u), un) : 0u];
-        }
-        if (doit) {
-#pragma unroll
-            for (int u = 0; u < kOxReg; ++u)
-                if (o0 + u < o1) V[x1[u]] = (uint16_t)(o0 + u);
-        }
-        wave_sync();
-        uint32_t keep = 0;
-        int cnt = 0;
-#pragma unroll
-        for (int u = 0; u < kOxReg; ++u) {
-            const uint32_t iv = V[x2[u]];
-            const bool kp = (o0 + u < o1) && (iv < ua || iv > ub);
-            keep |= kp ? (1u << u) : 0u;
-            cnt += kp ? 1 : 0;
-        }
-        const int pre = group_exclusive_scan(cnt, k, S);
-        if (doit) {
-            uint32_t dst = wrap_sub(ub + 1u + (uint32_t)pre, un);
-#pragma unroll
-            for (int u = 0; u < kOxReg; ++u)
-                if (keep & (1u << u)) {
-                    A[dst] = (uint16_t)x2[u];
-                    dst = wrap_sub(dst + 1u, un);
-                }
-        }
-        wave_sync();
+    if (REG && C <= 8) {
+        ox_reg<8>(A, B, V, un, ua, ub, doit, k, S, o0, o1);
         return;
     }
-    if (!LEAN && C <= kOxMid) {
-        // P2's genes held in registers between the count and the write
-        constexpr int U = 8;
-        if (doit) {
-            for (int t0 = o0; t0 < o1; t0 += U) {
-                uint32_t x[U];
-#pragma unroll
-                for (int u = 0; u < U; ++u) x[u] = A[t0 + u < o1 ? t0 + u : 0];
-#pragma unroll
-                for (int u = 0; u < U; ++u)
-                    if (t0 + u < o1) V[x[u]] = (uint16_t)(t0 + u);
-            }
-        }
-        wave_sync();
-        uint32_t x2[kOxMid];
-        unsigned long long keep = 0ull;
-        int cnt = 0;
-        if (doit) {
-#pragma unroll
-            for (int u = 0; u < kOxMid; ++u) {
-                const uint32_t p = wrap_sub(ub + 1u + (uint32_t)(o0 + u), un);
-                x2[u] = B[(o0 + u < o1) ? p : 0u];
-            }
-#pragma unroll
-            for (int u = 0; u < kOxMid; ++u) {
-                const uint32_t iv = V[x2[u]];
-                const bool kp = (o0 + u < o1) && (iv < ua || iv > ub);
-                keep |= kp ? (1ull << u) : 0ull;
-                cnt += kp ? 1 : 0;
-            }
-        }
-        const int pre = group_exclusive_scan(cnt, k, S);
-        if (doit) {
-            uint32_t dst = wrap_sub(ub + 1u + (uint32_t)pre, un);
-#pragma unroll
-            for (int u = 0; u < kOxMid; ++u)
-                if (keep & (1ull << u)) {
-                    A[dst] = (uint16_t)x2[u];
-                    dst = wrap_sub(dst + 1u, un);
-                }
-        }
-        wave_sync();
+    if (REG && C <= 16) {
+        ox_reg<16>(A, B, V, un, ua, ub, doit, k, S, o0, o1);
+        return;
+    }
+    if (REG && C <= kOxReg) {
+        ox_reg<kOxReg>(A, B, V, un, ua, ub, doit, k, S, o0, o1);
+        return;
+    }
+    if (MID && C <= 32) {
+        ox_mid<32>(A, B, V, un, ua, ub, doit, k, S, o0, o1);
+        return;
+    }
+    if (MID && C <= kOxMid) {
+        ox_mid<kOxMid>(A, B, V, un, ua, ub, doit, k, S, o0, o1);
         return;
     }
     // long rows: two passes over P2 in chunks of U
@@ -591,16 +620,20 @@ struct CellMeta {
     bool cx, mx;
 };
 
-// The child of cell `slot` at generation `gen` from candidate stream `sub`
-// (sub 0 is the plain GA's stream): parents = the two best of (self, N, E,
-// S, W) by (makespan, that order) in generation gen-1, then order crossover
-// and swap mutation on the group's LDS rows.  A receives the child.
-template <bool LEAN = false>
-__device__ __forceinline__ CellMeta cellular_offspring(const InstDesc* I, const IslandDesc* L, int slot, uint32_t sub,
-                                                   int gen, int cur, uint16_t* A, uint16_t* B, uint16_t* V, int k,
-                                                   int S, int g, bool active)
+// Parents and draws of the child of cell `slot` at generation `gen` from
+// candidate stream `sub` (sub 0 is the plain GA's stream): P1, P2 = the two
+// best of (self, N, E, S, W) by (makespan, that order) in generation gen-1
+// (or the selection variant of the island), then the crossover flag and
+// cuts and the swap mutation's flag and positions.
+struct CellPlan {
+    int p1, p2;
+    CellMeta meta;
+};
+
+__device__ __forceinline__ CellPlan cell_plan(const InstDesc* I, const IslandDesc* L, int slot, uint32_t sub, int gen,
+                                              int cur)
 {
-    const int n = I->n, n_pad = I->n_pad;
+    const int n = I->n;
     const auto* mkp = as_global(L->mk[cur]);
     const int rows = L->rows, cols = L->cols;
     const int r = slot / cols, c = slot - r * cols;
@@ -665,28 +698,101 @@ __device__ __forceinline__ CellMeta cellular_offspring(const InstDesc* I, const 
         if (bo != 4 && v4 < sv) { sv = v4; ss = nb4; }
         if (ss < 0) ss = nb1;   // only when every makespan is INT_MAX (never)
     }
-    const bool cx = (uint64_t)draw32(bk, 0) < L->tc;
+    CellPlan pl;
+    pl.p1 = bs;
+    pl.p2 = ss;
+    pl.meta.mk1 = bv;
+    pl.meta.mk2 = sv;
+    pl.meta.cx = (uint64_t)draw32(bk, 0) < L->tc;
     const int u = (int)below(draw32(bk, 1), (uint32_t)n), w = (int)below(draw32(bk, 2), (uint32_t)n);
-    const int a = u < w ? u : w, b = u < w ? w : u;
-    const bool mx = (uint64_t)draw32(bk, 3) < L->tm;
-    const int mi = (int)below(draw32(bk, 4), (uint32_t)n);
-    int mj = mi + 1 + (int)below(draw32(bk, 5), (uint32_t)(n - 1));
+    pl.meta.a = u < w ? u : w;
+    pl.meta.b = u < w ? w : u;
+    pl.meta.mx = (uint64_t)draw32(bk, 3) < L->tm;
+    pl.meta.mi = (int)below(draw32(bk, 4), (uint32_t)n);
+    int mj = pl.meta.mi + 1 + (int)below(draw32(bk, 5), (uint32_t)(n - 1));
     if (mj >= n) mj -= n;
+    pl.meta.mj = mj;
+    return pl;
+}
+
+// The child of cell `slot` (cell_plan) built on the group's LDS rows: order
+// crossover of P1 and P2, then the swap mutation.  A receives the child.
+template <bool LEAN = false>
+__device__ __forceinline__ CellMeta cellular_offspring(const InstDesc* I, const IslandDesc* L, int slot, uint32_t sub,
+                                                   int gen, int cur, uint16_t* A, uint16_t* B, uint16_t* V, int k,
+                                                   int S, int g, bool active)
+{
+    const int n = I->n, n_pad = I->n_pad;
+    const CellPlan pl = cell_plan(I, L, slot, sub, gen, cur);
     const uint16_t* gp = L->genes[cur];
-    if (active) rows_g2l(A, gp + (size_t)bs * n_pad, B, gp + (size_t)ss * n_pad, n_pad, k, S);
+    if (active) rows_g2l(A, gp + (size_t)pl.p1 * n_pad, B, gp + (size_t)pl.p2 * n_pad, n_pad, k, S);
     wave_sync();
-    ox_group<LEAN>(A, B, V, n, a, b, cx && active, k, S, g);
-    swap_genes(A, mx && active && k == 0, mi, mj);
-    CellMeta meta;
-    meta.mk1 = bv;
-    meta.mk2 = sv;
-    meta.a = a;
-    meta.b = b;
-    meta.mi = mi;
-    meta.mj = mj;
-    meta.cx = cx;
-    meta.mx = mx;
-    return meta;
+    ox_group<!LEAN, !LEAN>(A, B, V, n, pl.meta.a, pl.meta.b, pl.meta.cx && active, k, S, g);
+    swap_genes(A, pl.meta.mx && active && k == 0, pl.meta.mi, pl.meta.mj);
+    return pl.meta;
+}
+
+// Draws of the pseudo island's slot `slot` at generation `gen` (Section
+// 4.1, complementary parents): X = the better of its pair (2q, 2q + 1) by
+// (makespan, slot) in generation gen-1; the even slot gets OX(X, Y), the odd
+// one OX(Y, X) with Y = reverse(X), both with the pair's cuts; each child has
+// its own mutation draws.
+struct PairPlan {
+    int xs;
+    bool odd, cx, mx;
+    int a, b, mi, mj;
+};
+
+__device__ __forceinline__ PairPlan pair_plan(const InstDesc* I, const IslandDesc* L, int slot, int gen, int cur)
+{
+    const int n = I->n;
+    const auto* mkp = as_global(L->mk[cur]);
+    const int q = slot >> 1;
+    PairPlan pl;
+    pl.odd = slot & 1;
+    pl.xs = (mkp[2 * q] <= mkp[2 * q + 1]) ? 2 * q : 2 * q + 1;
+    const uint64_t seed = I->seed, iid = (uint64_t)I->inst_id;
+    const uint32_t isl_local = (uint32_t)L->local;
+    const Block4 b0 = stream_block(seed, iid, isl_local, (uint32_t)q, 0, (uint32_t)gen, kPair, 0);
+    const Block4 b1 = stream_block(seed, iid, isl_local, (uint32_t)q, 0, (uint32_t)gen, kPair, 1);
+    pl.cx = (uint64_t)draw32(b0, 0) < L->tc;
+    const int u = (int)below(draw32(b0, 1), (uint32_t)n), w = (int)below(draw32(b0, 2), (uint32_t)n);
+    pl.a = u < w ? u : w;
+    pl.b = u < w ? w : u;
+    const uint32_t dm = pl.odd ? draw32(b0, 6) : draw32(b0, 3);
+    const uint32_t di = pl.odd ? draw32(b0, 7) : draw32(b0, 4);
+    const uint32_t dj = pl.odd ? draw32(b1, 0) : draw32(b0, 5);
+    pl.mx = (uint64_t)dm < L->tm;
+    pl.mi = (int)below(di, (uint32_t)n);
+    int mj = pl.mi + 1 + (int)below(dj, (uint32_t)(n - 1));
+    if (mj >= n) mj -= n;
+    pl.mj = mj;
+    return pl;
+}
+
+// A = X (even slot) or reverse(X) (odd slot) and B the other, from X in V.
+__device__ __forceinline__ void pair_parents(uint16_t* A, uint16_t* B, const uint16_t* V, int n, bool odd, int k,
+                                             int S, bool active)
+{
+    if (active) {
+        constexpr int U = 4;
+        for (int t0 = k; t0 < n; t0 += U * S) {
+            uint16_t x[U], xr[U];
+#pragma unroll
+            for (int u = 0; u < U; ++u) {
+                const int t = t0 + u * S < n ? t0 + u * S : n - 1;
+                x[u] = V[t];
+                xr[u] = V[n - 1 - t];
+            }
+#pragma unroll
+            for (int u = 0; u < U; ++u) {
+                const int t = t0 + u * S < n ? t0 + u * S : n - 1;
+                A[t] = odd ? xr[u] : x[u];
+                B[t] = odd ? x[u] : xr[u];
+            }
+        }
+    }
+    wave_sync();
 }
 
 // Pre-screen input of the chromosome in A (the group's S lanes): lane k sums
@@ -790,47 +896,13 @@ __device__ __forceinline__ CellMeta make_child(const InstDesc* I, const IslandDe
     } else {
         // pseudo: X = better of the pair, Y = reverse(X); even slot gets
         // OX(X, Y), odd slot OX(Y, X), with shared cut points.
-        const auto* mkp = as_global(L->mk[cur]);
-        const int q = slot >> 1;
-        const bool odd = slot & 1;
-        const int xs = (mkp[2 * q] <= mkp[2 * q + 1]) ? 2 * q : 2 * q + 1;
-        const Block4 b0 = stream_block(seed, iid, isl_local, (uint32_t)q, 0, (uint32_t)gen, kPair, 0);
-        const Block4 b1 = stream_block(seed, iid, isl_local, (uint32_t)q, 0, (uint32_t)gen, kPair, 1);
-        const bool cx = (uint64_t)draw32(b0, 0) < L->tc;
-        const int u = (int)below(draw32(b0, 1), (uint32_t)n), w = (int)below(draw32(b0, 2), (uint32_t)n);
-        const int a = u < w ? u : w, b = u < w ? w : u;
-        const uint32_t dm = odd ? draw32(b0, 6) : draw32(b0, 3);
-        const uint32_t di = odd ? draw32(b0, 7) : draw32(b0, 4);
-        const uint32_t dj = odd ? draw32(b1, 0) : draw32(b0, 5);
-        const bool mx = (uint64_t)dm < L->tm;
-        const int mi = (int)below(di, (uint32_t)n);
-        int mj = mi + 1 + (int)below(dj, (uint32_t)(n - 1));
-        if (mj >= n) mj -= n;
-        if (active) row_g2l(V, L->genes[cur] + (size_t)xs * n_pad, n_pad, k, S);
+        const PairPlan pl = pair_plan(I, L, slot, gen, cur);
+        if (active) row_g2l(V, L->genes[cur] + (size_t)pl.xs * n_pad, n_pad, k, S);
         wave_sync();
-        if (active) {
-            constexpr int U = 4;
-            for (int t0 = k; t0 < n; t0 += U * S) {
-                uint16_t x[U], xr[U];
-#pragma unroll
-                for (int u = 0; u < U; ++u) {
-                    const int t = t0 + u * S < n ? t0 + u * S : n - 1;
-                    x[u] = V[t];
-                    xr[u] = V[n - 1 - t];
-                }
-#pragma unroll
-                for (int u = 0; u < U; ++u) {
-                    const int t = t0 + u * S < n ? t0 + u * S : n - 1;
-                    A[t] = odd ? xr[u] : x[u];
-                    B[t] = odd ? x[u] : xr[u];
-                }
-            }
-        }
-        wave_sync();
-        ox_group<LEAN>(A, B, V, n, a, b, cx && active, k, S, g);
-        swap_genes(A, mx && active && k == 0, mi, mj);
+        pair_parents(A, B, V, n, pl.odd, k, S, active);
+        ox_group<!LEAN, !LEAN>(A, B, V, n, pl.a, pl.b, pl.cx && active, k, S, g);
+        swap_genes(A, pl.mx && active && k == 0, pl.mi, pl.mj);
     }
-
     return meta;
 }
 

@@ -26,11 +26,11 @@
 // that lie inside a stage's dispatch range run unguarded; the first and
 // last windows of a stage run with per-slot (wave-uniform) guards.
 //
-// The generation kernel of this mapping builds each wave's 64 children with
-// the operators of ffs_kernels.h on groups of lanes (W = 64 / gop lanes per
-// group), writes them to the next generation's rows, decodes them one per
-// lane from there, then writes back the parent's row of every cellular cell
-// whose child is not strictly better.
+// The generation kernel of this mapping builds each wave's 64 children one
+// after the other with the operators of ffs_kernels.h on all 64 lanes,
+// writes them to the next generation's rows, decodes them one per lane from
+// there, then writes back the parent's row of every cellular cell whose
+// child is not strictly better.
 #pragma once
 #include "ffs_kernels.h"
 
@@ -39,11 +39,11 @@ namespace flowshop {
 constexpr int kLaneD = 16;           // slots per window
 constexpr int kLaneMaxMsum = 160;    // machine entries per lane (sum over stages) kept in LDS
 
-// LDS of one wave of the lane generation kernel: the operators' rows of
-// `gop` groups, later reused for the decode state (64 lanes x msum keys).
-__host__ __device__ inline size_t lane_gen_wave_lds(int gop, int n_pad, int msum)
+// LDS of one wave of the lane generation kernel: the operators' three rows,
+// later reused for the decode state (64 lanes x msum keys).
+__host__ __device__ inline size_t lane_gen_wave_lds(int n_pad, int msum)
 {
-    const size_t ops = (size_t)gop * group_stride(n_pad) * 2;
+    const size_t ops = (size_t)group_stride(n_pad) * 2;
     const size_t st = (size_t)64 * msum * 4;
     return align16(ops > st ? ops : st);
 }
@@ -264,7 +264,6 @@ __global__ void __launch_bounds__(512) k_generation_lane(const InstDesc* __restr
     const InstDesc* I = insts + wi.inst;
     const IslandDesc* L = isls + wi.island;
     const int n = I->n, S = I->S, n_pad = I->n_pad, jb = I->jb;
-    const int gop = I->gop, W = kWave / gop;
 
     PT* pT = reinterpret_cast<PT*>(ffs_smem);
     stage_pt<PT>(pT, I->pT, S, n_pad);
@@ -278,18 +277,86 @@ __global__ void __launch_bounds__(512) k_generation_lane(const InstDesc* __restr
     const int wcount = wi.count - w0 < 0 ? 0 : (wi.count - w0 > kWave ? kWave : wi.count - w0);
     const int sbase = wi.slot0 + w0;
 
-    // children, a group of W lanes per child, into the next generation's rows
+    // children, one at a time on all 64 lanes, into the next generation's
+    // rows.  Lane c first takes the parents and draws of child c (one Philox
+    // block per cell, two per pair); while a child is built, the parents'
+    // rows of the next one are already on their way into registers.
     {
-        const int g = lane / W, k = lane - g * W;
-        uint16_t* A = reinterpret_cast<uint16_t*>(wbase) + (size_t)g * group_stride(n_pad);
+        uint16_t* A = reinterpret_cast<uint16_t*>(wbase);
         uint16_t* B = A + n_pad;
         uint16_t* V = B + n_pad;
-        for (int r0 = 0; r0 < wcount; r0 += gop) {
-            const bool active = r0 + g < wcount;
-            const int slot = sbase + (active ? r0 + g : 0);
-            make_child<true>(I, L, slot, 0u, gen, cur, mode, A, B, V, k, W, g, active);
-            if (active) row_l2g(L->genes[nxt] + (size_t)slot * n_pad, A, n_pad, k, W);
-            wave_sync();
+        if (mode == 1) {
+            for (int c = 0; c < wcount; ++c) {
+                make_child<true>(I, L, sbase + c, 0u, gen, cur, 1, A, B, V, lane, kWave, 0, true);
+                row_l2g(L->genes[nxt] + (size_t)(sbase + c) * n_pad, A, n_pad, lane, kWave);
+                wave_sync();
+            }
+        } else if (wcount > 0) {
+            const bool cell = L->kind == 0;
+            const int pslot = sbase + (lane < wcount ? lane : 0);
+            uint32_t w_src, w_cut, w_mut;
+            if (cell) {
+                const CellPlan pl = cell_plan(I, L, pslot, 0u, gen, cur);
+                w_src = (uint32_t)pl.p1 | ((uint32_t)pl.p2 << 16);
+                w_cut = (uint32_t)pl.meta.a | ((uint32_t)pl.meta.b << 12) | (pl.meta.cx ? 1u << 24 : 0u) |
+                        (pl.meta.mx ? 1u << 25 : 0u);
+                w_mut = (uint32_t)pl.meta.mi | ((uint32_t)pl.meta.mj << 12);
+            } else {
+                const PairPlan pl = pair_plan(I, L, pslot, gen, cur);
+                w_src = (uint32_t)pl.xs | (pl.odd ? 1u << 31 : 0u);
+                w_cut = (uint32_t)pl.a | ((uint32_t)pl.b << 12) | (pl.cx ? 1u << 24 : 0u) | (pl.mx ? 1u << 25 : 0u);
+                w_mut = (uint32_t)pl.mi | ((uint32_t)pl.mj << 12);
+            }
+            const int nv = n_pad >> 3;                   // 16-byte vectors per row
+            constexpr int PV = 2;                         // vectors per lane per row held in registers
+            const bool pre = nv <= PV * kWave;            // rows of up to 1024 genes
+            const auto* g4 = as_global(reinterpret_cast<const u32x4*>(L->genes[cur]));
+            u32x4 ra[PV], rb[PV];
+            auto fetch = [&](int c) {
+                const uint32_t src = (uint32_t)__builtin_amdgcn_readlane((int)w_src, c);
+                const size_t r1 = (size_t)(cell ? (src & 0xFFFFu) : (src & 0x7FFFFFFFu)) * nv;
+                const size_t r2 = (size_t)(src >> 16) * nv;
+#pragma unroll
+                for (int v = 0; v < PV; ++v) {
+                    const int x = lane + v * kWave;
+                    if (x < nv) {
+                        ra[v] = g4[r1 + x];
+                        if (cell) rb[v] = g4[r2 + x];
+                    }
+                }
+            };
+            if (pre) fetch(0);
+            for (int c = 0; c < wcount; ++c) {
+                const uint32_t src = (uint32_t)__builtin_amdgcn_readlane((int)w_src, c);
+                const uint32_t cut = (uint32_t)__builtin_amdgcn_readlane((int)w_cut, c);
+                const uint32_t mut = (uint32_t)__builtin_amdgcn_readlane((int)w_mut, c);
+                const int slot = sbase + c;
+                if (pre) {
+                    u32x4* da = reinterpret_cast<u32x4*>(cell ? A : V);
+                    u32x4* db = reinterpret_cast<u32x4*>(B);
+#pragma unroll
+                    for (int v = 0; v < PV; ++v) {
+                        const int x = lane + v * kWave;
+                        if (x < nv) {
+                            da[x] = ra[v];
+                            if (cell) db[x] = rb[v];
+                        }
+                    }
+                } else if (cell) {
+                    rows_g2l(A, L->genes[cur] + (size_t)(src & 0xFFFFu) * n_pad, B,
+                             L->genes[cur] + (size_t)(src >> 16) * n_pad, n_pad, lane, kWave);
+                } else {
+                    row_g2l(V, L->genes[cur] + (size_t)(src & 0x7FFFFFFFu) * n_pad, n_pad, lane, kWave);
+                }
+                wave_sync();
+                if (pre && c + 1 < wcount) fetch(c + 1);
+                if (!cell) pair_parents(A, B, V, n, (src >> 31) != 0u, lane, kWave, true);
+                ox_group<true, false>(A, B, V, n, (int)(cut & 0xFFFu), (int)((cut >> 12) & 0xFFFu),
+                                      ((cut >> 24) & 1u) != 0u, lane, kWave, 0);
+                swap_genes(A, ((cut >> 25) & 1u) != 0u && lane == 0, (int)(mut & 0xFFFu), (int)(mut >> 12));
+                row_l2g(L->genes[nxt] + (size_t)slot * n_pad, A, n_pad, lane, kWave);
+                wave_sync();
+            }
         }
     }
     // the rows just written are read back by other lanes of this wave
