@@ -78,9 +78,11 @@ __device__ __forceinline__ void lane_stage(uint32_t (&r)[kLaneD], uint32_t (&key
 #pragma unroll
     for (int i = 0; i < kLaneD; ++i) {
         if (!GUARD || ((act >> i) & 1u)) {
+            // start = max(machine free, job ready): the larger key has the
+            // larger (or equal) time in its high bits
             const uint32_t o = key[0];
-            const uint32_t f = o >> jb, rd = r[i] >> jb;
-            const uint32_t c = (f > rd ? f : rd) + pj[i];
+            const uint32_t mx = o > r[i] ? o : r[i];
+            const uint32_t c = (mx >> jb) + pj[i];
             const uint32_t nk = (c << jb) | jj[i];
             if (M == 1) {
                 key[0] = nk;
