@@ -54,6 +54,8 @@ def parse():
     ap.add_argument("--waves-per-block", type=int, default=None)
     ap.add_argument("--mapping", type=int, default=-1, choices=[-1, 0, 1],
                     help="decode mapping: -1 automatic, 0 one lane per stage, 1 one lane per chromosome")
+    ap.add_argument("--no-autotune", action="store_true",
+                    help="batched workload: skip the per-shape tile autotuner (outside the timed region)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=12.0)
     ap.add_argument("--surrogate-seconds", type=float, default=8.0,
@@ -571,11 +573,21 @@ def measure(name: str, seed: int, steps: int, warmup: int, args) -> dict:
     for v in ws:
         ctx.add_instance(v["m"], v["p"], v["islands"], interval=I, theta=v["theta"], topology=v["topology"], seed=101,
                          surrogate_k=args.prescreen_k, surrogate_warmup=5)
+    tiles = None
+    if name == "batched" and not args.no_autotune and args.mapping < 0 and args.waves_per_block is None:
+        from paper_1903_10722_amd.autotune import autotune_instances
+        t_tune = time.perf_counter()
+        tiles = autotune_instances(ctx)
+        t_tune = time.perf_counter() - t_tune
+        print(f"[bench] batched tiles tuned in {t_tune:.1f} s: " +
+              ", ".join(f"{k}: {v['tile']}" for k, v in tiles["groups"].items()) +
+              f"; ms per generation {tiles['ms_per_generation']}", file=sys.stderr, flush=True)
     t_bind = time.perf_counter()
     ctx.bind()
     t_bind = time.perf_counter() - t_bind
     stream = ctx.stream
-    kernel = "k_generation_lane" if ctx.mapping() == 1 else "k_generation"
+    used = ctx.mapping()
+    kernel = {0: "k_generation", 1: "k_generation_lane", 2: "k_generation_lane+k_generation"}[used]
 
     for _ in range(warmup):
         ctx.evolve(I)
@@ -614,6 +626,12 @@ def measure(name: str, seed: int, steps: int, warmup: int, args) -> dict:
         for v in ws:
             ctx2.add_instance(v["m"], v["p"], v["islands"], interval=0, theta=v["theta"], topology=v["topology"],
                               seed=101)
+        if tiles:
+            from paper_1903_10722_amd.autotune import group_key
+            for i, inst in enumerate(ctx2.instances):
+                t = tiles["groups"][group_key(inst)]["tile"]
+                if t:
+                    ctx2.set_instance_tile(i, t[0], t[1])
         ctx2.bind()
         L = 16
         ctx2.evolve(L)
@@ -639,7 +657,9 @@ def measure(name: str, seed: int, steps: int, warmup: int, args) -> dict:
                                                   f"; learned pre-screen k={args.prescreen_k}"),
                    "machines": [int(x) for x in m] if len(ws) == 1 else "per instance",
                    "decodes_per_generation": decodes_per_gen, "generations_per_step": I,
-                   "mapping": "per lane" if kernel == "k_generation_lane" else "per stage"},
+                   "mapping": {0: "per stage", 1: "per lane", 2: "per instance (autotuned)"}[used],
+                   **({"tiles": {k: v["tile"] for k, v in tiles["groups"].items()},
+                       "tuning_ms_per_generation": tiles["ms_per_generation"]} if tiles else {})},
         "generations_per_s": gens / (ms / 1e3),
         "best_makespan": best["makespan"],
         "best_found_generation": best["generation"],

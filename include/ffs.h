@@ -148,9 +148,25 @@ int ffs_set_waves_per_block(ffs_ctx *ctx, int32_t waves);
  * counts <= 160 and no pre-screen; otherwise per stage is used whatever the
  * request.  Results never depend on the mapping.  May be called before or
  * after ffs_bind_workspace (after: waits for the stream and re-plans).
- * ffs_get_mapping reports the mapping the generation launches use (0 or 1). */
+ * ffs_get_mapping reports the mapping the generation launches use: 0 or 1,
+ * or 2 when instances use different ones (ffs_set_instance_tile).          */
 int ffs_set_mapping(ffs_ctx *ctx, int32_t mapping);
-int ffs_get_mapping(const ffs_ctx *ctx, int32_t *used);
+int ffs_get_mapping(ffs_ctx *ctx, int32_t *used);
+
+/* Tile of one instance (overrides the context's for it): mapping -1 / 0 / 1
+ * as in ffs_set_mapping (-1: the context's), waves per workgroup 1, 2, 4, 8
+ * (0: the context's; narrowed automatically while a workgroup would exceed
+ * the device's LDS).  Instances with the same tile and similar LDS needs
+ * share one launch per generation.  Results never depend on tiles.  Before
+ * or after ffs_bind_workspace (after: waits for the stream and re-plans).  */
+int ffs_set_instance_tile(ffs_ctx *ctx, int32_t inst, int32_t mapping, int32_t waves);
+
+/* When a generation has several launches (instances of different tiles or
+ * LDS needs), run them side by side on streams forked from and joined back
+ * into the context's stream (parallel branches of the captured graph), or
+ * one after another (enable = 0).  Default: side by side.  Results are
+ * identical.                                                               */
+int ffs_set_concurrent(ffs_ctx *ctx, int32_t enable);
 
 /* ffs_evolve replays whole migration epochs (or chunks of 16 generations
  * when nothing migrates) from one captured HIP graph when enable != 0 (the

@@ -26,7 +26,8 @@ EXPORTS = [
     "ffs_surrogate_params", "ffs_surrogate_set_params", "ffs_mlp_forward", "ffs_mlp_gradients",
     "ffs_mlp_train_step", "ffs_surrogate_candidates", "ffs_surrogate_choices", "ffs_surrogate_ring",
     "ffs_evaluate_host", "ffs_checkpoint_size", "ffs_checkpoint_save", "ffs_checkpoint_load",
-    "ffs_set_mapping", "ffs_get_mapping", "ffs_evaluate_noalloc",
+    "ffs_set_mapping", "ffs_get_mapping", "ffs_evaluate_noalloc", "ffs_set_instance_tile",
+    "ffs_set_concurrent",
 ]
 
 N_PARAMS = 394753
@@ -79,6 +80,8 @@ def load_library():
                                         ctypes.POINTER(GAConfig), u64, pi32]
     lib.ffs_set_waves_per_block.argtypes = [P, i32]
     lib.ffs_set_mapping.argtypes = [P, i32]
+    lib.ffs_set_instance_tile.argtypes = [P, i32, i32, i32]
+    lib.ffs_set_concurrent.argtypes = [P, i32]
     lib.ffs_evaluate_noalloc.argtypes = [P, i32, i32, pi32, pi32, P, i32, P]
     lib.ffs_get_mapping.argtypes = [P, pi32]
     lib.ffs_workspace_size.argtypes = [P, ctypes.POINTER(ctypes.c_size_t)]
@@ -276,8 +279,16 @@ class Context:
         """-1 automatic, 0 one lane per stage, 1 one lane per chromosome (ffs_set_mapping)."""
         self._check(self.lib.ffs_set_mapping(self._h, int(mapping)))
 
+    def set_instance_tile(self, inst: int, mapping: int = -1, waves: int = 0):
+        """Tile of one instance (ffs_set_instance_tile): mapping -1/0/1, waves 0/1/2/4/8."""
+        self._check(self.lib.ffs_set_instance_tile(self._h, int(inst), int(mapping), int(waves)))
+
+    def set_concurrent(self, enable: bool):
+        """Run a generation's launches side by side (True, the default) or in turn."""
+        self._check(self.lib.ffs_set_concurrent(self._h, 1 if enable else 0))
+
     def mapping(self) -> int:
-        """Mapping the generation launches use: 0 per stage, 1 per lane."""
+        """Mapping the generation launches use: 0 per stage, 1 per lane, 2 mixed."""
         v = ctypes.c_int32()
         self._check(self.lib.ffs_get_mapping(self._h, ctypes.byref(v)))
         return v.value

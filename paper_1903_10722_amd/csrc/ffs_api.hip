@@ -70,6 +70,8 @@ struct HostInstance {
     size_t lds = 0;               // LDS bytes of one generation workgroup
     size_t lane_wlds = 0, lane_wlds_eval = 0;   // lane mapping: LDS bytes per wave
     bool lane_ok = false;         // the lane mapping can run this instance
+    int tile_map = -1, tile_wpb = 0;   // requested tile (-1 / 0: the context's)
+    int map_eff = 0, wpb_eff = 4;      // tile the generation launches use
     int lds_bucket = 0, cls = 0;  // its LDS class
 };
 
@@ -181,12 +183,17 @@ struct ffs_ctx {
     size_t off_stage = 0;            // host-pointer decode: staged rows and results
     int max_work = 0;
     int n_isl = 0, n_work = 0, n_pairs = 0, max_size = 0, max_edges = 0, n_cls = 1;
-    std::vector<int> cls_w0;         // work range of LDS class k: [cls_w0[k], cls_w0[k+1])
+    std::vector<int> cls_w0;         // work range of class k: [cls_w0[k], cls_w0[k+1])
     std::vector<size_t> cls_lds;     // LDS bytes of class k's launch
+    std::vector<void*> cls_kern;     // generation kernel of class k
+    std::vector<int> cls_wpb;        // waves per workgroup of class k
+    int max_lds = 65536;             // dynamic LDS bytes a workgroup may use on this device
+    bool concurrent = true;          // classes of one generation run side by side
+    std::vector<hipStream_t> aux;    // streams of classes 1.. (forked from `stream`)
+    std::vector<hipEvent_t> fork_ev; // fork and join events, one per class
     int mm = 2, ptb = 1;
     size_t lds_gen = 0, lds_sort = 0;
     bool any_ring = false;
-    void* kgen = nullptr;
     void* keval = nullptr;
     std::vector<WorkItem> work;
     std::vector<PairDesc> pairs;
@@ -253,32 +260,44 @@ void layout(ffs_ctx* c)
     }
     c->mm = round_mmax(mmax);
     c->ptb = (maxP <= 255) ? 1 : 2;
+    // the context's mapping for instances without a tile of their own
     {
-        bool ok = c->mm <= 8;
         long long total = 0;
-        for (auto& I : c->inst) {
-            ok = ok && I.lane_ok && I.cfg.surrogate_k <= 1;
+        for (auto& I : c->inst)
             for (auto& L : I.isl) total += L.size;
-        }
-        c->lane = ok && (c->mapping == 1 || (c->mapping < 0 && total >= kLaneAutoMin));
+        c->lane = c->mapping == 1 || (c->mapping < 0 && total >= kLaneAutoMin);
     }
-    // LDS classes: instances whose workgroups need LDS within the same
-    // half-octave bucket (8 KB * sqrt(2)^b) share a launch sized for the
-    // class, so small instances are not held to the occupancy of the
-    // largest one
-    std::vector<int> buckets;
+    // each instance's tile: mapping (the lane mapping only where it can run)
+    // and waves per workgroup, narrowed until its workgroup fits in LDS
     for (auto& I : c->inst) {
-        I.lds = align16((size_t)I.S * ((size_t)I.n_pad * c->ptb + 4)) +
-                (size_t)c->wpb * (c->lane ? I.lane_wlds : wave_lds_bytes(I.G, I.n_pad));
+        const int want = I.tile_map >= 0 ? I.tile_map : (c->lane ? 1 : 0);
+        I.map_eff = (want == 1 && I.lane_ok && c->mm <= 8 && I.cfg.surrogate_k <= 1) ? 1 : 0;
+        I.wpb_eff = I.tile_wpb > 0 ? I.tile_wpb : c->wpb;
+        for (;;) {
+            I.lds = align16((size_t)I.S * ((size_t)I.n_pad * c->ptb + 4)) +
+                    (size_t)I.wpb_eff * (I.map_eff ? I.lane_wlds : wave_lds_bytes(I.G, I.n_pad));
+            if (I.lds <= (size_t)c->max_lds || I.wpb_eff == 1) break;
+            I.wpb_eff >>= 1;
+        }
+    }
+    // classes: instances with the same tile whose workgroups need LDS within
+    // the same half-octave bucket (8 KB * sqrt(2)^b) share a launch sized for
+    // the class, so small instances are not held to the occupancy of the
+    // largest one
+    std::vector<long long> keys;
+    auto class_key = [](const HostInstance& I) {
+        return ((long long)I.lds_bucket << 8) | ((long long)I.wpb_eff << 1) | I.map_eff;
+    };
+    for (auto& I : c->inst) {
         int b = 0;
         while ((size_t)(8192.0 * std::pow(1.41421356, (double)b)) < I.lds) ++b;
         I.lds_bucket = b;
-        if (std::find(buckets.begin(), buckets.end(), b) == buckets.end()) buckets.push_back(b);
+        const long long k = class_key(I);
+        if (std::find(keys.begin(), keys.end(), k) == keys.end()) keys.push_back(k);
     }
-    std::sort(buckets.begin(), buckets.end(), std::greater<int>());
-    for (auto& I : c->inst)
-        I.cls = (int)(std::find(buckets.begin(), buckets.end(), I.lds_bucket) - buckets.begin());
-    c->n_cls = (int)buckets.size();
+    std::sort(keys.begin(), keys.end(), std::greater<long long>());
+    for (auto& I : c->inst) I.cls = (int)(std::find(keys.begin(), keys.end(), class_key(I)) - keys.begin());
+    c->n_cls = (int)keys.size();
     // work items: per island, chunks of (waves per block) x G chromosomes,
     // ordered by cost (n * S * count), largest first
     c->work.clear();
@@ -286,7 +305,7 @@ void layout(ffs_ctx* c)
     int isl_base = 0;
     for (size_t ii = 0; ii < c->inst.size(); ++ii) {
         auto& I = c->inst[ii];
-        const int chunk = c->wpb * (c->lane ? kWave : I.G);
+        const int chunk = I.wpb_eff * (I.map_eff ? kWave : I.G);
         for (size_t x = 0; x < I.isl.size(); ++x) {
             for (int s0 = 0; s0 < I.isl[x].size; s0 += chunk) {
                 WorkItem w;
@@ -331,10 +350,16 @@ void layout(ffs_ctx* c)
     c->cls_lds.assign(c->n_cls, 0);
     for (auto& w : c->work) c->cls_w0[c->inst[w.inst].cls + 1] += 1;
     for (int k = 0; k < c->n_cls; ++k) c->cls_w0[k + 1] += c->cls_w0[k];
-    for (auto& I : c->inst) c->cls_lds[I.cls] = std::max(c->cls_lds[I.cls], I.lds);
+    c->cls_kern.assign(c->n_cls, nullptr);
+    c->cls_wpb.assign(c->n_cls, 1);
+    for (auto& I : c->inst) {
+        c->cls_lds[I.cls] = std::max(c->cls_lds[I.cls], I.lds);
+        c->cls_kern[I.cls] = I.map_eff ? pick_gen_lane(c->mm, c->ptb) : pick_gen(c->mm, c->ptb);
+        c->cls_wpb[I.cls] = I.wpb_eff;
+    }
     // the first class's launch carries the best-ever workgroup, whose scratch
     // is dynamic LDS too
-    if (c->n_cls > 0) c->cls_lds[0] = std::max(c->cls_lds[0], fold_lds_bytes(64 * c->wpb));
+    if (c->n_cls > 0) c->cls_lds[0] = std::max(c->cls_lds[0], fold_lds_bytes(64 * c->cls_wpb[0]));
 
     c->off_ctl = take(sizeof(Control));
     c->off_insts = take(sizeof(InstDesc) * c->inst.size());
@@ -367,7 +392,7 @@ void layout(ffs_ctx* c)
         }
         c->lds_gen = std::max(c->lds_gen, I.lds);
     }
-    c->lds_gen = std::max(c->lds_gen, fold_lds_bytes(64 * c->wpb));
+    for (size_t k = 0; k < c->cls_lds.size(); ++k) c->lds_gen = std::max(c->lds_gen, c->cls_lds[k]);
     int R = 1;
     while (R * kSortThreads < c->max_size) R <<= 1;
     c->lds_sort = sort_lds_bytes(R);
@@ -459,16 +484,30 @@ int launch_generation(ffs_ctx* c, int mode)
         c->ev_pool.pop_back();
         HIP_TRY(c, hipEventRecord(e0, c->stream));
     }
-    // one launch per LDS class; the first has one workgroup more than work
-    // items, which folds the previous generation into the best-ever records
+    // one launch per class; the first has one workgroup more than work
+    // items, which folds the previous generation into the best-ever records.
+    // Classes touch disjoint islands, so with several of them the launches
+    // after the first go to their own streams, forked from and joined back
+    // into the context's stream (parallel branches when captured in a graph)
+    const bool fork = c->concurrent && c->n_cls > 1 && (int)c->aux.size() >= c->n_cls - 1;
+    if (fork) HIP_TRY(c, hipEventRecord(c->fork_ev[0], c->stream));
     cnt_off = 0;
     for (int k = 0; k < c->n_cls; ++k) {
         const int nw = c->cls_w0[k + 1] - c->cls_w0[k];
         extra = (mode == 0 && k == 0) ? 1 : 0;
         if (nw + extra == 0) continue;
         dwk = dw + c->cls_w0[k];
-        HIP_TRY(c, hipLaunchKernel(c->kgen, dim3((unsigned)(nw + extra)), dim3(64 * c->wpb), args, c->cls_lds[k],
-                                   c->stream));
+        hipStream_t st = c->stream;
+        if (fork && k > 0) {
+            st = c->aux[k - 1];
+            HIP_TRY(c, hipStreamWaitEvent(st, c->fork_ev[0], 0));
+        }
+        HIP_TRY(c, hipLaunchKernel(c->cls_kern[k], dim3((unsigned)(nw + extra)), dim3(64 * c->cls_wpb[k]), args,
+                                   c->cls_lds[k], st));
+        if (fork && k > 0) {
+            HIP_TRY(c, hipEventRecord(c->fork_ev[k], st));
+            HIP_TRY(c, hipStreamWaitEvent(c->stream, c->fork_ev[k], 0));
+        }
         cnt_off += nw + extra;
     }
     if (e0) {
@@ -546,18 +585,38 @@ int common_interval(const ffs_ctx* c)
     return I;
 }
 
-// Upload the work list of the current tile shape and size the LDS of the
-// generation kernel for it.
+// Generation kernels of the classes (dynamic LDS limit of each) and the
+// streams and events that run the classes side by side.
+int prepare_classes(ffs_ctx* c)
+{
+    for (int k = 0; k < c->n_cls; ++k) {
+        if (!c->cls_kern[k]) return fail(c, FFS_EUNSUPPORTED, "no kernel for %d machines", c->mm);
+        HIP_TRY(c, hipFuncSetAttribute(c->cls_kern[k], hipFuncAttributeMaxDynamicSharedMemorySize, (int)c->lds_gen));
+    }
+    while ((int)c->aux.size() < c->n_cls - 1) {
+        hipStream_t st = nullptr;
+        HIP_TRY(c, hipStreamCreateWithFlags(&st, hipStreamNonBlocking));
+        c->aux.push_back(st);
+    }
+    while ((int)c->fork_ev.size() < c->n_cls) {
+        hipEvent_t e = nullptr;
+        HIP_TRY(c, hipEventCreateWithFlags(&e, hipEventDisableTiming));
+        c->fork_ev.push_back(e);
+    }
+    return FFS_OK;
+}
+
+// Upload the work list of the current tiles and size the LDS of the
+// generation kernels for it.
 int apply_tile(ffs_ctx* c)
 {
     int max_lds = 0;
     HIP_TRY(c, hipDeviceGetAttribute(&max_lds, hipDeviceAttributeMaxSharedMemoryPerBlock, c->device));
     layout(c);
     if (c->lds_gen > (size_t)max_lds)
-        return fail(c, FFS_EUNSUPPORTED, "tile of %d waves needs %zu bytes of LDS (limit %d)", c->wpb, c->lds_gen, max_lds);
-    c->kgen = c->lane ? pick_gen_lane(c->mm, c->ptb) : pick_gen(c->mm, c->ptb);
-    if (!c->kgen) return fail(c, FFS_EUNSUPPORTED, "no kernel for %d machines", c->mm);
-    HIP_TRY(c, hipFuncSetAttribute(c->kgen, hipFuncAttributeMaxDynamicSharedMemorySize, (int)c->lds_gen));
+        return fail(c, FFS_EUNSUPPORTED, "a workgroup needs %zu bytes of LDS (limit %d)", c->lds_gen, max_lds);
+    int rc = prepare_classes(c);
+    if (rc) return rc;
     if (c->n_work)
         HIP_TRY(c, hipMemcpy(c->ws + c->off_work, c->work.data(), sizeof(WorkItem) * c->work.size(),
                              hipMemcpyHostToDevice));
@@ -700,12 +759,12 @@ int surrogate_score(ffs_ctx* c, float* Tout)
     const InstDesc* di = reinterpret_cast<const InstDesc*>(c->ws + c->off_insts);
     const IslandDesc* dl = reinterpret_cast<const IslandDesc*>(c->ws + c->off_isls);
     const Control* ctl = reinterpret_cast<const Control*>(c->ws + c->off_ctl);
-    const int per_block = c->wpb * I.G;
+    const int per_block = I.wpb_eff * I.G;
     const int blocks = (c->surr_Nc + per_block - 1) / per_block;
     int inst = c->surr, Nc = c->surr_Nc;
     uint16_t* X = at<uint16_t>(c, c->o_Xall);
     void* args[] = {(void*)&di, (void*)&dl, (void*)&inst, (void*)&ctl, (void*)&Nc, (void*)&X, (void*)&Tout};
-    HIP_TRY(c, hipLaunchKernel(c->kcand, dim3(blocks), dim3(64 * c->wpb), args, c->lds_gen, c->stream));
+    HIP_TRY(c, hipLaunchKernel(c->kcand, dim3(blocks), dim3(64 * I.wpb_eff), args, I.lds, c->stream));
     return mlp_forward(c, X, c->surr_Ncp, at<uint16_t>(c, c->o_H1all), at<uint16_t>(c, c->o_H2all),
                        at<float>(c, c->o_yall), c->surr_K, at<int>(c, c->o_choice), c->surr_Nc);
 }
@@ -847,10 +906,12 @@ int ffs_ctx_create(void* hip_stream, ffs_ctx** out)
     ffs_ctx* c = new (std::nothrow) ffs_ctx();
     if (!c) return FFS_ENOMEM;
     c->stream = reinterpret_cast<hipStream_t>(hip_stream);
-    if (hipGetDevice(&c->device) != hipSuccess) {
+    if (hipGetDevice(&c->device) != hipSuccess ||
+        hipDeviceGetAttribute(&c->max_lds, hipDeviceAttributeMaxSharedMemoryPerBlock, c->device) != hipSuccess) {
         delete c;
         return FFS_EDEVICE;
     }
+    c->max_lds -= 256;   // the generation kernels' static LDS (generation number, wave minima)
     *out = c;
     return FFS_OK;
 }
@@ -861,6 +922,8 @@ void ffs_ctx_destroy(ffs_ctx* c)
     if (c->bound) (void)hipStreamSynchronize(c->stream);
     drop_graph(c);
     for (auto e : c->ev_pool) (void)hipEventDestroy(e);
+    for (auto e : c->fork_ev) (void)hipEventDestroy(e);
+    for (auto st : c->aux) (void)hipStreamDestroy(st);
     for (auto& pr : c->ev_used) {
         (void)hipEventDestroy(pr.first);
         (void)hipEventDestroy(pr.second);
@@ -1024,10 +1087,50 @@ int ffs_set_mapping(ffs_ctx* c, int32_t mapping)
     return FFS_OK;
 }
 
-int ffs_get_mapping(const ffs_ctx* c, int32_t* used)
+int ffs_get_mapping(ffs_ctx* c, int32_t* used)
 {
     if (!c || !used) return FFS_EINVAL;
-    *used = c->lane ? 1 : 0;
+    if (c->inst.empty()) return fail(c, FFS_ESTATE, "no instance created");
+    if (!c->bound) layout(c);
+    int lane = 0, stage = 0;
+    for (const auto& I : c->inst) (I.map_eff ? lane : stage) += 1;
+    *used = (lane && stage) ? 2 : (lane ? 1 : 0);
+    return FFS_OK;
+}
+
+int ffs_set_instance_tile(ffs_ctx* c, int32_t inst, int32_t mapping, int32_t waves)
+{
+    if (!c) return FFS_EINVAL;
+    if (inst < 0 || inst >= (int)c->inst.size()) return fail(c, FFS_EINVAL, "no instance %d", inst);
+    if (mapping < -1 || mapping > 1) return fail(c, FFS_EINVAL, "mapping must be -1, 0 or 1");
+    if (waves != 0 && waves != 1 && waves != 2 && waves != 4 && waves != 8)
+        return fail(c, FFS_EINVAL, "waves must be 0, 1, 2, 4 or 8");
+    auto& I = c->inst[inst];
+    if (!c->bound) {
+        I.tile_map = mapping;
+        I.tile_wpb = waves;
+        return FFS_OK;
+    }
+    HIP_TRY(c, hipStreamSynchronize(c->stream));
+    const int om = I.tile_map, ow = I.tile_wpb;
+    I.tile_map = mapping;
+    I.tile_wpb = waves;
+    int rc = apply_tile(c);
+    if (rc) {
+        I.tile_map = om;
+        I.tile_wpb = ow;
+        (void)apply_tile(c);
+        return rc;
+    }
+    return FFS_OK;
+}
+
+int ffs_set_concurrent(ffs_ctx* c, int32_t enable)
+{
+    if (!c) return FFS_EINVAL;
+    if (c->bound) HIP_TRY(c, hipStreamSynchronize(c->stream));
+    c->concurrent = enable != 0;
+    drop_graph(c);
     return FFS_OK;
 }
 
@@ -1050,20 +1153,17 @@ int ffs_bind_workspace(ffs_ctx* c, void* dptr, size_t bytes)
     if (reinterpret_cast<uintptr_t>(dptr) % 256 != 0) return fail(c, FFS_EINVAL, "workspace must be 256-byte aligned");
     layout(c);
     if (bytes < c->total) return fail(c, FFS_ENOMEM, "workspace too small: %zu < %zu", bytes, c->total);
-    int max_lds = 0;
-    HIP_TRY(c, hipDeviceGetAttribute(&max_lds, hipDeviceAttributeMaxSharedMemoryPerBlock, c->device));
-    while (c->lds_gen > (size_t)max_lds && c->wpb > 1) {
-        c->wpb >>= 1;
-        layout(c);
-    }
+    const int max_lds = c->max_lds;
     if (c->lds_gen > (size_t)max_lds)
         return fail(c, FFS_EUNSUPPORTED, "instance needs %zu bytes of LDS per workgroup (limit %d)", c->lds_gen, max_lds);
     if (c->lds_sort > (size_t)max_lds)
         return fail(c, FFS_EUNSUPPORTED, "island sort needs %zu bytes of LDS (limit %d)", c->lds_sort, max_lds);
-    c->kgen = c->lane ? pick_gen_lane(c->mm, c->ptb) : pick_gen(c->mm, c->ptb);
     c->keval = pick_eval(c->mm, c->ptb);
-    if (!c->kgen || !c->keval) return fail(c, FFS_EUNSUPPORTED, "no kernel for %d machines", c->mm);
-    HIP_TRY(c, hipFuncSetAttribute(c->kgen, hipFuncAttributeMaxDynamicSharedMemorySize, (int)c->lds_gen));
+    if (!c->keval) return fail(c, FFS_EUNSUPPORTED, "no kernel for %d machines", c->mm);
+    {
+        int prc = prepare_classes(c);
+        if (prc) return prc;
+    }
     HIP_TRY(c, hipFuncSetAttribute(c->keval, hipFuncAttributeMaxDynamicSharedMemorySize, max_lds));
     if (void* kl = pick_eval_lane(c->mm, c->ptb))
         HIP_TRY(c, hipFuncSetAttribute(kl, hipFuncAttributeMaxDynamicSharedMemorySize, max_lds));

@@ -218,3 +218,77 @@ def test_automatic_mapping_choice():
     ctx = make_ctx([w], mapping=1)
     assert ctx.mapping() == 0
     ctx.close()
+
+
+def test_instance_tiles_and_concurrent_classes():
+    """Eight uneven batched instances (grids shrunk eightfold) with a tile
+    each (both mappings, 1 to 8 waves per workgroup): every instance follows
+    its oracle trajectory over 20 generations with migration every 10, and
+    running the launches one after another gives the same state."""
+    ensure_built()
+    ws = inputs.batched_workloads(count=8, batch_seed=7, scale=8)
+    tiles = [(1, 4), (0, 2), (1, 1), (0, 8), (1, 8), (0, 1), (1, 2), (0, 4)]
+    states = []
+    for concurrent in (True, False):
+        say(f"[lane] instance tiles, concurrent={concurrent}")
+        from paper_1903_10722_amd import Context
+        ctx = Context(device=0)
+        for w in ws:
+            ctx.add_instance(w["m"], w["p"], w["islands"], interval=w["interval"], seed=101)
+        for i, (m, wv) in enumerate(tiles):
+            ctx.set_instance_tile(i, m, wv)
+        ctx.set_concurrent(concurrent)
+        ctx.bind()
+        assert ctx.mapping() == 2
+        ctx.evolve(20)
+        states.append([[ctx.population(i, x) for x in range(2)] for i in range(len(ws))])
+        if concurrent:
+            for i, w in enumerate(ws):
+                ga = oracle_ga(w, inst=i)
+                ga.evolve(20)
+                assert_same_state(ctx, ga, i, 2, f"instance {i} tile {tiles[i]}")
+                assert ctx.best(i)["makespan"] == ga.best()["makespan"]
+        ctx.close()
+    for a, b in zip(states[0], states[1]):
+        for (g1, m1), (g2, m2) in zip(a, b):
+            assert np.array_equal(g1, g2) and np.array_equal(m1, m2)
+
+
+def test_instance_tile_change_after_bind():
+    """Re-tiling one instance of a bound context mid-run keeps the trajectory."""
+    ensure_built()
+    ws = inputs.batched_workloads(count=3, batch_seed=11, scale=8)
+    ctx = make_ctx(ws)
+    ctx.evolve(7)
+    ctx.set_instance_tile(1, 1, 2)
+    ctx.set_instance_tile(2, 0, 1)
+    ctx.evolve(8)
+    for i, w in enumerate(ws):
+        ga = oracle_ga(w, inst=i)
+        ga.evolve(15)
+        assert_same_state(ctx, ga, i, 2, f"instance {i}")
+    ctx.close()
+
+
+def test_per_shape_autotuner_keeps_trajectories():
+    """The per-group tile autotuner picks a tile for each group of instances
+    (timed on throwaway contexts holding the whole batch) and applies it; the
+    tuned context follows the oracle."""
+    ensure_built()
+    from paper_1903_10722_amd import Context
+    from paper_1903_10722_amd.autotune import autotune_instances
+    ws = inputs.batched_workloads(count=4, batch_seed=7, scale=8)
+    ctx = Context(device=0)
+    for w in ws:
+        ctx.add_instance(w["m"], w["p"], w["islands"], interval=w["interval"], seed=101)
+    rep = autotune_instances(ctx, generations=2, use_cache=False)
+    say(f"[lane] tuned tiles: {[(k, v['tile']) for k, v in rep['groups'].items()]}")
+    assert sum(v["instances"] for v in rep["groups"].values()) == len(ws)
+    assert rep["ms_per_generation"]["tuned"] <= rep["ms_per_generation"]["automatic"]
+    ctx.bind()
+    ctx.evolve(12)
+    for i, w in enumerate(ws):
+        ga = oracle_ga(w, inst=i)
+        ga.evolve(12)
+        assert_same_state(ctx, ga, i, 2, f"instance {i}")
+    ctx.close()
