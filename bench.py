@@ -25,6 +25,7 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 PEAK_INT_TOPS = 256 * 64 * 2.4e9 / 1e12   # 256 CUs x 64 lanes/clk x 2.4 GHz (32-bit integer VALU)
+PEAK_LDS_TBS = 256 * 128 * 2.4e9 / 1e12   # 256 CUs x 128 bytes/clk x 2.4 GHz (nominal LDS bandwidth)
 
 WORKLOADS = {
     "medium": "medium: n=100 jobs, 5 stages, machines U[1,5], p U[1,99]; cellular 64x64 (pc 0.9, pm 0.1) + "
@@ -177,6 +178,32 @@ def cpu_baseline(name: str, seed: int, seconds: float) -> dict:
                       f"one thread, {pinned}",
             "generations_per_s": r["gens"] / r["seconds"], "host_cpu": host_cpu(),
             "host_threads": len(os.sched_getaffinity(0)), "affinity": r["affinity"]}
+
+
+def lds_peak(repeats: int = 3) -> dict:
+    """Achievable LDS read bandwidth of this GPU: the probe kernel of
+    csrc/lds_probe.hip (conflict-free 16-byte reads on every CU), best of
+    `repeats` launches timed with HIP events."""
+    import ctypes
+
+    import torch
+    from paper_1903_10722_amd.build import PROBE_LIB
+    lib = ctypes.CDLL(PROBE_LIB)
+    lib.lds_probe.argtypes = [ctypes.c_void_p, ctypes.c_int, ctypes.c_int, ctypes.c_void_p,
+                              ctypes.POINTER(ctypes.c_float), ctypes.POINTER(ctypes.c_double)]
+    blocks, iters = 256 * 16, 4096
+    out = torch.empty(blocks * 256, dtype=torch.int32, device="cuda")
+    st = torch.cuda.current_stream()
+    best = 0.0
+    for _ in range(repeats):
+        ms, nbytes = ctypes.c_float(), ctypes.c_double()
+        rc = lib.lds_probe(ctypes.c_void_p(st.cuda_stream), blocks, iters, ctypes.c_void_p(out.data_ptr()),
+                           ctypes.byref(ms), ctypes.byref(nbytes))
+        if rc != 0:
+            raise RuntimeError(f"lds_probe failed with HIP error {rc}")
+        best = max(best, nbytes.value / (ms.value / 1e3))
+    return {"kernel": "k_lds_probe", "bytes_per_s": best, "TB_per_s": best / 1e12, "blocks": blocks,
+            "reads_per_thread": iters, "nominal_TB_per_s": PEAK_LDS_TBS}
 
 
 def host_cpu() -> str:
@@ -544,6 +571,14 @@ def main():
         "bind_and_generation0_s": head["bind_and_generation0_s"],
         "roofline": head["roofline"],
     }
+    try:
+        peak = lds_peak()
+        lm = out["roofline"]["lds_model"]
+        lm["probe_TB_per_s"] = peak["TB_per_s"]
+        lm["frac_of_probe"] = lm["achieved_TB_per_s"] / peak["TB_per_s"]
+        lm["frac_of_nominal"] = lm["achieved_TB_per_s"] / PEAK_LDS_TBS
+    except (OSError, RuntimeError) as e:
+        print(f"[bench] LDS probe unavailable: {e}", file=sys.stderr, flush=True)
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(args.workload, args.seed, args.cpu_seconds)
     if args.secondary and args.secondary != args.workload:
@@ -650,6 +685,11 @@ def measure(name: str, seed: int, steps: int, warmup: int, args) -> dict:
     ops_per_launch = sum(int(v["p"].shape[0]) * int(sum(int(x) + 6 for x in v["m"])) *
                          sum(x["size"] for x in v["islands"]) for v in ws)
     achieved = ops_per_launch / avg_s / 1e12
+    # the decode's LDS traffic in the model of its algorithmic bytes:
+    # 4 n (2 S + sum m) bytes per decode (processing-time reads, machine-free
+    # scans and writes), against the probe's achievable LDS bandwidth
+    lds_bytes = sum(4 * int(v["p"].shape[0]) * (2 * int(v["p"].shape[1]) + int(sum(int(x) for x in v["m"]))) *
+                    sum(x["size"] for x in v["islands"]) for v in ws)
     return {
         "value": decodes / (ms / 1e3),
         "ms_per_step": ms / steps,
@@ -669,7 +709,8 @@ def measure(name: str, seed: int, steps: int, warmup: int, args) -> dict:
         "roofline": {"bound": "alu", "achieved": achieved, "peak": PEAK_INT_TOPS, "unit": "TOP/s",
                      "frac": achieved / PEAK_INT_TOPS, "traffic": recorded_traffic(kernel, name),
                      "kernel": kernel, "avg_launch_us": avg_s * 1e6, "launches": launches, "timing": timing,
-                     "ops_per_launch": ops_per_launch},
+                     "ops_per_launch": ops_per_launch,
+                     "lds_model": {"bytes_per_launch": lds_bytes, "achieved_TB_per_s": lds_bytes / avg_s / 1e12}},
     }
 
 
