@@ -77,6 +77,8 @@ def _load():
     lib.or_cell_parents_sel.restype = None
     lib.or_ga_set_selection.argtypes = [ctypes.c_void_p, ctypes.c_int, ctypes.c_int]
     lib.or_ga_set_selection.restype = None
+    lib.or_ga_set_sweep.argtypes = [ctypes.c_void_p, ctypes.c_int, ctypes.c_int]
+    lib.or_ga_set_sweep.restype = None
     lib.or_migration_policy.argtypes = [ctypes.c_int64, ctypes.c_int64, ctypes.c_int64,
                                         ctypes.c_int64, ctypes.c_int64, ctypes.c_double,
                                         ctypes.POINTER(ctypes.c_int)]
@@ -247,6 +249,8 @@ class GA:
         for i, x in enumerate(self.islands):
             if x["kind"] == 0 and int(x.get("sel", 0)):
                 self._lib.or_ga_set_selection(self._h, i, int(x["sel"]))
+            if x["kind"] == 0 and int(x.get("sweep", 0)):
+                self._lib.or_ga_set_sweep(self._h, i, 1)
 
     def __del__(self):
         h = getattr(self, "_h", None)

@@ -21,7 +21,9 @@
  *     Implemented below as "dispatch, then stable sort" -- the plainest form.
  *   - Cellular GA (Section 4.1 operator level, Section 4.2): individuals on a
  *     2-D torus, two parents from the neighbourhood, one child, mutation,
- *     replace the cell if the child is strictly better; synchronous update.
+ *     replace the cell if the child is strictly better; synchronous update,
+ *     or, as an alternative reading of the update schedule, an asynchronous
+ *     line sweep (cells in row-major order, in place).
  *   - Pseudo GA (Section 4.1 operator level): fixed complementary parent
  *     pairs; children replace both parents.  Complement of a permutation is
  *     its reversal (reading of the binary lower layer).
@@ -278,6 +280,7 @@ typedef struct {
     int size;            /* number of individuals                            */
     uint64_t tc, tm;     /* crossover / mutation thresholds                  */
     int sel;             /* cellular parent selection variant (or_cell_parents_sel) */
+    int sweep;           /* cellular update: 0 synchronous, 1 line sweep     */
     int *genes;          /* size * n, current generation                     */
     int *mk;             /* size                                             */
 } or_island_t;
@@ -424,6 +427,15 @@ void or_ga_set_selection(void *h, int island, int sel)
     g->isl[island].sel = sel;
 }
 
+/* Update schedule of a cellular island: 0 synchronous (Section 4.2, every
+ * cell from generation g-1), 1 asynchronous line sweep (an alternative
+ * reading: cells in row-major order, in place).                            */
+void or_ga_set_sweep(void *h, int island, int sweep)
+{
+    or_ga_t *g = (or_ga_t *)h;
+    g->isl[island].sweep = sweep;
+}
+
 /* Test access: the offspring a cell would get at the next generation from
  * candidate stream `sub`, with its meta data (see cell_offspring).          */
 void or_ga_cell_candidate(void *h, int island, int slot, int sub, int *child, int *meta)
@@ -470,6 +482,30 @@ static void cellular_step(or_ga_t *g, int island)
     }
     free(I->genes); free(I->mk); free(child);
     I->genes = ng; I->mk = nm;
+    free(g->choice[island]);
+    g->choice[island] = NULL;
+}
+
+/* one generation of a cellular island as an asynchronous line sweep: the
+ * cells in row-major order, each updated in place, so a cell's parents are
+ * taken from the state its earlier neighbours have already reached in this
+ * generation.  Draws, operators and the strict replacement rule are those of
+ * cellular_step.                                                           */
+static void cellular_sweep(or_ga_t *g, int island)
+{
+    or_island_t *I = &g->isl[island];
+    int n = g->n;
+    int *child = (int *)malloc(sizeof(int) * (size_t)n);
+    for (int s = 0; s < I->size; ++s) {
+        int sub = g->choice[island] ? g->choice[island][s] : 0;
+        cell_offspring(g, island, s, sub, child, NULL);
+        int cm = (int)dec(g, child);
+        if (cm < I->mk[s]) {
+            memcpy(I->genes + (size_t)s * n, child, sizeof(int) * (size_t)n);
+            I->mk[s] = cm;
+        }
+    }
+    free(child);
     free(g->choice[island]);
     g->choice[island] = NULL;
 }
@@ -629,8 +665,12 @@ void or_ga_evolve(void *h, int G)
     for (int it = 0; it < G; ++it) {
         g->gen += 1;
         for (int i = 0; i < g->n_islands; ++i) {
-            if (g->isl[i].kind == 0) cellular_step(g, i);
-            else pseudo_step(g, i);
+            if (g->isl[i].kind == 0) {
+                if (g->isl[i].sweep) cellular_sweep(g, i);
+                else cellular_step(g, i);
+            } else {
+                pseudo_step(g, i);
+            }
         }
         update_best(g);
         if (g->interval > 0 && g->gen % g->interval == 0) or_ga_migrate(g);
@@ -648,8 +688,12 @@ void or_ga_step_island(void *h, int island)
 {
     or_ga_t *g = (or_ga_t *)h;
     g->gen += 1;
-    if (g->isl[island].kind == 0) cellular_step(g, island);
-    else pseudo_step(g, island);
+    if (g->isl[island].kind == 0) {
+        if (g->isl[island].sweep) cellular_sweep(g, island);
+        else cellular_step(g, island);
+    } else {
+        pseudo_step(g, island);
+    }
     g->gen -= 1;
 }
 

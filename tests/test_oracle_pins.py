@@ -672,3 +672,93 @@ def test_pseudo_step_takes_the_pair_stream():
     c1, c2 = oracle.pseudo_children(X, d, 1 << 32, 1 << 32)
     got = ga.population(0)[0]
     assert got[0].tolist() == c1.tolist() and got[1].tolist() == c2.tolist()
+
+
+def _unique_best_population(m, p, N, seed):
+    rng = np.random.default_rng(seed)
+    n = p.shape[0]
+    while True:
+        genes = np.stack([rng.permutation(n) for _ in range(N)]).astype(np.int32)
+        mk = np.array([oracle.decode(m, p, g) for g in genes], dtype=np.int32)
+        if (mk == mk.min()).sum() == 1:
+            return genes, mk
+
+
+def test_line_sweep_worked_example():
+    """Hand-traced line sweep on a 3 x 4 torus (tests/golden): which cells
+    hold the unique best after one generation when children copy P1, for
+    the row-major in-place sweep and for the synchronous update."""
+    g = gold("line_sweep_worked_example.json")
+    rows, cols, b = g["rows"], g["cols"], g["best_slot"]
+    m, p = inputs.make_instance(9, 3, 1, 3, seed=8)
+    genes, mk = _unique_best_population(m, p, rows * cols, seed=5)
+    best = int(np.argmin(mk))
+    genes[[b, best]] = genes[[best, b]]
+    mk[[b, best]] = mk[[best, b]]
+    for sweep, want in ((1, g["holders_sweep"]), (0, g["holders_synchronous"])):
+        cell = dict(inputs.cellular(rows, cols, 0.0, 0.0), sweep=sweep)
+        ga = oracle.GA(m, p, [cell, inputs.pseudo(4, 0.0, 0.0)], interval=0, seed=2)
+        ga.set_population(0, genes, mk)
+        ga.evolve(1)
+        g1, mk1 = ga.population(0)
+        got = sorted(s for s in range(rows * cols) if mk1[s] == mk[b])
+        assert got == want, (sweep, got)
+        for s in got:
+            assert np.array_equal(g1[s], genes[b])
+
+
+def test_line_sweep_spreads_the_best_in_one_generation():
+    """A unique best at the sweep's first cell reaches every cell of the
+    torus in one line-sweep generation (each later cell already sees its
+    updated north or west neighbour); the synchronous update reaches only
+    its von Neumann neighbours."""
+    rows, cols = 5, 6
+    m, p = inputs.make_instance(10, 3, 1, 3, seed=3)
+    genes, mk = _unique_best_population(m, p, rows * cols, seed=7)
+    best = int(np.argmin(mk))
+    genes[[0, best]] = genes[[best, 0]]
+    mk[[0, best]] = mk[[best, 0]]
+    near = {0, 1, cols - 1, cols, (rows - 1) * cols}
+    for sweep, want in ((1, set(range(rows * cols))), (0, near)):
+        cell = dict(inputs.cellular(rows, cols, 0.0, 0.0), sweep=sweep)
+        ga = oracle.GA(m, p, [cell, inputs.pseudo(4, 0.0, 0.0)], interval=0, seed=4)
+        ga.set_population(0, genes, mk)
+        ga.evolve(1)
+        _, mk1 = ga.population(0)
+        assert {s for s in range(rows * cols) if mk1[s] == mk[0]} == want, sweep
+
+
+def test_line_sweep_makespans_are_a_sequential_minimum_filter():
+    """Children that copy P1 under the strict replacement rule leave every
+    cell with the minimum makespan of its neighbourhood.  For the line sweep
+    that minimum is taken in row-major order over the state reached so far
+    (an in-place filter); for the synchronous update over generation g-1.
+    A non-square grid tells rows from columns; every row stays a copy of an
+    initial individual whose decode gives the cell's makespan."""
+    rows, cols = 4, 7
+    m, p = inputs.make_instance(11, 4, 1, 3, seed=9)
+    rng = np.random.default_rng(12)
+    genes = np.stack([rng.permutation(11) for _ in range(rows * cols)]).astype(np.int32)
+    mk = np.array([oracle.decode(m, p, g) for g in genes], dtype=np.int32)
+
+    def nbrs(s):
+        r, c = divmod(s, cols)
+        return [s, ((r - 1) % rows) * cols + c, r * cols + (c + 1) % cols, ((r + 1) % rows) * cols + c,
+                r * cols + (c - 1) % cols]
+
+    seq = mk.copy()
+    for s in range(rows * cols):
+        seq[s] = min(seq[x] for x in nbrs(s))
+    syn = np.array([min(mk[x] for x in nbrs(s)) for s in range(rows * cols)], dtype=np.int32)
+    assert not np.array_equal(seq, syn)
+    initial = {tuple(g) for g in genes.tolist()}
+    for sweep, want in ((1, seq), (0, syn)):
+        cell = dict(inputs.cellular(rows, cols, 0.0, 0.0), sweep=sweep)
+        ga = oracle.GA(m, p, [cell, inputs.pseudo(4, 0.0, 0.0)], interval=0, seed=5)
+        ga.set_population(0, genes, mk)
+        ga.evolve(1)
+        g1, mk1 = ga.population(0)
+        assert np.array_equal(mk1, want), sweep
+        for s in range(rows * cols):
+            assert tuple(g1[s].tolist()) in initial
+            assert oracle.decode(m, p, g1[s]) == mk1[s]
