@@ -63,6 +63,13 @@ enum {
  *               block each give x uniform in [0, 25), the neighbourhood
  *               positions x / 5 and x % 5, and the better of the two by
  *               (makespan, position) is the parent.
+ *          sweep (the paper gives one thread per cell, Section 4.2, and no
+ *          update order): 0 = synchronous, every cell from generation g-1;
+ *          1 = asynchronous line sweep, the cells in row-major order, each
+ *          seeing the cells before it already updated in this generation
+ *          (run as one launch per anti-diagonal r + c; needs the lane
+ *          mapping's limits: at most 8 machines per stage and 160 in all;
+ *          no pre-screen).
  *   kind 1 (pseudo): `size` individuals (even, >= 2) in fixed pairs; each pair
  *          mates its better member with that member's complement (the
  *          reversed permutation) and both children replace the pair.
@@ -73,6 +80,7 @@ typedef struct {
     int32_t size;         /* kind 1; ignored for kind 0 (rows*cols)           */
     double p_c, p_m;      /* in [0, 1]                                        */
     int32_t selection;    /* kind 0: 0, 1 or 2 (above); kind 1: must be 0     */
+    int32_t sweep;        /* kind 0: 0 or 1 (above); kind 1: must be 0        */
 } ffs_island_spec;
 
 /* Migration (paper Section 4.3).  Islands are paired (i, i + H), H = half the

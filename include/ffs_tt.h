@@ -23,7 +23,8 @@
  * its stage, the child kept if strictly better) or kind 1 (pseudo: pairs
  * (X, complement of X); the better of a pair mates with its complement by
  * two-point crossover with probability p_c, the two children replace the
- * pair; each child then mutates with probability p_m).  `selection` must be 0.
+ * pair; each child then mutates with probability p_m).  `selection` and
+ * `sweep` must be 0 (the update schedule is set per context, below).
  * Migration (Section 4.3, equations (1) and (2)) pairs island i with island
  * i + H (H = islands / 2) every `interval` generations on the fitness
  * max(E_max - objective, 0), E_max = WT * sum_j max(0, H_t - D_j) + H_t with

@@ -44,7 +44,7 @@ class FFSError(RuntimeError):
 class IslandSpec(ctypes.Structure):
     _fields_ = [("kind", ctypes.c_int32), ("rows", ctypes.c_int32), ("cols", ctypes.c_int32),
                 ("size", ctypes.c_int32), ("p_c", ctypes.c_double), ("p_m", ctypes.c_double),
-                ("selection", ctypes.c_int32)]
+                ("selection", ctypes.c_int32), ("sweep", ctypes.c_int32)]
 
 
 class GAConfig(ctypes.Structure):
@@ -175,7 +175,8 @@ class Context:
         specs = (IslandSpec * len(islands))()
         for i, x in enumerate(islands):
             specs[i] = IslandSpec(int(x["kind"]), int(x.get("rows", 0)), int(x.get("cols", 0)),
-                                  int(x.get("size", 0)), float(x["pc"]), float(x["pm"]), int(x.get("sel", 0)))
+                                  int(x.get("size", 0)), float(x["pc"]), float(x["pm"]), int(x.get("sel", 0)),
+                                  int(x.get("sweep", 0)))
         cfg = GAConfig(int(interval), int(topology), float(theta), int(surrogate_k), int(surrogate_warmup))
         out = ctypes.c_int32()
         self._check(self.lib.ffs_create_instance(self._h, n, S, _p32(m), _p32(p), specs, len(islands),

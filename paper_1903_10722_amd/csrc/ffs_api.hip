@@ -100,6 +100,16 @@ void* pick_gen(int mm, int ptb)
     return nullptr;
 }
 
+void* pick_cand_features(int sm, int ptb)
+{
+#define FFS_CASE(SM)                                                                             \
+    if (sm == SM) return ptb == 1 ? reinterpret_cast<void*>(&k_cand_features<SM, uint8_t>)      \
+                                  : reinterpret_cast<void*>(&k_cand_features<SM, uint16_t>);
+    FFS_CASE(8) FFS_CASE(16) FFS_CASE(24) FFS_CASE(32)
+#undef FFS_CASE
+    return nullptr;
+}
+
 void* pick_cand(int mm, int ptb)
 {
 #define FFS_CASE(M)                                                          \
@@ -156,6 +166,8 @@ constexpr int kBatch = 4096;    // training minibatch of the pre-screen
 constexpr size_t kStageBytes = (size_t)4 << 20;   // staging of ffs_evaluate_host
 constexpr int kRing = 65536;    // replay ring entries
 constexpr float kLr = 1e-3f, kBeta1 = 0.9f, kBeta2 = 0.999f, kEps = 1e-8f;
+constexpr int kBcSteps = 32768;
+constexpr int kSweepWaves = 2;   // waves per workgroup of a line-sweep launch  // Adam steps with a bias-correction table entry (both 1 in FP32 after)
 
 uint64_t rate_threshold(double p)
 {
@@ -197,15 +209,25 @@ struct ffs_ctx {
     void* keval = nullptr;
     std::vector<WorkItem> work;
     std::vector<PairDesc> pairs;
+    // line-sweep islands: one work item each, launched one anti-diagonal at a
+    // time after every generation launch
+    std::vector<WorkItem> sweep;
+    int sweep_diags = 0;
+    size_t off_sweep = 0, sweep_lds = 0;
+    void* sweep_kern = nullptr;
     // learned pre-screen (at most one instance per context)
     int surr = -1;                 // instance with the pre-screen, or -1
     int surr_K = 0, surr_warmup = 0, surr_cells = 0, surr_Nc = 0, surr_Ncp = 0;
-    long long adam_steps = 0;
     void* kcand = nullptr;
+    void* kcandf = nullptr;          // one-wave-per-cell candidate features (stages <= 32)
+    int cand_sm = 0, cand_rsb = 0;   // its stage tier and job-major row bytes
+    int cand_waves = 16;             // its waves per workgroup (cells per workgroup)
+    size_t o_pJ = 0;
     size_t o_w = 0, o_wb = 0, o_m = 0, o_v = 0, o_g = 0;
     size_t o_Xall = 0, o_H1all = 0, o_H2all = 0, o_yall = 0, o_Tall = 0, o_choice = 0;
     size_t o_idx = 0, o_Xb = 0, o_tb = 0, o_H1b = 0, o_H2b = 0, o_yb = 0, o_dy = 0, o_dZ2 = 0, o_dZ1 = 0;
     size_t o_part = 0, o_cpart = 0, o_dpart = 0, o_ringX = 0, o_ringT = 0;
+    size_t o_adam = 0, o_bc = 0;     // Adam step count (int64) + its corrections; correction table
     // graph of one migration epoch (or a fixed chunk when nothing migrates)
     bool use_graphs = true;
     hipGraphExec_t epoch_exec = nullptr;
@@ -323,6 +345,23 @@ void layout(ffs_ctx* c)
         isl_base += (int)I.isl.size();
     }
     c->n_pairs = (int)c->pairs.size();
+    // line-sweep islands (lane kernel, two waves: a torus of at most 16384
+    // cells has anti-diagonals of at most 128)
+    c->sweep.clear();
+    c->sweep_diags = 0;
+    c->sweep_lds = 0;
+    for (size_t ii = 0; ii < c->inst.size(); ++ii) {
+        const auto& I = c->inst[ii];
+        for (size_t x = 0; x < I.isl.size(); ++x) {
+            const auto& L = I.isl[x];
+            if (L.spec.kind != 0 || !L.spec.sweep) continue;
+            c->sweep.push_back(WorkItem{I.isl_base + (int)x, 0, L.size, (int)ii});
+            c->sweep_diags = std::max(c->sweep_diags, L.spec.rows + L.spec.cols - 1);
+            c->sweep_lds = std::max(c->sweep_lds, align16((size_t)I.S * ((size_t)I.n_pad * c->ptb + 4)) +
+                                                      (size_t)kSweepWaves * I.lane_wlds);
+        }
+    }
+    c->sweep_kern = c->sweep.empty() ? nullptr : pick_gen_lane(c->mm, c->ptb);
     // topology 2: the ring c0, p0, c1, p1, ... as a list of edges after the pairs
     c->max_edges = 0;
     for (size_t ii = 0; ii < c->inst.size(); ++ii) {
@@ -374,6 +413,7 @@ void layout(ffs_ctx* c)
     c->off_counts = take(sizeof(int) * (max_work + 16));
     c->off_stage = take(kStageBytes);
     c->off_pairs = take(sizeof(PairDesc) * std::max<size_t>(1, c->pairs.size()));
+    c->off_sweep = take(sizeof(WorkItem) * std::max<size_t>(1, c->sweep.size()));
     c->lds_gen = 0;
     for (auto& I : c->inst) {
         I.off_pT = take((size_t)I.S * I.n_pad * c->ptb);
@@ -393,6 +433,7 @@ void layout(ffs_ctx* c)
         c->lds_gen = std::max(c->lds_gen, I.lds);
     }
     for (size_t k = 0; k < c->cls_lds.size(); ++k) c->lds_gen = std::max(c->lds_gen, c->cls_lds[k]);
+    c->lds_gen = std::max(c->lds_gen, c->sweep_lds);
     int R = 1;
     while (R * kSortThreads < c->max_size) R <<= 1;
     c->lds_sort = sort_lds_bytes(R);
@@ -429,10 +470,16 @@ void layout(ffs_ctx* c)
         c->o_dZ2 = take(Bt * kHidden * 2);
         c->o_dZ1 = take(Bt * kHidden * 2);
         c->o_part = take((size_t)(kBatch / 128) * kHidden * kHidden * 4);
-        c->o_cpart = take((size_t)(kBatch / 64) * kHidden * 4);
+        c->o_cpart = take((size_t)(kBatch / 64) * 3 * kHidden * 4);
         c->o_dpart = take((size_t)(kBatch / 64) * 4);
         c->o_ringX = take((size_t)kRing * kFeat * 2);
         c->o_ringT = take((size_t)kRing * 4);
+        c->o_adam = take(16);
+        c->o_bc = take((size_t)kBcSteps * 8);
+        // job-major processing times for the candidates' features
+        c->cand_sm = I.S <= 8 ? 8 : (I.S <= 16 ? 16 : (I.S <= 24 ? 24 : (I.S <= 32 ? 32 : 0)));
+        c->cand_rsb = (c->cand_sm * c->ptb + 15) / 16 * 16;
+        c->o_pJ = take((size_t)I.n * std::max(c->cand_rsb, 16));
     }
     c->total = off;
 }
@@ -509,6 +556,16 @@ int launch_generation(ffs_ctx* c, int mode)
             HIP_TRY(c, hipStreamWaitEvent(c->stream, c->fork_ev[k], 0));
         }
         cnt_off += nw + extra;
+    }
+    if (mode == 0 && !c->sweep.empty()) {
+        // line sweep: anti-diagonal d of every line-sweep island, d in order
+        const WorkItem* ds = reinterpret_cast<const WorkItem*>(c->ws + c->off_sweep);
+        int smode = 2, diag = 0, none = 0;
+        void* sargs[] = {(void*)&di, (void*)&dl, (void*)&ds, (void*)&ctl, (void*)&n_inst, (void*)&smode, (void*)&diag,
+                         (void*)&none};
+        for (diag = 0; diag < c->sweep_diags; ++diag)
+            HIP_TRY(c, hipLaunchKernel(c->sweep_kern, dim3(1, (unsigned)c->sweep.size()), dim3(64 * kSweepWaves), sargs,
+                                       c->sweep_lds, c->stream));
     }
     if (e0) {
         HIP_TRY(c, hipEventRecord(e1, c->stream));
@@ -593,6 +650,10 @@ int prepare_classes(ffs_ctx* c)
         if (!c->cls_kern[k]) return fail(c, FFS_EUNSUPPORTED, "no kernel for %d machines", c->mm);
         HIP_TRY(c, hipFuncSetAttribute(c->cls_kern[k], hipFuncAttributeMaxDynamicSharedMemorySize, (int)c->lds_gen));
     }
+    if (!c->sweep.empty()) {
+        if (!c->sweep_kern) return fail(c, FFS_EUNSUPPORTED, "the line sweep needs at most 8 machines per stage");
+        HIP_TRY(c, hipFuncSetAttribute(c->sweep_kern, hipFuncAttributeMaxDynamicSharedMemorySize, (int)c->lds_gen));
+    }
     while ((int)c->aux.size() < c->n_cls - 1) {
         hipStream_t st = nullptr;
         HIP_TRY(c, hipStreamCreateWithFlags(&st, hipStreamNonBlocking));
@@ -666,22 +727,6 @@ int mlp_forward(ffs_ctx* c, const uint16_t* X, int rows, uint16_t* H1, uint16_t*
     return FFS_OK;
 }
 
-// column sums of a [rows][cols] BF16 matrix (optionally weighted by dy) into
-// out[cols] (and sum(dy) into *dsum), deterministic two-stage order
-int colsum(ffs_ctx* c, const uint16_t* X, const float* dy, int rows, int cols, float* out, float* dsum)
-{
-    const int chunks = rows / 64;
-    float* part = at<float>(c, c->o_cpart);
-    float* dpart = at<float>(c, c->o_dpart);
-    hipLaunchKernelGGL(k_colsum, dim3((cols + 255) / 256, chunks), dim3(256), 0, c->stream, X, dy, rows, cols, part,
-                       dsum ? dpart : nullptr);
-    hipLaunchKernelGGL(k_sum_splits, dim3((cols + 255) / 256), dim3(256), 0, c->stream, part, chunks, (size_t)cols,
-                       out);
-    if (dsum)
-        hipLaunchKernelGGL(k_sum_splits, dim3(1), dim3(256), 0, c->stream, dpart, chunks, (size_t)1, dsum);
-    return FFS_OK;
-}
-
 // Gradients of mean((y - t)^2) for `rows` rows of X into grad (parameter
 // layout).  H1, H2, y, dZ2, dZ1 are the batch buffers unless given.
 int mlp_gradients(ffs_ctx* c, const uint16_t* X, const float* t, int rows, float* grad, uint16_t* dZ2o,
@@ -700,8 +745,6 @@ int mlp_gradients(ffs_ctx* c, const uint16_t* X, const float* t, int rows, float
     if (rc) return rc;
     hipLaunchKernelGGL(k_mlp_dz2, dim3(rows * kHidden / 256), dim3(256), 0, c->stream, y, t, H2, wb + kP_w3, rows, dy,
                        dZ2);
-    colsum(c, H2, dy, rows, kHidden, grad + kP_w3, grad + kP_b3);
-    colsum(c, dZ2, nullptr, rows, kHidden, grad + kP_b2, nullptr);
     const int splits = rows / 128;
     rc = gemm<true, false, EPI_F32>(c, dZ2, H1, kHidden, kHidden, rows, kHidden, kHidden, part, nullptr, kHidden,
                                     nullptr, nullptr, splits);
@@ -711,7 +754,23 @@ int mlp_gradients(ffs_ctx* c, const uint16_t* X, const float* t, int rows, float
     rc = gemm<false, false, EPI_MASK_BF16>(c, dZ2, wb + kP_W2, rows, kHidden, kHidden, kHidden, kHidden, nullptr, dZ1,
                                            kHidden, nullptr, H1, 1);
     if (rc) return rc;
-    colsum(c, dZ1, nullptr, rows, kHidden, grad + kP_b1, nullptr);
+    {
+        // bias gradients and the output layer's weight gradient: column
+        // sums of dy * H2, dZ2 and dZ1 in one launch, then their chunk sums
+        Colsum3 cs;
+        cs.X[0] = H2;
+        cs.X[1] = dZ2;
+        cs.X[2] = dZ1;
+        cs.out[0] = grad + kP_w3;
+        cs.out[1] = grad + kP_b2;
+        cs.out[2] = grad + kP_b1;
+        float* cpart = at<float>(c, c->o_cpart);
+        float* dpart = at<float>(c, c->o_dpart);
+        const int chunks = rows / 64;
+        hipLaunchKernelGGL(k_colsum3, dim3(1, chunks, 3), dim3(256), 0, c->stream, cs, (const float*)dy, cpart, dpart);
+        hipLaunchKernelGGL(k_colsum3_sum, dim3((3 * kHidden + 1 + 255) / 256), dim3(256), 0, c->stream, cs,
+                           (const float*)cpart, chunks, (const float*)dpart, grad + kP_b3);
+    }
     rc = gemm<true, false, EPI_F32>(c, dZ1, X, kHidden, kFeat, rows, kHidden, kFeat, part, nullptr, kFeat, nullptr,
                                     nullptr, splits);
     if (rc) return rc;
@@ -723,26 +782,25 @@ int mlp_gradients(ffs_ctx* c, const uint16_t* X, const float* t, int rows, float
 
 int mlp_adam(ffs_ctx* c)
 {
-    c->adam_steps += 1;
-    const double st = (double)c->adam_steps;
-    const float bc1 = (float)(1.0 - std::pow((double)kBeta1, st));
-    const float bc2 = (float)(1.0 - std::pow((double)kBeta2, st));
+    float* bc = reinterpret_cast<float*>(c->ws + c->o_adam + 8);
+    hipLaunchKernelGGL(k_adam_prep, dim3(1), dim3(64), 0, c->stream, at<long long>(c, c->o_adam),
+                       at<const float2>(c, c->o_bc), kBcSteps, bc);
     hipLaunchKernelGGL(k_adam, dim3((kParams + 255) / 256), dim3(256), 0, c->stream, at<float>(c, c->o_w),
                        at<float>(c, c->o_m), at<float>(c, c->o_v), at<const float>(c, c->o_g),
-                       at<uint16_t>(c, c->o_wb), kParams, kLr, kBeta1, kBeta2, kEps, bc1, bc2);
+                       at<uint16_t>(c, c->o_wb), kParams, kLr, kBeta1, kBeta2, kEps, (const float*)bc);
     HIP_TRY(c, hipGetLastError());
     return FFS_OK;
 }
 
-// One training step after generation g: a minibatch from the replay ring,
-// gradients, Adam.
-int surrogate_train(ffs_ctx* c, int g)
+// One training step after the last completed generation (read from the
+// control block): a minibatch from the replay ring, gradients, Adam.
+int surrogate_train(ffs_ctx* c)
 {
     const auto& I = c->inst[c->surr];
-    const long long filled = std::min<long long>((long long)g * c->surr_cells, kRing);
     int* idx = at<int>(c, c->o_idx);
+    const Control* ctl = reinterpret_cast<const Control*>(c->ws + c->off_ctl);
     hipLaunchKernelGGL(k_batch_idx, dim3((kBatch / 8 + 255) / 256), dim3(256), 0, c->stream, (uint64_t)I.seed,
-                       (uint64_t)c->surr, g, (int)filled, kBatch, idx);
+                       (uint64_t)c->surr, ctl, c->surr_cells, kRing, kBatch, idx);
     hipLaunchKernelGGL(k_gather_batch, dim3(kBatch / 8), dim3(256), 0, c->stream, at<const uint16_t>(c, c->o_ringX),
                        at<const float>(c, c->o_ringT), idx, kBatch, at<uint16_t>(c, c->o_Xb), at<float>(c, c->o_tb));
     int rc = mlp_gradients(c, at<const uint16_t>(c, c->o_Xb), at<const float>(c, c->o_tb), kBatch,
@@ -759,12 +817,21 @@ int surrogate_score(ffs_ctx* c, float* Tout)
     const InstDesc* di = reinterpret_cast<const InstDesc*>(c->ws + c->off_insts);
     const IslandDesc* dl = reinterpret_cast<const IslandDesc*>(c->ws + c->off_isls);
     const Control* ctl = reinterpret_cast<const Control*>(c->ws + c->off_ctl);
-    const int per_block = I.wpb_eff * I.G;
-    const int blocks = (c->surr_Nc + per_block - 1) / per_block;
     int inst = c->surr, Nc = c->surr_Nc;
     uint16_t* X = at<uint16_t>(c, c->o_Xall);
-    void* args[] = {(void*)&di, (void*)&dl, (void*)&inst, (void*)&ctl, (void*)&Nc, (void*)&X, (void*)&Tout};
-    HIP_TRY(c, hipLaunchKernel(c->kcand, dim3(blocks), dim3(64 * I.wpb_eff), args, I.lds, c->stream));
+    if (!Tout && c->kcandf) {
+        // features only: one wave per cell, up to 16 cells per workgroup
+        int cells = c->surr_cells;
+        const int wv = c->cand_waves;
+        void* args[] = {(void*)&di, (void*)&dl, (void*)&inst, (void*)&ctl, (void*)&cells, (void*)&X};
+        HIP_TRY(c, hipLaunchKernel(c->kcandf, dim3((cells + wv - 1) / wv), dim3(64 * wv), args,
+                                   cand_lds_bytes(I.n, I.n_pad, c->cand_rsb, wv), c->stream));
+    } else {
+        const int per_block = I.wpb_eff * I.G;
+        const int blocks = (c->surr_Nc + per_block - 1) / per_block;
+        void* args[] = {(void*)&di, (void*)&dl, (void*)&inst, (void*)&ctl, (void*)&Nc, (void*)&X, (void*)&Tout};
+        HIP_TRY(c, hipLaunchKernel(c->kcand, dim3(blocks), dim3(64 * I.wpb_eff), args, I.lds, c->stream));
+    }
     return mlp_forward(c, X, c->surr_Ncp, at<uint16_t>(c, c->o_H1all), at<uint16_t>(c, c->o_H2all),
                        at<float>(c, c->o_yall), c->surr_K, at<int>(c, c->o_choice), c->surr_Nc);
 }
@@ -838,7 +905,7 @@ uint64_t fingerprint(const ffs_ctx* c)
         h = fnv(h, I.p.data(), I.p.size() * sizeof(int));
         for (const auto& L : I.isl) {
             const ffs_island_spec& s = L.spec;
-            const int32_t v[5] = {s.kind, s.rows, s.cols, L.size, s.selection};
+            const int32_t v[6] = {s.kind, s.rows, s.cols, L.size, s.selection, s.sweep};
             h = fnv(h, v, sizeof v);
             h = fnv(h, &s.p_c, sizeof s.p_c);
             h = fnv(h, &s.p_m, sizeof s.p_m);
@@ -864,17 +931,25 @@ size_t ckpt_bytes(const ffs_ctx* c)
     return b;
 }
 
-// The (device offset, bytes) pieces of the image after the header, in order.
-std::vector<std::pair<size_t, size_t>> ckpt_pieces(const ffs_ctx* c)
+// The pieces of the image after the header, in order: device offset and
+// bytes, and for rows of permutations (u16, n_pad per row) the genes per row,
+// whose padding the image stores as zeros (kernels leave it undefined).
+struct CkptPiece {
+    size_t off, bytes;
+    int n = 0, n_pad = 0;
+    CkptPiece(size_t o, size_t b, int nn = 0, int np = 0) : off(o), bytes(b), n(nn), n_pad(np) {}
+};
+
+std::vector<CkptPiece> ckpt_pieces(const ffs_ctx* c)
 {
-    std::vector<std::pair<size_t, size_t>> v;
+    std::vector<CkptPiece> v;
     const int par = c->gen & 1;
     for (const auto& I : c->inst) {
         v.emplace_back(I.off_best_rec, 4 * sizeof(int32_t));
-        v.emplace_back(I.off_best_perm, (size_t)I.n_pad * 2);
+        v.emplace_back(I.off_best_perm, (size_t)I.n_pad * 2, I.n, I.n_pad);
         v.emplace_back(I.off_counters, 2 * sizeof(int64_t));
         for (const auto& L : I.isl) {
-            v.emplace_back(L.off_genes[par], (size_t)L.size * I.n_pad * 2);
+            v.emplace_back(L.off_genes[par], (size_t)L.size * I.n_pad * 2, I.n, I.n_pad);
             v.emplace_back(L.off_mk[par], (size_t)L.size * 4);
         }
     }
@@ -885,6 +960,7 @@ std::vector<std::pair<size_t, size_t>> ckpt_pieces(const ffs_ctx* c)
         v.emplace_back(c->o_ringX, (size_t)kRing * kFeat * 2);
         v.emplace_back(c->o_ringT, (size_t)kRing * 4);
         v.emplace_back(c->o_choice, (size_t)c->surr_cells * 4);
+        v.emplace_back(c->o_adam, sizeof(int64_t));   // Adam steps taken
     }
     return v;
 }
@@ -990,12 +1066,14 @@ int ffs_create_instance(ffs_ctx* c, int32_t n, int32_t S, const int32_t* machine
             if (sp.rows < 3 || sp.cols < 3) return fail(c, FFS_EINVAL, "island %d: grid must be at least 3x3", x);
             if (sp.selection < 0 || sp.selection > 2)
                 return fail(c, FFS_EINVAL, "island %d: selection must be 0, 1 or 2", x);
+            if (sp.sweep != 0 && sp.sweep != 1) return fail(c, FFS_EINVAL, "island %d: sweep must be 0 or 1", x);
             if ((long long)sp.rows * sp.cols > 16384)
                 return fail(c, FFS_EUNSUPPORTED, "island %d: more than 16384 individuals", x);
             L.size = sp.rows * sp.cols;
         } else if (sp.kind == 1) {
             if (sp.size < 2 || (sp.size % 2) != 0) return fail(c, FFS_EINVAL, "island %d: pseudo size must be even >= 2", x);
             if (sp.selection != 0) return fail(c, FFS_EINVAL, "island %d: selection applies to cellular islands", x);
+            if (sp.sweep != 0) return fail(c, FFS_EINVAL, "island %d: the line sweep applies to cellular islands", x);
             if (sp.size > 16384) return fail(c, FFS_EUNSUPPORTED, "island %d: more than 16384 individuals", x);
             L.size = sp.size;
         } else {
@@ -1027,6 +1105,13 @@ int ffs_create_instance(ffs_ctx* c, int32_t n, int32_t S, const int32_t* machine
     I.lane_wlds = lane_gen_wave_lds(I.n_pad, I.msum);
     I.lane_wlds_eval = lane_eval_wave_lds(n, I.msum);
     I.lane_ok = I.msum <= kLaneMaxMsum && I.mmax <= 8;
+    for (int x = 0; x < n_islands; ++x) {
+        if (!islands[x].sweep) continue;
+        if (!I.lane_ok)
+            return fail(c, FFS_EUNSUPPORTED, "island %d: the line sweep needs the lane mapping (at most 8 machines "
+                        "per stage, at most %d in all)", x, kLaneMaxMsum);
+        if (cfg->surrogate_k > 1) return fail(c, FFS_EUNSUPPORTED, "island %d: the line sweep has no pre-screen", x);
+    }
     I.n_cells = 0;
     for (auto& L : I.isl) {
         L.cell_base = (L.spec.kind == 0) ? I.n_cells : -1;
@@ -1214,6 +1299,8 @@ int ffs_bind_workspace(ffs_ctx* c, void* dptr, size_t bytes)
             d.surr_X = reinterpret_cast<const uint16_t*>(c->ws + c->o_Xall);
             d.ring_X = reinterpret_cast<uint16_t*>(c->ws + c->o_ringX);
             d.ring_T = reinterpret_cast<float*>(c->ws + c->o_ringT);
+            d.pJ = c->ws + c->o_pJ;
+            d.pj_row_bytes = c->cand_rsb;
         }
         hi[ii] = d;
         for (size_t x = 0; x < I.isl.size(); ++x) {
@@ -1238,6 +1325,7 @@ int ffs_bind_workspace(ffs_ctx* c, void* dptr, size_t bytes)
             e.local = (int)x;
             e.cell_base = L.cell_base;
             e.sel = L.spec.kind == 0 ? L.spec.selection : 0;
+            e.sweep = L.spec.kind == 0 ? L.spec.sweep : 0;
             hl.push_back(e);
         }
         isl_base += (int)I.isl.size();
@@ -1258,6 +1346,9 @@ int ffs_bind_workspace(ffs_ctx* c, void* dptr, size_t bytes)
                              hipMemcpyHostToDevice));
     if (c->n_pairs)
         HIP_TRY(c, hipMemcpy(c->ws + c->off_pairs, c->pairs.data(), sizeof(PairDesc) * c->pairs.size(),
+                             hipMemcpyHostToDevice));
+    if (!c->sweep.empty())
+        HIP_TRY(c, hipMemcpy(c->ws + c->off_sweep, c->sweep.data(), sizeof(WorkItem) * c->sweep.size(),
                              hipMemcpyHostToDevice));
     for (auto& I : c->inst) {
         // processing times, stage-major, padded rows
@@ -1282,6 +1373,28 @@ int ffs_bind_workspace(ffs_ctx* c, void* dptr, size_t bytes)
         c->kcand = pick_cand(c->mm, c->ptb);
         if (!c->kcand) return fail(c, FFS_EUNSUPPORTED, "no candidate kernel for %d machines", c->mm);
         HIP_TRY(c, hipFuncSetAttribute(c->kcand, hipFuncAttributeMaxDynamicSharedMemorySize, (int)c->lds_gen));
+        c->kcandf = pick_cand_features(c->cand_sm, c->ptb);
+        if (c->kcandf) {
+            const auto& I = c->inst[c->surr];
+            c->cand_waves = 16;
+            while (c->cand_waves > 1 && cand_lds_bytes(I.n, I.n_pad, c->cand_rsb, c->cand_waves) > (size_t)c->max_lds)
+                c->cand_waves >>= 1;
+            const size_t lds = cand_lds_bytes(I.n, I.n_pad, c->cand_rsb, c->cand_waves);
+            if (lds > (size_t)c->max_lds) {
+                c->kcandf = nullptr;
+            } else {
+                HIP_TRY(c, hipFuncSetAttribute(c->kcandf, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
+                // job-major table, rows of cand_sm entries, zero past the last stage
+                std::vector<uint8_t> pj((size_t)I.n * c->cand_rsb, 0);
+                for (int j = 0; j < I.n; ++j)
+                    for (int k = 0; k < I.S; ++k) {
+                        const int v = I.p[(size_t)j * I.S + k];
+                        if (c->ptb == 1) pj[(size_t)j * c->cand_rsb + k] = (uint8_t)v;
+                        else reinterpret_cast<uint16_t*>(pj.data() + (size_t)j * c->cand_rsb)[k] = (uint16_t)v;
+                    }
+                HIP_TRY(c, hipMemcpy(c->ws + c->o_pJ, pj.data(), pj.size(), hipMemcpyHostToDevice));
+            }
+        }
         hipLaunchKernelGGL(k_mlp_init, dim3((kParams + 255) / 256), dim3(256), 0, c->stream, (uint64_t)c->inst[c->surr].seed,
                            (uint64_t)c->surr, at<float>(c, c->o_w), at<uint16_t>(c, c->o_wb), at<float>(c, c->o_m),
                            at<float>(c, c->o_v));
@@ -1290,7 +1403,24 @@ int ffs_bind_workspace(ffs_ctx* c, void* dptr, size_t bytes)
                            at<uint32_t>(c, c->o_Xall), xw);
         hipLaunchKernelGGL(k_zero_u32, dim3((c->surr_cells + 255) / 256), dim3(256), 0, c->stream,
                            at<uint32_t>(c, c->o_choice), (size_t)c->surr_cells);
-        c->adam_steps = 0;
+        // the replay ring starts empty (zeros, so that checkpoint images of
+        // equal states are equal)
+        const size_t rw = (size_t)kRing * kFeat / 2;
+        hipLaunchKernelGGL(k_zero_u32, dim3((unsigned)((rw + 255) / 256)), dim3(256), 0, c->stream,
+                           at<uint32_t>(c, c->o_ringX), rw);
+        hipLaunchKernelGGL(k_zero_u32, dim3((kRing + 255) / 256), dim3(256), 0, c->stream,
+                           at<uint32_t>(c, c->o_ringT), (size_t)kRing);
+        // Adam: no steps taken; bias corrections of steps 1..kBcSteps
+        std::vector<float> bct(2 * (size_t)kBcSteps);
+        for (int t = 1; t <= kBcSteps; ++t) {
+            bct[2 * (size_t)(t - 1)] = (float)(1.0 - std::pow((double)kBeta1, (double)t));
+            bct[2 * (size_t)(t - 1) + 1] = (float)(1.0 - std::pow((double)kBeta2, (double)t));
+        }
+        if (bct[2 * (size_t)kBcSteps - 2] != 1.f || bct[2 * (size_t)kBcSteps - 1] != 1.f)
+            return fail(c, FFS_EUNSUPPORTED, "Adam bias corrections are not 1 after %d steps", kBcSteps);
+        HIP_TRY(c, hipMemcpy(c->ws + c->o_bc, bct.data(), bct.size() * 4, hipMemcpyHostToDevice));
+        const int64_t zero16[2] = {0, 0};
+        HIP_TRY(c, hipMemcpy(c->ws + c->o_adam, zero16, sizeof zero16, hipMemcpyHostToDevice));
         HIP_TRY(c, hipGetLastError());
     }
     c->bound = true;
@@ -1347,18 +1477,24 @@ int ffs_evolve(ffs_ctx* c, int32_t generations)
     if (generations < 0) return fail(c, FFS_EINVAL, "generations must be >= 0");
     const int I = common_interval(c);
     // whole epochs replay one captured graph: the kernels read the generation
-    // from the control block, so the same graph serves every epoch
-    const bool graphs = c->use_graphs && !c->timing && c->stream != nullptr && I >= 0 && c->surr < 0;
+    // (and the pre-screen its Adam step) from device memory, so the same
+    // graph serves every epoch; with the pre-screen only epochs past its
+    // warm-up, where every generation scores candidates
+    const bool graphs = c->use_graphs && !c->timing && c->stream != nullptr && I >= 0;
     const int L = (I > 0) ? I : 16;
     int left = generations;
     while (left > 0) {
-        if (graphs && c->gen % L == 0 && left >= L) {
+        if (graphs && c->gen % L == 0 && left >= L && (c->surr < 0 || c->gen >= c->surr_warmup)) {
             if (!c->epoch_exec || c->epoch_len != L) {
                 drop_graph(c);
                 hipGraph_t graph = nullptr;
                 HIP_TRY(c, hipStreamBeginCapture(c->stream, hipStreamCaptureModeRelaxed));
                 int crc = FFS_OK;
-                for (int t = 0; t < L && crc == FFS_OK; ++t) crc = launch_generation(c, 0);
+                for (int t = 0; t < L && crc == FFS_OK; ++t) {
+                    if (c->surr >= 0) crc = surrogate_score(c, nullptr);
+                    if (crc == FFS_OK) crc = launch_generation(c, 0);
+                    if (crc == FFS_OK && c->surr >= 0) crc = surrogate_train(c);
+                }
                 if (crc == FFS_OK && I > 0) crc = launch_migration(c, -1);
                 hipError_t ec = hipStreamEndCapture(c->stream, &graph);
                 if (crc) {
@@ -1388,7 +1524,7 @@ int ffs_evolve(ffs_ctx* c, int32_t generations)
         if (rc) return rc;
         c->gen = g;
         if (c->surr >= 0) {
-            rc = surrogate_train(c, g);
+            rc = surrogate_train(c);
             if (rc) return rc;
         }
         if (migration_due(c, g)) {
@@ -1660,15 +1796,23 @@ int ffs_checkpoint_save(ffs_ctx* c, void* host, size_t bytes)
     h.n_inst = (int32_t)c->inst.size();
     memcpy(out, &h, sizeof h);
     size_t pos = sizeof h;
-    for (const auto& pc : ckpt_pieces(c)) {
-        HIP_TRY(c, hipMemcpyAsync(out + pos, c->ws + pc.first, pc.second, hipMemcpyDeviceToHost, c->stream));
-        pos += pc.second;
+    const auto pieces = ckpt_pieces(c);
+    for (const auto& pc : pieces) {
+        HIP_TRY(c, hipMemcpyAsync(out + pos, c->ws + pc.off, pc.bytes, hipMemcpyDeviceToHost, c->stream));
+        pos += pc.bytes;
     }
-    if (c->surr >= 0) {
-        const int64_t st = c->adam_steps;
-        memcpy(out + pos, &st, sizeof st);
+    rc = check_faults(c);   // waits for the copies
+    if (rc) return rc;
+    pos = sizeof h;
+    for (const auto& pc : pieces) {
+        if (pc.n_pad > pc.n) {
+            uint16_t* rows = reinterpret_cast<uint16_t*>(out + pos);
+            for (size_t r = 0; r < pc.bytes / 2 / (size_t)pc.n_pad; ++r)
+                std::fill(rows + r * pc.n_pad + pc.n, rows + (r + 1) * pc.n_pad, (uint16_t)0);
+        }
+        pos += pc.bytes;
     }
-    return check_faults(c);
+    return FFS_OK;
 }
 
 int ffs_checkpoint_load(ffs_ctx* c, const void* host, size_t bytes)
@@ -1690,13 +1834,10 @@ int ffs_checkpoint_load(ffs_ctx* c, const void* host, size_t bytes)
     const unsigned char* in = static_cast<const unsigned char*>(host);
     size_t pos = sizeof h;
     for (const auto& pc : ckpt_pieces(c)) {
-        HIP_TRY(c, hipMemcpyAsync(c->ws + pc.first, in + pos, pc.second, hipMemcpyHostToDevice, c->stream));
-        pos += pc.second;
+        HIP_TRY(c, hipMemcpyAsync(c->ws + pc.off, in + pos, pc.bytes, hipMemcpyHostToDevice, c->stream));
+        pos += pc.bytes;
     }
     if (c->surr >= 0) {
-        int64_t st;
-        memcpy(&st, in + pos, sizeof st);
-        c->adam_steps = st;
         hipLaunchKernelGGL(k_to_bf16, dim3((kParams + 255) / 256), dim3(256), 0, c->stream, at<const float>(c, c->o_w),
                            at<uint16_t>(c, c->o_wb), kParams);
         HIP_TRY(c, hipGetLastError());

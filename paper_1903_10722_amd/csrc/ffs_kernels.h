@@ -50,6 +50,8 @@ struct InstDesc {
     float* ring_T;               // [ring_size] (C - LB) / LB
     int LB, msum;
     int lane_wlds, lane_wlds_eval;   // lane mapping: LDS bytes per wave (generation, ffs_evaluate)
+    const void* pJ;              // pre-screen: job-major processing times, rows of pj_row_bytes
+    int pj_row_bytes;
     int mach[kMaxStages];
     int Pk[kMaxStages];          // sum over jobs of p[j][k]
 };
@@ -67,6 +69,7 @@ struct IslandDesc {
     int local;                   // island index inside its instance
     int cell_base;               // index of slot 0 among the instance's cellular cells
     int sel;                     // cellular parent selection variant (0, 1, 2)
+    int sweep;                   // cellular update: 0 synchronous, 1 line sweep
 };
 
 struct WorkItem {
@@ -411,8 +414,8 @@ __device__ __forceinline__ void build_ap(uint32_t* AP, const uint16_t* A, const 
 // the group owns the cyclic offsets [kC, kC + C) of P2 (C = ceil(n / S)):
 // it counts the genes it keeps, an exclusive scan over the group's lanes
 // gives its first destination, and a second pass writes them.  REG and MID
-// select which register-holding paths are compiled; without both only the
-// two-pass path remains (fewest registers).
+// select which register-holding paths are compiled (REG up to RMAX genes
+// per lane); without both only the two-pass path remains (fewest registers).
 __device__ __forceinline__ uint32_t wrap_sub(uint32_t x, uint32_t n)
 {
     const uint32_t y = x - n;   // x < 2n: x mod n
@@ -525,7 +528,7 @@ __device__ __forceinline__ void ox_mid(uint16_t* A, const uint16_t* B, uint16_t*
     wave_sync();
 }
 
-template <bool REG = true, bool MID = true>
+template <bool REG = true, bool MID = true, int RMAX = kOxReg>
 __device__ __forceinline__ void ox_group(uint16_t* A, const uint16_t* B, uint16_t* V, int n, int a, int b,
                                          bool doit, int k, int S, int g)
 {
@@ -536,11 +539,11 @@ __device__ __forceinline__ void ox_group(uint16_t* A, const uint16_t* B, uint16_
         ox_reg<8>(A, B, V, un, ua, ub, doit, k, S, o0, o1);
         return;
     }
-    if (REG && C <= 16) {
+    if (REG && RMAX >= 16 && C <= 16) {
         ox_reg<16>(A, B, V, un, ua, ub, doit, k, S, o0, o1);
         return;
     }
-    if (REG && C <= kOxReg) {
+    if (REG && RMAX >= kOxReg && C <= kOxReg) {
         ox_reg<kOxReg>(A, B, V, un, ua, ub, doit, k, S, o0, o1);
         return;
     }
@@ -627,14 +630,22 @@ struct CellMeta {
 // cuts and the swap mutation's flag and positions.
 struct CellPlan {
     int p1, p2;
+    bool n1, n2;      // line sweep: the parent's row is already the new generation's
     CellMeta meta;
 };
 
+// Parents and draws of cell `slot` at generation `gen` (Section 4.2).  With
+// sdiag >= 0 (the cell's anti-diagonal r + c in a line sweep) a neighbour on
+// a lower anti-diagonal precedes the cell in row-major order, the torus's
+// wrapped neighbours included, so its makespan and row are read from the
+// generation being built (buffer cur ^ 1); the others and the cell itself
+// from generation gen - 1.
 __device__ __forceinline__ CellPlan cell_plan(const InstDesc* I, const IslandDesc* L, int slot, uint32_t sub, int gen,
-                                              int cur)
+                                              int cur, int sdiag = -1)
 {
     const int n = I->n;
     const auto* mkp = as_global(L->mk[cur]);
+    const auto* mkn = as_global(L->mk[cur ^ 1]);
     const int rows = L->rows, cols = L->cols;
     const int r = slot / cols, c = slot - r * cols;
     const int nb0 = slot;
@@ -642,7 +653,11 @@ __device__ __forceinline__ CellPlan cell_plan(const InstDesc* I, const IslandDes
     const int nb2 = r * cols + ((c == cols - 1) ? 0 : c + 1);
     const int nb3 = ((r == rows - 1) ? 0 : r + 1) * cols + c;
     const int nb4 = r * cols + ((c == 0) ? cols - 1 : c - 1);
-    const int v0 = mkp[nb0], v1 = mkp[nb1], v2 = mkp[nb2], v3 = mkp[nb3], v4 = mkp[nb4];
+    const bool sw = sdiag >= 0;
+    const bool u1 = sw && r > 0, u2 = sw && c == cols - 1, u3 = sw && r == rows - 1, u4 = sw && c > 0;
+    const int v0 = mkp[nb0];
+    const int v1 = (u1 ? mkn : mkp)[nb1], v2 = (u2 ? mkn : mkp)[nb2];
+    const int v3 = (u3 ? mkn : mkp)[nb3], v4 = (u4 ? mkn : mkp)[nb4];
     const Block4 bk = stream_block(I->seed, (uint64_t)I->inst_id, (uint32_t)L->local, (uint32_t)slot, sub,
                                    (uint32_t)gen, kCell, 0);
     int bv, bs, sv, ss;
@@ -701,6 +716,8 @@ __device__ __forceinline__ CellPlan cell_plan(const InstDesc* I, const IslandDes
     CellPlan pl;
     pl.p1 = bs;
     pl.p2 = ss;
+    pl.n1 = (bs == nb1 && u1) || (bs == nb2 && u2) || (bs == nb3 && u3) || (bs == nb4 && u4);
+    pl.n2 = (ss == nb1 && u1) || (ss == nb2 && u2) || (ss == nb3 && u3) || (ss == nb4 && u4);
     pl.meta.mk1 = bv;
     pl.meta.mk2 = sv;
     pl.meta.cx = (uint64_t)draw32(bk, 0) < L->tc;
@@ -1017,6 +1034,7 @@ __global__ void __launch_bounds__(512) k_generation(const InstDesc* __restrict__
     const WorkItem wi = work[widx];
     const InstDesc* I = insts + wi.inst;
     const IslandDesc* L = isls + wi.island;
+    if (mode == 0 && L->sweep) return;   // line-sweep islands have launches of their own
     const int n = I->n, S = I->S, n_pad = I->n_pad, jb = I->jb, G = I->G;
 
     PT* pT = reinterpret_cast<PT*>(ffs_smem);
@@ -1230,18 +1248,23 @@ __global__ void __launch_bounds__(256) k_mlp_init(uint64_t seed, uint64_t inst, 
     v[i] = 0.f;
 }
 
-// Minibatch rows of training step `gen`: uniform over the filled part of the
-// replay ring, from the MLP_BATCH stream (draw r -> row r).
-__global__ void __launch_bounds__(256) k_batch_idx(uint64_t seed, uint64_t inst, int gen, int filled, int rows,
-                                                   int* __restrict__ idx)
+// Minibatch rows of the training step after the last completed generation
+// g: uniform over the filled part of the replay ring (min(g * cells, ring)
+// rows), from the MLP_BATCH stream of step g (draw r -> row r).  The
+// generation comes from the control block, so a captured graph replays it.
+__global__ void __launch_bounds__(256) k_batch_idx(uint64_t seed, uint64_t inst, const Control* __restrict__ ctl,
+                                                   int cells, int ring, int rows, int* __restrict__ idx)
 {
     const int blk = blockIdx.x * blockDim.x + threadIdx.x;
     if (blk * 8 >= rows) return;
+    const int gen = completed_gen(ctl);
+    const long long f = (long long)gen * cells;
+    const uint32_t filled = (uint32_t)(f < ring ? f : ring);
     const Block4 b = stream_block(seed, inst, 0, 0, 0, (uint32_t)gen, kMlpBatch, (uint32_t)blk);
 #pragma unroll
     for (int d = 0; d < 8; ++d) {
         const int r = blk * 8 + d;
-        if (r < rows) idx[r] = (int)below(draw32(b, d), (uint32_t)filled);
+        if (r < rows) idx[r] = (int)below(draw32(b, d), filled);
     }
 }
 

@@ -231,7 +231,10 @@ __device__ uint32_t lane_decode(const Src& src, const PT* pT, int pts, const int
 // ---- one generation (mode 0) or generation 0 (mode 1), lane mapping --------
 // Work item = up to 64 * waves chromosomes of one island; wave w takes 64 of
 // them.  Same generation bookkeeping, best-ever workgroup and XCD placement
-// as k_generation.
+// as k_generation.  Mode 0 leaves line-sweep islands alone; mode 2 runs the
+// cells of anti-diagonal `cnt_off` of line-sweep island work[blockIdx.y]
+// for the generation the last mode-0 launch counted (one launch per
+// anti-diagonal, in order, after that launch).
 template <int MMAX, typename PT>
 __global__ void __launch_bounds__(512) k_generation_lane(const InstDesc* __restrict__ insts,
                                                          const IslandDesc* __restrict__ isls,
@@ -239,6 +242,7 @@ __global__ void __launch_bounds__(512) k_generation_lane(const InstDesc* __restr
                                                          int mode, int cnt_off, int has_extra)
 {
     __shared__ int s_gen;
+    const bool sweep = mode == 2;
     if (threadIdx.x == 0) {
         int gg = 0;
         if (mode == 0) {
@@ -246,6 +250,8 @@ __global__ void __launch_bounds__(512) k_generation_lane(const InstDesc* __restr
             const int t = *cnt;
             *cnt = t + 1;
             gg = ctl->base + 1 + t;
+        } else if (sweep) {
+            gg = completed_gen(ctl);
         }
         s_gen = gg;
     }
@@ -256,8 +262,8 @@ __global__ void __launch_bounds__(512) k_generation_lane(const InstDesc* __restr
         return;
     }
     const int nw = (int)gridDim.x - has_extra;
-    int widx = (int)blockIdx.x;
-    if (nw <= 256) {
+    int widx = sweep ? (int)blockIdx.y : (int)blockIdx.x;
+    if (!sweep && nw <= 256) {
         const int per = (nw + 7) / 8, full = nw - 8 * (per - 1);
         const int xcd = widx & 7, rnk = widx >> 3;
         widx = (xcd < full) ? xcd * per + rnk : full * per + (xcd - full) * (per - 1) + rnk;
@@ -265,6 +271,16 @@ __global__ void __launch_bounds__(512) k_generation_lane(const InstDesc* __restr
     const WorkItem wi = work[widx];
     const InstDesc* I = insts + wi.inst;
     const IslandDesc* L = isls + wi.island;
+    if (mode == 0 && L->sweep) return;   // line-sweep islands have launches of their own
+    // line sweep: the cells of anti-diagonal diag, rows rlo .. rlo + dcount - 1
+    const int diag = sweep ? cnt_off : -1;
+    int rlo = 0, dcount = 0;
+    if (sweep) {
+        rlo = diag - (L->cols - 1) > 0 ? diag - (L->cols - 1) : 0;
+        const int rhi = diag < L->rows - 1 ? diag : L->rows - 1;
+        dcount = rhi - rlo + 1;
+        if (dcount <= 0) return;
+    }
     const int n = I->n, S = I->S, n_pad = I->n_pad, jb = I->jb;
 
     PT* pT = reinterpret_cast<PT*>(ffs_smem);
@@ -275,9 +291,13 @@ __global__ void __launch_bounds__(512) k_generation_lane(const InstDesc* __restr
 
     const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
     unsigned char* wbase = ffs_smem + pt_lds_bytes<PT>(S, n_pad) + (size_t)wave * I->lane_wlds;
-    const int w0 = wave * kWave;
-    const int wcount = wi.count - w0 < 0 ? 0 : (wi.count - w0 > kWave ? kWave : wi.count - w0);
-    const int sbase = wi.slot0 + w0;
+    // chromosome i of this wave sits in slot slot_of(sbase + i)
+    const int w0 = wave * kWave + (sweep ? (int)blockIdx.x * (int)blockDim.x : 0);
+    const int total = sweep ? dcount : wi.count;
+    const int wcount = total - w0 < 0 ? 0 : (total - w0 > kWave ? kWave : total - w0);
+    const int sbase = sweep ? w0 : wi.slot0 + w0;
+    const int lcols = L->cols;
+    auto slot_of = [&](int i) { return sweep ? (rlo + i) * lcols + (diag - rlo - i) : i; };
 
     // children, one at a time on all 64 lanes, into the next generation's
     // rows.  Lane c first takes the parents and draws of child c (one Philox
@@ -289,17 +309,18 @@ __global__ void __launch_bounds__(512) k_generation_lane(const InstDesc* __restr
         uint16_t* V = B + n_pad;
         if (mode == 1) {
             for (int c = 0; c < wcount; ++c) {
-                make_child<true>(I, L, sbase + c, 0u, gen, cur, 1, A, B, V, lane, kWave, 0, true);
-                row_l2g(L->genes[nxt] + (size_t)(sbase + c) * n_pad, A, n_pad, lane, kWave);
+                make_child<true>(I, L, slot_of(sbase + c), 0u, gen, cur, 1, A, B, V, lane, kWave, 0, true);
+                row_l2g(L->genes[nxt] + (size_t)slot_of(sbase + c) * n_pad, A, n_pad, lane, kWave);
                 wave_sync();
             }
         } else if (wcount > 0) {
             const bool cell = L->kind == 0;
-            const int pslot = sbase + (lane < wcount ? lane : 0);
+            const int pslot = slot_of(sbase + (lane < wcount ? lane : 0));
             uint32_t w_src, w_cut, w_mut;
             if (cell) {
-                const CellPlan pl = cell_plan(I, L, pslot, 0u, gen, cur);
-                w_src = (uint32_t)pl.p1 | ((uint32_t)pl.p2 << 16);
+                // slots < 2^14; bits 15 and 31: that parent's row is the new generation's
+                const CellPlan pl = cell_plan(I, L, pslot, 0u, gen, cur, diag);
+                w_src = (uint32_t)pl.p1 | ((uint32_t)pl.p2 << 16) | (pl.n1 ? 1u << 15 : 0u) | (pl.n2 ? 1u << 31 : 0u);
                 w_cut = (uint32_t)pl.meta.a | ((uint32_t)pl.meta.b << 12) | (pl.meta.cx ? 1u << 24 : 0u) |
                         (pl.meta.mx ? 1u << 25 : 0u);
                 w_mut = (uint32_t)pl.meta.mi | ((uint32_t)pl.meta.mj << 12);
@@ -313,17 +334,20 @@ __global__ void __launch_bounds__(512) k_generation_lane(const InstDesc* __restr
             constexpr int PV = 2;                         // vectors per lane per row held in registers
             const bool pre = nv <= PV * kWave;            // rows of up to 1024 genes
             const auto* g4 = as_global(reinterpret_cast<const u32x4*>(L->genes[cur]));
+            const auto* g4n = as_global(reinterpret_cast<const u32x4*>(L->genes[nxt]));
             u32x4 ra[PV], rb[PV];
             auto fetch = [&](int c) {
                 const uint32_t src = (uint32_t)__builtin_amdgcn_readlane((int)w_src, c);
-                const size_t r1 = (size_t)(cell ? (src & 0xFFFFu) : (src & 0x7FFFFFFFu)) * nv;
-                const size_t r2 = (size_t)(src >> 16) * nv;
+                const size_t r1 = (size_t)(cell ? (src & 0x7FFFu) : (src & 0x7FFFFFFFu)) * nv;
+                const size_t r2 = (size_t)((src >> 16) & 0x7FFFu) * nv;
+                const auto* s1 = (cell && (src & 0x8000u)) ? g4n : g4;
+                const auto* s2 = (cell && (src >> 31)) ? g4n : g4;
 #pragma unroll
                 for (int v = 0; v < PV; ++v) {
                     const int x = lane + v * kWave;
                     if (x < nv) {
-                        ra[v] = g4[r1 + x];
-                        if (cell) rb[v] = g4[r2 + x];
+                        ra[v] = s1[r1 + x];
+                        if (cell) rb[v] = s2[r2 + x];
                     }
                 }
             };
@@ -332,7 +356,7 @@ __global__ void __launch_bounds__(512) k_generation_lane(const InstDesc* __restr
                 const uint32_t src = (uint32_t)__builtin_amdgcn_readlane((int)w_src, c);
                 const uint32_t cut = (uint32_t)__builtin_amdgcn_readlane((int)w_cut, c);
                 const uint32_t mut = (uint32_t)__builtin_amdgcn_readlane((int)w_mut, c);
-                const int slot = sbase + c;
+                const int slot = slot_of(sbase + c);
                 if (pre) {
                     u32x4* da = reinterpret_cast<u32x4*>(cell ? A : V);
                     u32x4* db = reinterpret_cast<u32x4*>(B);
@@ -345,8 +369,9 @@ __global__ void __launch_bounds__(512) k_generation_lane(const InstDesc* __restr
                         }
                     }
                 } else if (cell) {
-                    rows_g2l(A, L->genes[cur] + (size_t)(src & 0xFFFFu) * n_pad, B,
-                             L->genes[cur] + (size_t)(src >> 16) * n_pad, n_pad, lane, kWave);
+                    rows_g2l(A, L->genes[(src & 0x8000u) ? nxt : cur] + (size_t)(src & 0x7FFFu) * n_pad, B,
+                             L->genes[(src >> 31) ? nxt : cur] + (size_t)((src >> 16) & 0x7FFFu) * n_pad, n_pad,
+                             lane, kWave);
                 } else {
                     row_g2l(V, L->genes[cur] + (size_t)(src & 0x7FFFFFFFu) * n_pad, n_pad, lane, kWave);
                 }
@@ -367,7 +392,7 @@ __global__ void __launch_bounds__(512) k_generation_lane(const InstDesc* __restr
     __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
 
     const bool active = lane < wcount;
-    const int slot = sbase + (active ? lane : 0);
+    const int slot = slot_of(sbase + (active ? lane : 0));
     unsigned long long wkey = ~0ull;
     if (wcount > 0) {
         const GenesU16 src{L->genes[nxt] + (size_t)slot * n_pad};
@@ -376,7 +401,7 @@ __global__ void __launch_bounds__(512) k_generation_lane(const InstDesc* __restr
         bool keep_old = false;
         if (active) {
             int mk_new = (int)cm;
-            if (mode == 0 && L->kind == 0) {
+            if (mode != 1 && L->kind == 0) {
                 const int mk_old = as_global(L->mk[cur])[slot];
                 keep_old = !((int)cm < mk_old);
                 mk_new = keep_old ? mk_old : (int)cm;
@@ -397,7 +422,7 @@ __global__ void __launch_bounds__(512) k_generation_lane(const InstDesc* __restr
             for (int t = 0; t < 4; ++t) {
                 rows[t] = -1;
                 if (km) {
-                    rows[t] = sbase + (int)__builtin_ctzll(km);
+                    rows[t] = slot_of(sbase + (int)__builtin_ctzll(km));
                     km &= km - 1ull;
                     ++cnt;
                 }
@@ -472,6 +497,218 @@ __global__ void __launch_bounds__(512) k_evaluate_lane(const InstDesc* __restric
     const uint32_t cm = lane_decode<MMAX, PT>(src, pT, pt_stride<PT>(n_pad), I->mach, S, n, jb, wbase, lane);
     if (active) out[idx] = bad ? -1 : (int)cm;
     if (active && bad) atomicOr(&ctl->err, 1);
+}
+
+}  // namespace flowshop
+
+namespace flowshop {
+
+// ---- candidates of the learned pre-screen, one wave per cell ----------------
+// Features of the chromosome in A (n genes) as features_group computes them,
+// from the job-major table pJ (row of job j at pJ + j * rsb bytes, the
+// stages' processing times, zero past S): lane l sums the positions
+// [l C, l C + C) (C = ceil(n / 64)) stage by stage in registers and adds each
+// bucket's partial sums into acc[b * S + k] in LDS (integer sums: the order
+// does not matter), then the 256 entries are written to out.
+template <int SM, typename PT>
+__device__ __forceinline__ void cand_features(const uint16_t* A, const unsigned char* pJ, int rsb, const InstDesc* I,
+                                              const CellMeta& cm, uint32_t* acc, int lane, uint16_t* out)
+{
+    const int n = I->n, S = I->S, B = 240 / S;
+    for (int e = lane; e < B * S; e += kWave) acc[e] = 0u;
+    wave_sync();
+    const int C = (n + kWave - 1) / kWave;
+    const int t0 = lane * C < n ? lane * C : n, t1 = t0 + C < n ? t0 + C : n;
+    // per-lane sums over at most 64 positions; with one-byte processing
+    // times (<= 255) they fit in 16 bits, so stages 4d + {0, 2} and
+    // 4d + {1, 3} share a register and are added pairwise (integer packed adds)
+    constexpr bool PK = sizeof(PT) == 1;
+    constexpr int NR = PK ? (SM + 1) / 2 : SM;   // accumulator registers
+    uint32_t s[NR];
+#pragma unroll
+    for (int k = 0; k < NR; ++k) s[k] = 0u;
+    int cb = (int)(((long long)t0 * B) / n);
+    int next = (int)(((long long)(cb + 1) * n + B - 1) / B);   // first position of bucket cb + 1
+    auto flush = [&]() {
+#pragma unroll
+        for (int k = 0; k < SM; ++k)
+            if (k < S) {
+                // stage k sits in register 2 (k / 4) + (k & 1), half (k >> 1) & 1
+                const uint32_t v = PK ? (s[2 * (k >> 2) + (k & 1)] >> (16 * ((k >> 1) & 1))) & 0xFFFFu : s[k];
+                if (v) atomicAdd(&acc[cb * S + k], v);
+            }
+#pragma unroll
+        for (int k = 0; k < NR; ++k) s[k] = 0u;
+    };
+    for (int t = t0; t < t1; ++t) {
+        if (t >= next) {
+            flush();
+            cb += 1;
+            next = (int)(((long long)(cb + 1) * n + B - 1) / B);
+        }
+        const PT* row = reinterpret_cast<const PT*>(pJ + (size_t)A[t] * rsb);
+        constexpr int PV = 16 / (int)sizeof(PT);   // processing times per 16-byte read
+        constexpr int NB = (SM + PV - 1) / PV;     // 16-byte reads per row
+#pragma unroll
+        for (int v = 0; v < NB; ++v) {
+            const uint4 w = reinterpret_cast<const uint4*>(row)[v];
+            const uint32_t ww[4] = {w.x, w.y, w.z, w.w};
+            if (PK) {
+                typedef uint16_t u16x2 __attribute__((ext_vector_type(2)));
+#pragma unroll
+                for (int d = 0; d < 4; ++d) {
+                    const int r = 2 * (v * 4 + d);   // registers of stages 4 (4v + d) + {0, 2} and + {1, 3}
+                    if (r < NR) {
+                        const u16x2 lo = __builtin_bit_cast(u16x2, ww[d] & 0x00FF00FFu);
+                        const u16x2 hi = __builtin_bit_cast(u16x2, (ww[d] >> 8) & 0x00FF00FFu);
+                        s[r] = __builtin_bit_cast(uint32_t, __builtin_bit_cast(u16x2, s[r]) + lo);
+                        s[r + 1] = __builtin_bit_cast(uint32_t, __builtin_bit_cast(u16x2, s[r + 1]) + hi);
+                    }
+                }
+            } else {
+#pragma unroll
+                for (int q = 0; q < PV; ++q)
+                    if (v * PV + q < SM) s[v * PV + q] += (ww[q >> 1] >> (16 * (q & 1))) & 0xFFFFu;
+            }
+        }
+    }
+    if (t0 < t1) flush();
+    wave_sync();
+    const float fn = (float)n, fLB = (float)I->LB;
+    for (int e = lane; e < kFeat; e += kWave) {
+        float v = 0.f;
+        if (e < B * S) {
+            const int k = e - (e / S) * S;
+            v = __fdiv_rn((float)((uint64_t)acc[e] * (uint64_t)B), (float)I->Pk[k]);
+        } else {
+            switch (e - 240) {
+                case 0: v = __fdiv_rn((float)cm.mk1, fLB); break;
+                case 1: v = __fdiv_rn((float)cm.mk2, fLB); break;
+                case 2: v = __fdiv_rn((float)cm.a, fn); break;
+                case 3: v = __fdiv_rn((float)cm.b, fn); break;
+                case 4: v = cm.cx ? 1.f : 0.f; break;
+                case 5: v = cm.mx ? 1.f : 0.f; break;
+                case 6: v = __fdiv_rn((float)cm.mi, fn); break;
+                case 7: v = __fdiv_rn((float)cm.mj, fn); break;
+                case 8: v = __fdiv_rn(fLB, (float)I->E); break;
+                case 9: v = __fdiv_rn(fn, 1000.f); break;
+                case 10: v = __fdiv_rn((float)S, 20.f); break;
+                case 11: v = __fdiv_rn((float)I->msum, (float)(6 * S)); break;
+                default: break;
+            }
+        }
+        out[e] = f32_to_bf16(v);
+    }
+}
+
+// One wave per cell of the pre-screened instance's cellular islands: lane c
+// (< K) takes the parents and draws of candidate c (candidate stream c of
+// the CELL purpose, generation completed + 1); the wave then builds each
+// candidate on all 64 lanes (order crossover, swap mutation) and writes its
+// features to Xout[(cell * K + c) * 256].  LDS: the job-major table (rows of
+// rsb bytes), then per wave three rows and B * S bucket sums.
+template <int SM, typename PT>
+__global__ void __launch_bounds__(1024) k_cand_features(const InstDesc* __restrict__ insts,
+                                                       const IslandDesc* __restrict__ isls, int inst,
+                                                       const Control* ctl, int cells, uint16_t* __restrict__ Xout)
+{
+    const InstDesc* I = insts + inst;
+    const int n = I->n, S = I->S, n_pad = I->n_pad, K = I->surr_k;
+    const int rsb = I->pj_row_bytes;
+    const int done = completed_gen(ctl);
+    const int gen = done + 1, cur = done & 1;
+    unsigned char* pJ = ffs_smem;
+    {
+        const size_t words = (size_t)n * rsb / 16;
+        const auto* s4 = as_global(reinterpret_cast<const u32x4*>(I->pJ));
+        u32x4* d4 = reinterpret_cast<u32x4*>(pJ);
+        for (size_t v = threadIdx.x; v < words; v += blockDim.x) d4[v] = s4[v];
+    }
+    __syncthreads();
+    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    const int cell = blockIdx.x * (blockDim.x >> 6) + wave;
+    if (cell >= cells) return;
+    uint16_t* A = reinterpret_cast<uint16_t*>(pJ + align16((size_t)n * rsb) +
+                                              (size_t)wave * (group_stride(n_pad) * 2 + 240 * 4));
+    uint16_t* B = A + n_pad;
+    uint16_t* V = B + n_pad;
+    uint32_t* acc = reinterpret_cast<uint32_t*>(A + group_stride(n_pad));
+    // the cellular island holding this cell
+    const IslandDesc* L = isls + I->island0;
+    int slot = 0;
+    for (int x = 0; x < I->n_islands; ++x) {
+        const IslandDesc* X = isls + I->island0 + x;
+        if (X->kind == 0 && cell >= X->cell_base && cell < X->cell_base + X->size) {
+            L = X;
+            slot = cell - X->cell_base;
+        }
+    }
+    const CellPlan pl = cell_plan(I, L, slot, (uint32_t)(lane < K ? lane : 0), gen, cur);
+    const uint32_t w_src = (uint32_t)pl.p1 | ((uint32_t)pl.p2 << 16);
+    const uint32_t w_cut = (uint32_t)pl.meta.a | ((uint32_t)pl.meta.b << 12) | (pl.meta.cx ? 1u << 24 : 0u) |
+                           (pl.meta.mx ? 1u << 25 : 0u);
+    const uint32_t w_mut = (uint32_t)pl.meta.mi | ((uint32_t)pl.meta.mj << 12);
+    const uint16_t* gp = L->genes[cur];
+    // the parents' rows of the next candidate are read into registers while
+    // the current one is built (rows of up to 1024 genes)
+    const int nv = n_pad >> 3;
+    constexpr int PV2 = 2;
+    const bool pre = nv <= PV2 * kWave;
+    const auto* g4 = as_global(reinterpret_cast<const u32x4*>(gp));
+    u32x4 ra[PV2], rb[PV2];
+    auto fetch = [&](int c) {
+        const uint32_t src = (uint32_t)__builtin_amdgcn_readlane((int)w_src, c);
+#pragma unroll
+        for (int v = 0; v < PV2; ++v) {
+            const int x = lane + v * kWave;
+            if (x < nv) {
+                ra[v] = g4[(size_t)(src & 0xFFFFu) * nv + x];
+                rb[v] = g4[(size_t)(src >> 16) * nv + x];
+            }
+        }
+    };
+    if (pre) fetch(0);
+    for (int c = 0; c < K; ++c) {
+        const uint32_t src = (uint32_t)__builtin_amdgcn_readlane((int)w_src, c);
+        const uint32_t cut = (uint32_t)__builtin_amdgcn_readlane((int)w_cut, c);
+        const uint32_t mut = (uint32_t)__builtin_amdgcn_readlane((int)w_mut, c);
+        CellMeta cm;
+        cm.mk1 = __builtin_amdgcn_readlane(pl.meta.mk1, c);
+        cm.mk2 = __builtin_amdgcn_readlane(pl.meta.mk2, c);
+        cm.a = (int)(cut & 0xFFFu);
+        cm.b = (int)((cut >> 12) & 0xFFFu);
+        cm.cx = ((cut >> 24) & 1u) != 0u;
+        cm.mx = ((cut >> 25) & 1u) != 0u;
+        cm.mi = (int)(mut & 0xFFFu);
+        cm.mj = (int)(mut >> 12);
+        if (pre) {
+            u32x4* da = reinterpret_cast<u32x4*>(A);
+            u32x4* db = reinterpret_cast<u32x4*>(B);
+#pragma unroll
+            for (int v = 0; v < PV2; ++v) {
+                const int x = lane + v * kWave;
+                if (x < nv) {
+                    da[x] = ra[v];
+                    db[x] = rb[v];
+                }
+            }
+        } else {
+            rows_g2l(A, gp + (size_t)(src & 0xFFFFu) * n_pad, B, gp + (size_t)(src >> 16) * n_pad, n_pad, lane,
+                     kWave);
+        }
+        wave_sync();
+        if (pre && c + 1 < K) fetch(c + 1);
+        ox_group<true, false, 16>(A, B, V, n, cm.a, cm.b, cm.cx, lane, kWave, 0);
+        swap_genes(A, cm.mx && lane == 0, cm.mi, cm.mj);
+        cand_features<SM, PT>(A, pJ, rsb, I, cm, acc, lane, Xout + ((size_t)cell * K + c) * kFeat);
+        wave_sync();
+    }
+}
+
+// LDS bytes of a k_cand_features workgroup of `waves` waves.
+__host__ __device__ inline size_t cand_lds_bytes(int n, int n_pad, int rsb, int waves)
+{
+    return align16((size_t)n * rsb) + (size_t)waves * ((size_t)group_stride(n_pad) * 2 + 240 * 4);
 }
 
 }  // namespace flowshop

@@ -190,37 +190,94 @@ __global__ void __launch_bounds__(256) k_mlp_dz2(const float* __restrict__ y, co
     dZ2[e] = (bf16_to_f32(H2[e]) > 0.f) ? f32_to_bf16(d * bf16_to_f32(w3[j])) : (uint16_t)0;
 }
 
-// Column sums over rows in two fixed-order stages (deterministic): block
-// (x, z) sums rows [z * rows / gridDim.z, (z+1) * rows / gridDim.z) of 256
-// columns into part[z][j]; k_sum_splits adds the slices.  part[z][j] =
-// sum_i X[i][j] (BF16 X), or sum_i X[i][j] * dy[i] when dy != nullptr; with
-// dsum != nullptr the thread of column 0 also writes dsum[z] = sum_i dy[i].
-__global__ void __launch_bounds__(256) k_colsum(const uint16_t* __restrict__ X, const float* __restrict__ dy,
-                                                int rows, int cols, float* __restrict__ part,
-                                                float* __restrict__ dsum)
+// Column sums of three BF16 matrices [rows][512] in one launch, in two
+// fixed-order stages (deterministic).  Block (0, y, m) sums rows
+// [64 y, 64 y + 64) of matrix m: thread (r, g) adds rows 64 y + 16 r .. + 15
+// for columns 8 g .. 8 g + 7 (16-byte reads), the four row groups are added
+// in order through LDS, and part[y][m * 512 + j] receives the chunk's sum.
+// Matrix 0 is weighted by dy[i]; block y of matrix 0 also writes
+// dpart[y] = sum of dy over its rows.  k_colsum3_sum adds the chunks.
+struct Colsum3 {
+    const uint16_t* X[3];
+    float* out[3];
+};
+
+__global__ void __launch_bounds__(256) k_colsum3(Colsum3 a, const float* __restrict__ dy, float* __restrict__ part,
+                                                 float* __restrict__ dpart)
 {
-    const int j = blockIdx.x * blockDim.x + threadIdx.x;
-    if (j >= cols) return;
-    const int per = rows / gridDim.y;
-    const int r0 = blockIdx.y * per, r1 = r0 + per;
-    float s = 0.f, sd = 0.f;
-#pragma unroll 8
-    for (int i = r0; i < r1; ++i) {
-        const float x = bf16_to_f32(X[(size_t)i * cols + j]);
-        s += dy ? x * dy[i] : x;
-        if (dsum && j == 0) sd += dy[i];
+    __shared__ float red[4][kHidden];
+    const int m = blockIdx.z, y = blockIdx.y;
+    const int r = threadIdx.x >> 6, g = threadIdx.x & 63;
+    const uint16_t* X = a.X[m];
+    float acc[8];
+#pragma unroll
+    for (int t = 0; t < 8; ++t) acc[t] = 0.f;
+    const int i0 = y * 64 + r * 16;
+    uint4 v[16];
+#pragma unroll
+    for (int u = 0; u < 16; ++u) v[u] = *reinterpret_cast<const uint4*>(&X[(size_t)(i0 + u) * kHidden + 8 * g]);
+#pragma unroll
+    for (int u = 0; u < 16; ++u) {
+        const uint16_t* e = reinterpret_cast<const uint16_t*>(&v[u]);
+        const float w = (m == 0) ? dy[i0 + u] : 1.f;
+#pragma unroll
+        for (int t = 0; t < 8; ++t) acc[t] += (m == 0) ? bf16_to_f32(e[t]) * w : bf16_to_f32(e[t]);
     }
-    part[(size_t)blockIdx.y * cols + j] = s;
-    if (dsum && j == 0) dsum[blockIdx.y] = sd;
+#pragma unroll
+    for (int t = 0; t < 8; ++t) red[r][8 * g + t] = acc[t];
+    __syncthreads();
+    for (int j = threadIdx.x; j < kHidden; j += 256)
+        part[(size_t)y * 3 * kHidden + m * kHidden + j] = ((red[0][j] + red[1][j]) + red[2][j]) + red[3][j];
+    if (m == 0 && threadIdx.x == 0) {
+        float sd = 0.f;
+        for (int u = 0; u < 64; ++u) sd += dy[y * 64 + u];
+        dpart[y] = sd;
+    }
+}
+
+// out_m[j] = sum over chunks y (in order) of part[y][m * 512 + j]; dsum =
+// sum of dpart in order.
+__global__ void __launch_bounds__(256) k_colsum3_sum(Colsum3 a, const float* __restrict__ part, int chunks,
+                                                     const float* __restrict__ dpart, float* __restrict__ dsum)
+{
+    const int e = blockIdx.x * blockDim.x + threadIdx.x;
+    if (e < 3 * kHidden) {
+        float s = 0.f;
+        for (int y = 0; y < chunks; ++y) s += part[(size_t)y * 3 * kHidden + e];
+        a.out[e / kHidden][e % kHidden] = s;
+    }
+    if (e == 3 * kHidden) {
+        float s = 0.f;
+        for (int y = 0; y < chunks; ++y) s += dpart[y];
+        *dsum = s;
+    }
 }
 
 // Adam (Kingma & Ba) on FP32 master weights; writes the BF16 copy when given.
+// Advances the Adam step count kept in device memory and looks up that
+// step's bias corrections 1 - beta^t (computed on the host in FP64 and
+// rounded to FP32; table[t - 1] for t <= steps, both exactly 1 beyond).
+// Run by one thread before k_adam, so a captured graph can replay training
+// steps without the host knowing their number.
+__global__ void k_adam_prep(long long* __restrict__ step, const float2* __restrict__ table, int steps,
+                            float* __restrict__ bc)
+{
+    if (threadIdx.x != 0 || blockIdx.x != 0) return;
+    const long long t = *step + 1;
+    *step = t;
+    const float2 b = (t <= steps) ? table[t - 1] : make_float2(1.f, 1.f);
+    bc[0] = b.x;
+    bc[1] = b.y;
+}
+
 __global__ void __launch_bounds__(256) k_adam(float* __restrict__ w, float* __restrict__ m, float* __restrict__ v,
                                               const float* __restrict__ g, uint16_t* __restrict__ wb, int count,
-                                              float lr, float beta1, float beta2, float eps, float bc1, float bc2)
+                                              float lr, float beta1, float beta2, float eps,
+                                              const float* __restrict__ bc)
 {
     const int i = blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= count) return;
+    const float bc1 = bc[0], bc2 = bc[1];
     const float gi = g[i];
     const float mi = beta1 * m[i] + (1.f - beta1) * gi;
     const float vi = beta2 * v[i] + (1.f - beta2) * gi * gi;

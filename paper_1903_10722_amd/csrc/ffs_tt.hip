@@ -1127,6 +1127,7 @@ int ffs_tt_add_island(ffs_tt_ctx* c, const ffs_island_spec* s)
     if ((int)c->isl.size() >= kMaxIsl) return fail(c, FFS_EUNSUPPORTED, "more than %d islands", kMaxIsl);
     if (s->kind != 0 && s->kind != 1) return fail(c, FFS_EINVAL, "kind %d", s->kind);
     if (s->selection != 0) return fail(c, FFS_EINVAL, "selection must be 0");
+    if (s->sweep != 0) return fail(c, FFS_EINVAL, "sweep must be 0 (the update schedule is set per context)");
     if (!(s->p_c >= 0.0 && s->p_c <= 1.0 && s->p_m >= 0.0 && s->p_m <= 1.0)) return fail(c, FFS_EINVAL, "rates outside [0, 1]");
     const int size = (s->kind == 0) ? s->rows * s->cols : s->size;
     if (s->kind == 0 && (s->rows < 3 || s->cols < 3)) return fail(c, FFS_EINVAL, "cellular grid below 3x3");

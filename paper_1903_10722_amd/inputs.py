@@ -40,11 +40,11 @@ def random_perms(count: int, n: int, seed: int = 0) -> np.ndarray:
     return np.argsort(keys, axis=1).astype(np.int32)
 
 
-def cellular(rows: int, cols: int, pc: float, pm: float, sel: int = 0) -> dict:
+def cellular(rows: int, cols: int, pc: float, pm: float, sel: int = 0, sweep: int = 0) -> dict:
     """A rows x cols cellular island; `sel` is the parent selection variant
     (0 two best of the neighbourhood, 1 self + best neighbour, 2 binary
-    tournaments)."""
-    return dict(kind=0, rows=rows, cols=cols, size=rows * cols, pc=pc, pm=pm, sel=sel)
+    tournaments), `sweep` the update schedule (0 synchronous, 1 line sweep)."""
+    return dict(kind=0, rows=rows, cols=cols, size=rows * cols, pc=pc, pm=pm, sel=sel, sweep=sweep)
 
 
 def pseudo(size: int, pc: float, pm: float) -> dict:

@@ -306,3 +306,61 @@ def test_surrogate_workload_size_features_and_replay():
             assert t[cell] == sg.target(oracle.decode(w["m"], w["p"], child), LB)
         say(f"[surrogate] workload size: generation {g} replayed")
     ctx.close()
+
+
+@pytest.mark.parametrize("shape", [(60, 10, 99, 0), (1000, 20, 99, 0), (37, 3, 99, 0), (90, 7, 3000, 0),
+                                   (200, 30, 99, 2)],
+                         ids=["n60_S10", "n1000_S20", "n37_S3", "wide_p", "S30_tournaments"])
+def test_one_wave_per_cell_candidate_features(shape):
+    """Scoring builds the candidates one wave per cell and sums the features
+    from a job-major table; every candidate's features equal the oracle's
+    (and those of the per-stage candidate kernel that also decodes them)."""
+    ensure_built()
+    n, S, p_hi, sel = shape
+    m, p = inputs.make_instance(n, S, 2, 6, p_hi=p_hi, seed=n + S)
+    isl = [dict(inputs.cellular(8, 8, 0.9, 0.1), sel=sel), inputs.pseudo(64, 0.75, 0.0)]
+    w = dict(m=m, p=p, islands=isl, interval=10)
+    say(f"[surrogate] one wave per cell: n={n} S={S} p<={p_hi} selection={sel}")
+    ctx = _ctx(w)
+    ga = oracle.GA(w["m"], w["p"], w["islands"], interval=w["interval"], seed=11)
+    fast = ctx.surrogate_candidates(exact=False, features=True)
+    slow = ctx.surrogate_candidates(exact=True, features=True)
+    assert np.array_equal(fast["features"], slow["features"])
+    genes0, mk0 = ga.population(0)
+    for cell in range(0, 64, 7):
+        for c in range(8):
+            child, meta = ga.cell_candidate(0, cell, c)
+            f = sg.features(w["m"], w["p"], child, int(mk0[meta[0]]), int(mk0[meta[1]]), meta)
+            assert np.array_equal(fast["features"][cell, c], f), (cell, c)
+    ctx.close()
+
+
+def test_captured_epochs_match_eager_generations():
+    """Past the warm-up, whole migration epochs with the pre-screen replay one
+    captured graph (batch rows and Adam bias corrections read on the device).
+    Each replay, with eager reads and synchronisations in between, leaves the
+    same state as generation-by-generation eager launches: populations,
+    network parameters, Adam moments and step count, replay ring, choices."""
+    ensure_built()
+    w = _small(seed=6)
+    say("[surrogate] captured epochs against eager generations")
+    eager = _ctx(w, warmup=3, seed=21)
+    eager.set_graphs(False)
+    graph = _ctx(w, warmup=3, seed=21)
+    graph.evolve(10)             # warm-up and the first epoch run eagerly
+    for _ in range(10):
+        eager.evolve(1)
+    for epoch in range(4):
+        graph.evolve(10)
+        for _ in range(10):
+            eager.evolve(1)
+        gen = 20 + 10 * epoch
+        for isl in range(2):
+            ge, me = eager.population(0, isl)
+            gg, mg = graph.population(0, isl)
+            assert np.array_equal(ge, gg) and np.array_equal(me, mg), (gen, isl)
+        assert np.array_equal(eager.surrogate_choices(), graph.surrogate_choices()), gen
+        assert np.array_equal(eager.surrogate_params(), graph.surrogate_params()), gen
+        assert eager.checkpoint() == graph.checkpoint(), gen
+    eager.close()
+    graph.close()
