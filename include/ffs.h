@@ -151,7 +151,7 @@ int ffs_set_waves_per_block(ffs_ctx *ctx, int32_t waves);
  *   1: per lane -- one lane decodes one chromosome through all stages;
  *  -1: automatic (the default): per lane when every instance fits it and the
  *      context holds at least 131072 individuals (ffs_evaluate: at least
- *      65536 rows), per stage otherwise.
+ *      65536 rows of at least 8 stages), per stage otherwise.
  * The per-lane mapping needs at most 8 machines per stage, a sum of machine
  * counts <= 160 and no pre-screen; otherwise per stage is used whatever the
  * request.  Results never depend on the mapping.  May be called before or

@@ -105,7 +105,7 @@ void* pick_cand_features(int sm, int ptb)
 #define FFS_CASE(SM)                                                                             \
     if (sm == SM) return ptb == 1 ? reinterpret_cast<void*>(&k_cand_features<SM, uint8_t>)      \
                                   : reinterpret_cast<void*>(&k_cand_features<SM, uint16_t>);
-    FFS_CASE(8) FFS_CASE(16) FFS_CASE(24) FFS_CASE(32)
+    FFS_CASE(8) FFS_CASE(16) FFS_CASE(20) FFS_CASE(24) FFS_CASE(32)
 #undef FFS_CASE
     return nullptr;
 }
@@ -151,7 +151,11 @@ void* pick_eval_lane(int mm, int ptb)
 // SIMDs idle (one wave per 64 individuals), and the per-stage lane mapping
 // of k_generation is chosen when the mapping is automatic.
 constexpr long long kLaneAutoMin = 131072;
+// ffs_evaluate takes the lane mapping from this many rows of at least this
+// many stages (a million random rows: 1.45x and 1.65x faster at 10 and 20
+// stages, 2.3x slower at 5, where the per-stage groups fill the wave too)
 constexpr int kLaneEvalAutoMin = 65536;
+constexpr int kLaneEvalMinStages = 8;
 
 int round_mmax(int m)
 {
@@ -477,7 +481,7 @@ void layout(ffs_ctx* c)
         c->o_adam = take(16);
         c->o_bc = take((size_t)kBcSteps * 8);
         // job-major processing times for the candidates' features
-        c->cand_sm = I.S <= 8 ? 8 : (I.S <= 16 ? 16 : (I.S <= 24 ? 24 : (I.S <= 32 ? 32 : 0)));
+        c->cand_sm = I.S <= 8 ? 8 : (I.S <= 16 ? 16 : (I.S <= 20 ? 20 : (I.S <= 24 ? 24 : (I.S <= 32 ? 32 : 0))));
         c->cand_rsb = (c->cand_sm * c->ptb + 15) / 16 * 16;
         c->o_pJ = take((size_t)I.n * std::max(c->cand_rsb, 16));
     }
@@ -843,7 +847,8 @@ int launch_eval(ffs_ctx* c, int inst, const int32_t* perms, int count, int32_t* 
     const InstDesc* di = reinterpret_cast<const InstDesc*>(c->ws + c->off_insts) + inst;
     Control* ctl = reinterpret_cast<Control*>(c->ws + c->off_ctl);
     void* kl = I.lane_ok ? pick_eval_lane(c->mm, c->ptb) : nullptr;
-    const bool lane = kl && (c->mapping == 1 || (c->mapping < 0 && count >= kLaneEvalAutoMin));
+    const bool lane = kl && (c->mapping == 1 || (c->mapping < 0 && count >= kLaneEvalAutoMin &&
+                                                 I.S >= kLaneEvalMinStages));
     const int per_block = c->wpb * (lane ? kWave : I.G);
     const int blocks = (count + per_block - 1) / per_block;
     const size_t lds = align16((size_t)I.S * ((size_t)I.n_pad * c->ptb + 4)) +
@@ -1927,7 +1932,7 @@ int ffs_evaluate_noalloc(void* hip_stream, int32_t n, int32_t S, const int32_t* 
     // the automatic choice of ffs_evaluate at four waves per workgroup
     constexpr int wpb = 4;
     void* kl = (msum <= kLaneMaxMsum && mmax <= 8) ? pick_eval_lane(mm, ptb) : nullptr;
-    const bool lane = kl && count >= kLaneEvalAutoMin;
+    const bool lane = kl && count >= kLaneEvalAutoMin && S >= kLaneEvalMinStages;
     void* kern = lane ? kl : pick_eval(mm, ptb);
     if (!kern) return FFS_EUNSUPPORTED;
     const size_t lds = align16((size_t)S * ((size_t)n_pad * ptb + 4)) +

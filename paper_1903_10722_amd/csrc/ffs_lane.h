@@ -529,23 +529,7 @@ __device__ __forceinline__ void cand_features(const uint16_t* A, const unsigned 
     for (int k = 0; k < NR; ++k) s[k] = 0u;
     int cb = (int)(((long long)t0 * B) / n);
     int next = (int)(((long long)(cb + 1) * n + B - 1) / B);   // first position of bucket cb + 1
-    auto flush = [&]() {
-#pragma unroll
-        for (int k = 0; k < SM; ++k)
-            if (k < S) {
-                // stage k sits in register 2 (k / 4) + (k & 1), half (k >> 1) & 1
-                const uint32_t v = PK ? (s[2 * (k >> 2) + (k & 1)] >> (16 * ((k >> 1) & 1))) & 0xFFFFu : s[k];
-                if (v) atomicAdd(&acc[cb * S + k], v);
-            }
-#pragma unroll
-        for (int k = 0; k < NR; ++k) s[k] = 0u;
-    };
-    for (int t = t0; t < t1; ++t) {
-        if (t >= next) {
-            flush();
-            cb += 1;
-            next = (int)(((long long)(cb + 1) * n + B - 1) / B);
-        }
+    auto add_row = [&](uint32_t* x, int t) {
         const PT* row = reinterpret_cast<const PT*>(pJ + (size_t)A[t] * rsb);
         constexpr int PV = 16 / (int)sizeof(PT);   // processing times per 16-byte read
         constexpr int NB = (SM + PV - 1) / PV;     // 16-byte reads per row
@@ -561,18 +545,76 @@ __device__ __forceinline__ void cand_features(const uint16_t* A, const unsigned 
                     if (r < NR) {
                         const u16x2 lo = __builtin_bit_cast(u16x2, ww[d] & 0x00FF00FFu);
                         const u16x2 hi = __builtin_bit_cast(u16x2, (ww[d] >> 8) & 0x00FF00FFu);
-                        s[r] = __builtin_bit_cast(uint32_t, __builtin_bit_cast(u16x2, s[r]) + lo);
-                        s[r + 1] = __builtin_bit_cast(uint32_t, __builtin_bit_cast(u16x2, s[r + 1]) + hi);
+                        x[r] = __builtin_bit_cast(uint32_t, __builtin_bit_cast(u16x2, x[r]) + lo);
+                        x[r + 1] = __builtin_bit_cast(uint32_t, __builtin_bit_cast(u16x2, x[r + 1]) + hi);
                     }
                 }
             } else {
 #pragma unroll
                 for (int q = 0; q < PV; ++q)
-                    if (v * PV + q < SM) s[v * PV + q] += (ww[q >> 1] >> (16 * (q & 1))) & 0xFFFFu;
+                    if (v * PV + q < SM) x[v * PV + q] += (ww[q >> 1] >> (16 * (q & 1))) & 0xFFFFu;
             }
         }
+    };
+    auto flush = [&]() {
+#pragma unroll
+        for (int k = 0; k < SM; ++k)
+            if (k < S) {
+                // stage k sits in register 2 (k / 4) + (k & 1), half (k >> 1) & 1
+                const uint32_t v = PK ? (s[2 * (k >> 2) + (k & 1)] >> (16 * ((k >> 1) & 1))) & 0xFFFFu : s[k];
+                if (v) atomicAdd(&acc[cb * S + k], v);
+            }
+#pragma unroll
+        for (int k = 0; k < NR; ++k) s[k] = 0u;
+    };
+    if (n / B >= C) {
+        // every bucket holds at least C positions, so [t0, t1) meets at most
+        // one boundary, tb: the sums are snapshotted there (a select per
+        // register, no divergent flush inside the loop) and split after it
+        const int tb = next < t1 ? next : t1;
+        uint32_t snap[NR];
+#pragma unroll
+        for (int k = 0; k < NR; ++k) snap[k] = 0u;
+#pragma unroll 2
+        for (int t = t0; t < t1; ++t) {
+            const bool at = t == tb;
+#pragma unroll
+            for (int k = 0; k < NR; ++k) snap[k] = at ? s[k] : snap[k];
+            add_row(s, t);
+        }
+        if (tb >= t1) {
+#pragma unroll
+            for (int k = 0; k < NR; ++k) snap[k] = s[k];
+        }
+        // s - snap per 16-bit half (each half only grows, so no borrow crosses)
+#pragma unroll
+        for (int k = 0; k < NR; ++k) {
+            if (PK) {
+                typedef uint16_t u16x2 __attribute__((ext_vector_type(2)));
+                s[k] = __builtin_bit_cast(uint32_t, __builtin_bit_cast(u16x2, s[k]) - __builtin_bit_cast(u16x2, snap[k]));
+            } else {
+                s[k] -= snap[k];
+            }
+        }
+#pragma unroll
+        for (int k = 0; k < SM; ++k)
+            if (k < S && t0 < t1) {
+                const uint32_t v0 = PK ? (snap[2 * (k >> 2) + (k & 1)] >> (16 * ((k >> 1) & 1))) & 0xFFFFu : snap[k];
+                const uint32_t v1 = PK ? (s[2 * (k >> 2) + (k & 1)] >> (16 * ((k >> 1) & 1))) & 0xFFFFu : s[k];
+                if (v0) atomicAdd(&acc[cb * S + k], v0);
+                if (v1) atomicAdd(&acc[(cb + 1) * S + k], v1);
+            }
+    } else {
+        for (int t = t0; t < t1; ++t) {
+            if (t >= next) {
+                flush();
+                cb += 1;
+                next = (int)(((long long)(cb + 1) * n + B - 1) / B);
+            }
+            add_row(s, t);
+        }
+        if (t0 < t1) flush();
     }
-    if (t0 < t1) flush();
     wave_sync();
     const float fn = (float)n, fLB = (float)I->LB;
     for (int e = lane; e < kFeat; e += kWave) {

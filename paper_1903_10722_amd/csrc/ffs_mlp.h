@@ -13,6 +13,7 @@ namespace flowshop {
 
 typedef __bf16 bf16x8_t __attribute__((ext_vector_type(8)));
 typedef float f32x16_t __attribute__((ext_vector_type(16)));
+typedef uint32_t gu32x4_t __attribute__((ext_vector_type(4)));
 
 constexpr int kFeat = 256;
 constexpr int kHidden = 512;
@@ -30,14 +31,82 @@ __device__ __forceinline__ float bf16_to_f32(uint16_t h) { return __uint_as_floa
 // C[M x N] = opA[M x K] * opB[K x N], BF16 operands, FP32 accumulation.
 //   TA = false: A stored [M][K] (row stride lda);  true: stored [K][M].
 //   TB = false: B stored [K][N] (row stride ldb);  true: stored [N][K].
-// Block tile 128 x 128, K step 32, four waves of 64 x 64 (2 x 2 MFMA 32x32x16).
+// Block tile 128 x 128, K step 64, four waves of 64 x 64 (2 x 2 MFMA 32x32x16).
 // v_mfma_f32_32x32x16_bf16 lane layout: lane l supplies row (l % 32) of A and
 // column (l % 32) of B for k = 8 (l / 32) .. + 7; it receives column (l % 32)
 // of D at rows 8 (r / 4) + 4 (l / 32) + r % 4, r = 0..15.
+// Both operands sit in LDS k-contiguous per row ([i][k], [j][k]).  The next K
+// tile is read from HBM into registers while the MFMAs run on the current
+// one.  A K-contiguous operand is read as 16-byte rows (four per thread); an
+// operand stored k-major ([K][M] or [K][N]) is read by half the workgroup as
+// 8 x 8 blocks (eight 16-byte rows of k), transposed in registers with byte
+// permutes and written as eight 16-byte rows of i.
 // blockIdx.z splits K into gridDim.z equal ranges (EPI_F32 writes each
 // split's partial product to its own M x N slice).
 enum GemmEpi { EPI_F32 = 0, EPI_BIAS_RELU_BF16 = 1, EPI_MASK_BF16 = 2 };
-constexpr int GBM = 128, GBN = 128, GBK = 32, GLD = GBK + 8;
+constexpr int GBM = 128, GBN = 128, GBK = 64, GLD = GBK + 8;
+
+// Transpose of an 8 x 8 block of 16-bit values: x[r] holds row r (element c
+// in half c % 2 of word c / 2); y[c] receives column c.
+__device__ __forceinline__ void transpose8x8_u16(const gu32x4_t (&x)[8], gu32x4_t (&y)[8])
+{
+#pragma unroll
+    for (int c = 0; c < 8; ++c) {
+        const uint32_t sel = (c & 1) ? 0x07060302u : 0x05040100u;
+        uint32_t w[4];
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+            w[q] = __builtin_amdgcn_perm(x[2 * q + 1][c >> 1], x[2 * q][c >> 1], sel);
+        }
+        y[c] = gu32x4_t{w[0], w[1], w[2], w[3]};
+    }
+}
+
+// One operand's share of a K tile, HBM -> registers -> LDS ([x][k] rows of
+// GLD).  KM = false: the operand is k-contiguous per row, 1024 16-byte rows
+// of 8 k, four per thread.  KM = true: stored k-major, one 8 x 8 block per
+// thread of the half `half` of the workgroup, transposed in registers.
+template <bool KM>
+struct GemmStage {
+    gu32x4_t r[KM ? 8 : 4];
+
+    __device__ __forceinline__ void load(const uint16_t* __restrict__ X, int ld, int x0, int k0, int tid, int half)
+    {
+        if constexpr (!KM) {
+#pragma unroll
+            for (int u = 0; u < 4; ++u) {
+                const int v = tid + 256 * u, x = v >> 3, kk = (v & 7) * 8;
+                r[u] = *reinterpret_cast<const gu32x4_t*>(&X[(size_t)(x0 + x) * ld + k0 + kk]);
+            }
+        } else {
+            if ((tid >> 7) == half) {
+                const int q = tid & 127, kb = (q >> 4) * 8, xb = (q & 15) * 8;
+#pragma unroll
+                for (int t = 0; t < 8; ++t)
+                    r[t] = *reinterpret_cast<const gu32x4_t*>(&X[(size_t)(k0 + kb + t) * ld + x0 + xb]);
+            }
+        }
+    }
+
+    __device__ __forceinline__ void store(uint16_t* Xs, int tid, int half) const
+    {
+        if constexpr (!KM) {
+#pragma unroll
+            for (int u = 0; u < 4; ++u) {
+                const int v = tid + 256 * u, x = v >> 3, kk = (v & 7) * 8;
+                *reinterpret_cast<gu32x4_t*>(&Xs[x * GLD + kk]) = r[u];
+            }
+        } else {
+            if ((tid >> 7) == half) {
+                const int q = tid & 127, kb = (q >> 4) * 8, xb = (q & 15) * 8;
+                gu32x4_t y[8];
+                transpose8x8_u16(r, y);
+#pragma unroll
+                for (int c = 0; c < 8; ++c) *reinterpret_cast<gu32x4_t*>(&Xs[(xb + c) * GLD + kb]) = y[c];
+            }
+        }
+    }
+};
 
 template <bool TA, bool TB, int EPI>
 __global__ void __launch_bounds__(256) k_gemm(const uint16_t* __restrict__ A, const uint16_t* __restrict__ B,
@@ -59,40 +128,15 @@ __global__ void __launch_bounds__(256) k_gemm(const uint16_t* __restrict__ A, co
 #pragma unroll
             for (int r = 0; r < 16; ++r) acc[a][b][r] = 0.f;
 
-    for (int k0 = kbeg; k0 < kend; k0 += GBK) {
-        // stage A as As[i][k]
-        if (!TA) {
-            for (int v = tid; v < GBM * GBK / 8; v += 256) {
-                const int i = v >> 2, kk = (v & 3) * 8;
-                *reinterpret_cast<uint4*>(&As[i * GLD + kk]) =
-                    *reinterpret_cast<const uint4*>(&A[(size_t)(bm + i) * lda + k0 + kk]);
-            }
-        } else {
-            for (int v = tid; v < GBK * GBM / 8; v += 256) {
-                const int kk = v >> 4, i = (v & 15) * 8;
-                const uint4 x = *reinterpret_cast<const uint4*>(&A[(size_t)(k0 + kk) * lda + bm + i]);
-                const uint16_t* e = reinterpret_cast<const uint16_t*>(&x);
-#pragma unroll
-                for (int t = 0; t < 8; ++t) As[(i + t) * GLD + kk] = e[t];
-            }
-        }
-        // stage B as Bs[j][k]
-        if (TB) {
-            for (int v = tid; v < GBN * GBK / 8; v += 256) {
-                const int j = v >> 2, kk = (v & 3) * 8;
-                *reinterpret_cast<uint4*>(&Bs[j * GLD + kk]) =
-                    *reinterpret_cast<const uint4*>(&B[(size_t)(bn + j) * ldb + k0 + kk]);
-            }
-        } else {
-            for (int v = tid; v < GBK * GBN / 8; v += 256) {
-                const int kk = v >> 4, j = (v & 15) * 8;
-                const uint4 x = *reinterpret_cast<const uint4*>(&B[(size_t)(k0 + kk) * ldb + bn + j]);
-                const uint16_t* e = reinterpret_cast<const uint16_t*>(&x);
-#pragma unroll
-                for (int t = 0; t < 8; ++t) Bs[(j + t) * GLD + kk] = e[t];
-            }
-        }
-        __syncthreads();
+    // k-major operands: A by threads 0..127, B by threads 128..255
+    GemmStage<TA> sa;
+    GemmStage<!TB> sb;
+    sa.load(A, lda, bm, kbeg, tid, 0);
+    sb.load(B, ldb, bn, kbeg, tid, 1);
+    sa.store(As, tid, 0);
+    sb.store(Bs, tid, 1);
+    __syncthreads();
+    auto mfma_tile = [&]() {
 #pragma unroll
         for (int kk = 0; kk < GBK; kk += 16) {
             bf16x8_t a[2], b[2];
@@ -107,8 +151,20 @@ __global__ void __launch_bounds__(256) k_gemm(const uint16_t* __restrict__ A, co
                 for (int tj = 0; tj < 2; ++tj)
                     acc[ti][tj] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a[ti], b[tj], acc[ti][tj], 0, 0, 0);
         }
+    };
+    // every K tile but the last: the next one's HBM reads are in flight
+    // during this one's MFMAs
+    for (int k0 = kbeg; k0 + GBK < kend; k0 += GBK) {
+        sa.load(A, lda, bm, k0 + GBK, tid, 0);
+        sb.load(B, ldb, bn, k0 + GBK, tid, 1);
+        __builtin_amdgcn_sched_barrier(0);   // issue the reads before the MFMAs
+        mfma_tile();
+        __syncthreads();
+        sa.store(As, tid, 0);
+        sb.store(Bs, tid, 1);
         __syncthreads();
     }
+    mfma_tile();
     float* Cz = (EPI == EPI_F32) ? Cf + (size_t)blockIdx.z * M * ldc : nullptr;
 #pragma unroll
     for (int ti = 0; ti < 2; ++ti)
@@ -131,15 +187,30 @@ __global__ void __launch_bounds__(256) k_gemm(const uint16_t* __restrict__ A, co
             }
 }
 
+// sum of x[y * stride], y = 0 .. n - 1, added in that order; the reads of
+// 16 terms are issued before their sums.
+__device__ __forceinline__ float sum_strided(const float* __restrict__ x, size_t stride, int n)
+{
+    float s = 0.f;
+    int y = 0;
+    for (; y + 16 <= n; y += 16) {
+        float v[16];
+#pragma unroll
+        for (int u = 0; u < 16; ++u) v[u] = x[(size_t)(y + u) * stride];
+#pragma unroll
+        for (int u = 0; u < 16; ++u) s += v[u];
+    }
+    for (; y < n; ++y) s += x[(size_t)y * stride];
+    return s;
+}
+
 // out[i] = sum over splits s of part[s][i]  (fixed order: deterministic)
 __global__ void __launch_bounds__(256) k_sum_splits(const float* __restrict__ part, int splits, size_t count,
                                                     float* __restrict__ out)
 {
     const size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= count) return;
-    float s = 0.f;
-    for (int z = 0; z < splits; ++z) s += part[(size_t)z * count + i];
-    out[i] = s;
+    out[i] = sum_strided(part + i, count, splits);
 }
 
 // ---- output layer --------------------------------------------------------
@@ -241,16 +312,8 @@ __global__ void __launch_bounds__(256) k_colsum3_sum(Colsum3 a, const float* __r
                                                      const float* __restrict__ dpart, float* __restrict__ dsum)
 {
     const int e = blockIdx.x * blockDim.x + threadIdx.x;
-    if (e < 3 * kHidden) {
-        float s = 0.f;
-        for (int y = 0; y < chunks; ++y) s += part[(size_t)y * 3 * kHidden + e];
-        a.out[e / kHidden][e % kHidden] = s;
-    }
-    if (e == 3 * kHidden) {
-        float s = 0.f;
-        for (int y = 0; y < chunks; ++y) s += dpart[y];
-        *dsum = s;
-    }
+    if (e < 3 * kHidden) a.out[e / kHidden][e % kHidden] = sum_strided(part + e, (size_t)3 * kHidden, chunks);
+    if (e == 3 * kHidden) *dsum = sum_strided(dpart, 1, chunks);
 }
 
 // Adam (Kingma & Ba) on FP32 master weights; writes the BF16 copy when given.
