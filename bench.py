@@ -248,7 +248,7 @@ def surrogate_compare(seconds: float, seed: int = 101) -> dict:
         torch.cuda.synchronize()
         t0 = time.perf_counter()
         while time.perf_counter() - t0 < seconds:
-            ctx.evolve(5)
+            ctx.evolve(w["interval"])   # whole epochs, replayed from a captured graph
             torch.cuda.synchronize()
         dt = time.perf_counter() - t0
         res = {"best_makespan": ctx.best(0)["makespan"], "generations": ctx.generation, "seconds": dt}

@@ -713,7 +713,8 @@ T* at(ffs_ctx* c, size_t off) { return reinterpret_cast<T*>(c->ws + off); }
 
 // y = MLP(X) for `rows` rows (multiple of 128; the output layer covers the
 // first out_rows); H1, H2 receive the hidden activations; with K > 0 also
-// choice[cell] = argmin over each cell's K consecutive rows.
+// choice[cell] = argmin over each cell's K consecutive rows.  out_rows = 0:
+// the hidden layers only (training fuses the output layer with its gradient).
 int mlp_forward(ffs_ctx* c, const uint16_t* X, int rows, uint16_t* H1, uint16_t* H2, float* y, int K, int* choice,
                 int out_rows)
 {
@@ -725,6 +726,7 @@ int mlp_forward(ffs_ctx* c, const uint16_t* X, int rows, uint16_t* H1, uint16_t*
     rc = gemm<false, true, EPI_BIAS_RELU_BF16>(c, H1, wb + kP_W2, rows, kHidden, kHidden, kHidden, kHidden, nullptr, H2,
                                                kHidden, w + kP_b2, nullptr, 1);
     if (rc) return rc;
+    if (out_rows == 0) return FFS_OK;
     const int waves = (K > 0) ? out_rows / K : out_rows;
     hipLaunchKernelGGL(k_mlp_out, dim3((waves + 3) / 4), dim3(256), 0, c->stream, H2, wb + kP_w3, w + kP_b3,
                        K > 0 ? waves * K : out_rows, K, y, choice);
@@ -732,9 +734,10 @@ int mlp_forward(ffs_ctx* c, const uint16_t* X, int rows, uint16_t* H1, uint16_t*
 }
 
 // Gradients of mean((y - t)^2) for `rows` rows of X into grad (parameter
-// layout).  H1, H2, y, dZ2, dZ1 are the batch buffers unless given.
+// layout).  H1, H2, y, dZ2, dZ1 are the batch buffers unless given.  With
+// `step` an Adam step follows: the step count advances on the device.
 int mlp_gradients(ffs_ctx* c, const uint16_t* X, const float* t, int rows, float* grad, uint16_t* dZ2o,
-                  uint16_t* dZ1o)
+                  uint16_t* dZ1o, bool step)
 {
     if (rows < 128 || rows > kBatch || rows % 128) return fail(c, FFS_EINVAL, "rows must be a multiple of 128 in [128, %d]", kBatch);
     uint16_t* H1 = at<uint16_t>(c, c->o_H1b);
@@ -745,10 +748,10 @@ int mlp_gradients(ffs_ctx* c, const uint16_t* X, const float* t, int rows, float
     uint16_t* dZ1 = dZ1o ? dZ1o : at<uint16_t>(c, c->o_dZ1);
     const uint16_t* wb = at<uint16_t>(c, c->o_wb);
     float* part = at<float>(c, c->o_part);
-    int rc = mlp_forward(c, X, rows, H1, H2, y, 0, nullptr, rows);
+    int rc = mlp_forward(c, X, rows, H1, H2, y, 0, nullptr, 0);
     if (rc) return rc;
-    hipLaunchKernelGGL(k_mlp_dz2, dim3(rows * kHidden / 256), dim3(256), 0, c->stream, y, t, H2, wb + kP_w3, rows, dy,
-                       dZ2);
+    hipLaunchKernelGGL(k_mlp_out_dz2, dim3(rows / 4), dim3(256), 0, c->stream, (const uint16_t*)H2, wb + kP_w3,
+                       at<const float>(c, c->o_w) + kP_b3, t, rows, y, dy, dZ2);
     const int splits = rows / 128;
     rc = gemm<true, false, EPI_F32>(c, dZ2, H1, kHidden, kHidden, rows, kHidden, kHidden, part, nullptr, kHidden,
                                     nullptr, nullptr, splits);
@@ -773,7 +776,9 @@ int mlp_gradients(ffs_ctx* c, const uint16_t* X, const float* t, int rows, float
         const int chunks = rows / 64;
         hipLaunchKernelGGL(k_colsum3, dim3(1, chunks, 3), dim3(256), 0, c->stream, cs, (const float*)dy, cpart, dpart);
         hipLaunchKernelGGL(k_colsum3_sum, dim3((3 * kHidden + 1 + 255) / 256), dim3(256), 0, c->stream, cs,
-                           (const float*)cpart, chunks, (const float*)dpart, grad + kP_b3);
+                           (const float*)cpart, chunks, (const float*)dpart, grad + kP_b3,
+                           step ? at<long long>(c, c->o_adam) : nullptr, at<const float2>(c, c->o_bc), kBcSteps,
+                           reinterpret_cast<float*>(c->ws + c->o_adam + 8));
     }
     rc = gemm<true, false, EPI_F32>(c, dZ1, X, kHidden, kFeat, rows, kHidden, kFeat, part, nullptr, kFeat, nullptr,
                                     nullptr, splits);
@@ -784,14 +789,14 @@ int mlp_gradients(ffs_ctx* c, const uint16_t* X, const float* t, int rows, float
     return FFS_OK;
 }
 
+// One Adam step; the step count and its bias corrections were advanced by
+// the gradients' column-sum kernel (mlp_gradients with `step` set).
 int mlp_adam(ffs_ctx* c)
 {
-    float* bc = reinterpret_cast<float*>(c->ws + c->o_adam + 8);
-    hipLaunchKernelGGL(k_adam_prep, dim3(1), dim3(64), 0, c->stream, at<long long>(c, c->o_adam),
-                       at<const float2>(c, c->o_bc), kBcSteps, bc);
     hipLaunchKernelGGL(k_adam, dim3((kParams + 255) / 256), dim3(256), 0, c->stream, at<float>(c, c->o_w),
                        at<float>(c, c->o_m), at<float>(c, c->o_v), at<const float>(c, c->o_g),
-                       at<uint16_t>(c, c->o_wb), kParams, kLr, kBeta1, kBeta2, kEps, (const float*)bc);
+                       at<uint16_t>(c, c->o_wb), kParams, kLr, kBeta1, kBeta2, kEps,
+                       reinterpret_cast<const float*>(c->ws + c->o_adam + 8));
     HIP_TRY(c, hipGetLastError());
     return FFS_OK;
 }
@@ -801,14 +806,15 @@ int mlp_adam(ffs_ctx* c)
 int surrogate_train(ffs_ctx* c)
 {
     const auto& I = c->inst[c->surr];
-    int* idx = at<int>(c, c->o_idx);
     const Control* ctl = reinterpret_cast<const Control*>(c->ws + c->off_ctl);
+    int* idx = at<int>(c, c->o_idx);
     hipLaunchKernelGGL(k_batch_idx, dim3((kBatch / 8 + 255) / 256), dim3(256), 0, c->stream, (uint64_t)I.seed,
                        (uint64_t)c->surr, ctl, c->surr_cells, kRing, kBatch, idx);
     hipLaunchKernelGGL(k_gather_batch, dim3(kBatch / 8), dim3(256), 0, c->stream, at<const uint16_t>(c, c->o_ringX),
-                       at<const float>(c, c->o_ringT), idx, kBatch, at<uint16_t>(c, c->o_Xb), at<float>(c, c->o_tb));
+                       at<const float>(c, c->o_ringT), (const int*)idx, kBatch, at<uint16_t>(c, c->o_Xb),
+                       at<float>(c, c->o_tb));
     int rc = mlp_gradients(c, at<const uint16_t>(c, c->o_Xb), at<const float>(c, c->o_tb), kBatch,
-                           at<float>(c, c->o_g), nullptr, nullptr);
+                           at<float>(c, c->o_g), nullptr, nullptr, true);
     if (rc) return rc;
     return mlp_adam(c);
 }
@@ -1709,7 +1715,7 @@ int ffs_mlp_gradients(ffs_ctx* c, int32_t inst, const uint16_t* X, const float* 
     int rc = check_surr(c, inst);
     if (rc) return rc;
     if (!X || !t || !grad) return fail(c, FFS_EINVAL, "null buffer");
-    rc = mlp_gradients(c, X, t, rows, grad, dZ2, dZ1);
+    rc = mlp_gradients(c, X, t, rows, grad, dZ2, dZ1, false);
     if (rc) return rc;
     HIP_TRY(c, hipStreamSynchronize(c->stream));
     return FFS_OK;
@@ -1720,7 +1726,7 @@ int ffs_mlp_train_step(ffs_ctx* c, int32_t inst, const uint16_t* X, const float*
     int rc = check_surr(c, inst);
     if (rc) return rc;
     if (!X || !t) return fail(c, FFS_EINVAL, "null buffer");
-    rc = mlp_gradients(c, X, t, rows, at<float>(c, c->o_g), nullptr, nullptr);
+    rc = mlp_gradients(c, X, t, rows, at<float>(c, c->o_g), nullptr, nullptr, true);
     if (rc) return rc;
     rc = mlp_adam(c);
     if (rc) return rc;

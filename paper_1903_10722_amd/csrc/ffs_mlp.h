@@ -248,17 +248,35 @@ __global__ void __launch_bounds__(256) k_mlp_out(const uint16_t* __restrict__ H2
 }
 
 // ---- backward pieces -------------------------------------------------------
-// dy = 2 (y - t) / rows; dZ2[i][j] = bf16(dy[i] * w3[j]) where H2[i][j] > 0.
-__global__ void __launch_bounds__(256) k_mlp_dz2(const float* __restrict__ y, const float* __restrict__ t,
-                                                 const uint16_t* __restrict__ H2, const uint16_t* __restrict__ w3,
-                                                 int rows, float* __restrict__ dy, uint16_t* __restrict__ dZ2)
+// Output layer and its gradient for training, one wave per row:
+// y[i] = H2[i] . w3 + b3 (as k_mlp_out), dy[i] = 2 (y[i] - t[i]) / rows and
+// dZ2[i][j] = bf16(dy[i] * w3[j]) where H2[i][j] > 0.
+__global__ void __launch_bounds__(256) k_mlp_out_dz2(const uint16_t* __restrict__ H2, const uint16_t* __restrict__ w3,
+                                                     const float* __restrict__ b3, const float* __restrict__ t,
+                                                     int rows, float* __restrict__ y, float* __restrict__ dy,
+                                                     uint16_t* __restrict__ dZ2)
 {
-    const size_t e = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (e >= (size_t)rows * kHidden) return;
-    const int i = (int)(e / kHidden), j = (int)(e % kHidden);
-    const float d = 2.f * (y[i] - t[i]) / (float)rows;
-    if (j == 0) dy[i] = d;
-    dZ2[e] = (bf16_to_f32(H2[e]) > 0.f) ? f32_to_bf16(d * bf16_to_f32(w3[j])) : (uint16_t)0;
+    const int i = (blockIdx.x * blockDim.x + threadIdx.x) >> 6, lane = threadIdx.x & 63;
+    if (i >= rows) return;
+    const uint4 wv = *reinterpret_cast<const uint4*>(&w3[lane * 8]);
+    const uint16_t* we = reinterpret_cast<const uint16_t*>(&wv);
+    const uint4 hv = *reinterpret_cast<const uint4*>(&H2[(size_t)i * kHidden + lane * 8]);
+    const uint16_t* he = reinterpret_cast<const uint16_t*>(&hv);
+    float s = 0.f;
+#pragma unroll
+    for (int q = 0; q < 8; ++q) s += bf16_to_f32(he[q]) * bf16_to_f32(we[q]);
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) s += __shfl_xor(s, off, 64);
+    s += b3[0];
+    const float d = 2.f * (s - t[i]) / (float)rows;
+    if (lane == 0) {
+        y[i] = s;
+        dy[i] = d;
+    }
+    uint16_t o[8];
+#pragma unroll
+    for (int q = 0; q < 8; ++q) o[q] = (bf16_to_f32(he[q]) > 0.f) ? f32_to_bf16(d * bf16_to_f32(we[q])) : (uint16_t)0;
+    *reinterpret_cast<uint4*>(&dZ2[(size_t)i * kHidden + lane * 8]) = *reinterpret_cast<const uint4*>(o);
 }
 
 // Column sums of three BF16 matrices [rows][512] in one launch, in two
@@ -307,32 +325,35 @@ __global__ void __launch_bounds__(256) k_colsum3(Colsum3 a, const float* __restr
 }
 
 // out_m[j] = sum over chunks y (in order) of part[y][m * 512 + j]; dsum =
-// sum of dpart in order.
+// sum of dpart in order.  With step non-null (a training step follows) one
+// thread also advances the Adam step count t kept in device memory (so a
+// captured graph can replay training steps without the host knowing their
+// number) and writes step t + 1's bias corrections 1 - beta^(t+1) to bc,
+// from `table` (computed on the host in FP64 and rounded to FP32; entry t for
+// t < steps, both exactly 1 beyond).
 __global__ void __launch_bounds__(256) k_colsum3_sum(Colsum3 a, const float* __restrict__ part, int chunks,
-                                                     const float* __restrict__ dpart, float* __restrict__ dsum)
+                                                     const float* __restrict__ dpart, float* __restrict__ dsum,
+                                                     long long* step, const float2* __restrict__ table, int steps,
+                                                     float* __restrict__ bc)
 {
     const int e = blockIdx.x * blockDim.x + threadIdx.x;
     if (e < 3 * kHidden) a.out[e / kHidden][e % kHidden] = sum_strided(part + e, (size_t)3 * kHidden, chunks);
-    if (e == 3 * kHidden) *dsum = sum_strided(dpart, 1, chunks);
+    if (e == 3 * kHidden) {
+        *dsum = sum_strided(dpart, 1, chunks);
+        if (step) {
+            const long long t = *step + 1;
+            *step = t;
+            const float2 b = (t <= steps) ? table[t - 1] : make_float2(1.f, 1.f);
+            bc[0] = b.x;
+            bc[1] = b.y;
+        }
+    }
 }
 
 // Adam (Kingma & Ba) on FP32 master weights; writes the BF16 copy when given.
-// Advances the Adam step count kept in device memory and looks up that
-// step's bias corrections 1 - beta^t (computed on the host in FP64 and
-// rounded to FP32; table[t - 1] for t <= steps, both exactly 1 beyond).
-// Run by one thread before k_adam, so a captured graph can replay training
-// steps without the host knowing their number.
-__global__ void k_adam_prep(long long* __restrict__ step, const float2* __restrict__ table, int steps,
-                            float* __restrict__ bc)
-{
-    if (threadIdx.x != 0 || blockIdx.x != 0) return;
-    const long long t = *step + 1;
-    *step = t;
-    const float2 b = (t <= steps) ? table[t - 1] : make_float2(1.f, 1.f);
-    bc[0] = b.x;
-    bc[1] = b.y;
-}
-
+// One Adam step on every parameter with the bias corrections bc[0] =
+// 1 - beta1^t, bc[1] = 1 - beta2^t of step t, which k_colsum3_sum looked up
+// when it advanced the step count kept in device memory.
 __global__ void __launch_bounds__(256) k_adam(float* __restrict__ w, float* __restrict__ m, float* __restrict__ v,
                                               const float* __restrict__ g, uint16_t* __restrict__ wb, int count,
                                               float lr, float beta1, float beta2, float eps,
