@@ -95,3 +95,48 @@ def test_line_sweep_rejections():
     with pytest.raises(FFSError):
         ctx.add_instance(m9, p9, [inputs.cellular(4, 4, 0.9, 0.1, sweep=1), inputs.pseudo(16, 0.5, 0.0)], interval=0)
     ctx.close()
+
+
+def test_line_sweep_sixteen_islands_with_ring():
+    """The large workload's layout at 1/16 of the side (8 swept 8 x 8 grids and
+    8 pseudo islands, ring-then-adaptive migration every 5 generations),
+    generation by generation on the lane mapping (every anti-diagonal launch
+    holds all eight swept islands) against the oracle."""
+    ensure_built()
+    w = inputs.workload("large", seed=3, scale=16)
+    w["interval"] = 5
+    for x in w["islands"]:
+        if x["kind"] == 0:
+            x["sweep"] = 1
+    say("[sweep] sixteen islands, ring")
+    ctx = make_ctx([w], mapping=1)
+    ga = oracle_ga(w)
+    for g in (1, 4, 1, 5, 5):
+        ctx.evolve(g)
+        ga.evolve(g)
+        assert_same_state(ctx, ga, 0, 16, f"sixteen islands sweep generation {ctx.generation}")
+    assert ctx.migration_counters(0) == ga.counters()
+    ctx.close()
+
+
+def test_line_sweep_checkpoint_restore():
+    """A checkpoint taken mid-run and restored into a fresh context continues
+    the line-sweep trajectory exactly as the uninterrupted run and the oracle
+    do."""
+    ensure_built()
+    w = _sweep_workload(40, 5, 9, 6, 54, interval=4, seed=9, sel=2)
+    say("[sweep] checkpoint and restore")
+    a = make_ctx([w])
+    a.evolve(7)
+    image = a.checkpoint()
+    a.evolve(9)
+    b = make_ctx([w])
+    b.restore(image)
+    b.evolve(9)
+    ga = oracle_ga(w)
+    ga.evolve(16)
+    assert_same_state(a, ga, 0, 2, "uninterrupted generation 16")
+    assert_same_state(b, ga, 0, 2, "restored generation 16")
+    assert a.checkpoint() == b.checkpoint()
+    a.close()
+    b.close()
