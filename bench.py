@@ -622,6 +622,7 @@ def measure(name: str, seed: int, steps: int, warmup: int, args) -> dict:
     t_bind = time.perf_counter() - t_bind
     stream = ctx.stream
     used = ctx.mapping()
+    chains = ctx.chains()
     kernel = {0: "k_generation", 1: "k_generation_lane", 2: "k_generation_lane+k_generation"}[used]
 
     for _ in range(warmup):
@@ -681,6 +682,9 @@ def measure(name: str, seed: int, steps: int, warmup: int, args) -> dict:
         k_ms, launches = k0.elapsed_time(k1), L * epochs
         ctx2.close()
         timing = "HIP events around back-to-back graph replays of generation launches only"
+        if chains == 2:
+            timing += ("; one launch = one generation of every island: two concurrent dispatches (launch chains), "
+                       "each over half of the islands")
     avg_s = k_ms / max(1, launches) / 1e3
     ops_per_launch = sum(int(v["p"].shape[0]) * int(sum(int(x) + 6 for x in v["m"])) *
                          sum(x["size"] for x in v["islands"]) for v in ws)
@@ -698,6 +702,7 @@ def measure(name: str, seed: int, steps: int, warmup: int, args) -> dict:
                    "machines": [int(x) for x in m] if len(ws) == 1 else "per instance",
                    "decodes_per_generation": decodes_per_gen, "generations_per_step": I,
                    "mapping": {0: "per stage", 1: "per lane", 2: "per instance (autotuned)"}[used],
+                   "launch_chains": chains,
                    **({"tiles": {k: v["tile"] for k, v in tiles["groups"].items()},
                        "tuning_ms_per_generation": tiles["ms_per_generation"]} if tiles else {})},
         "generations_per_s": gens / (ms / 1e3),

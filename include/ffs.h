@@ -161,6 +161,26 @@ int ffs_set_waves_per_block(ffs_ctx *ctx, int32_t waves);
 int ffs_set_mapping(ffs_ctx *ctx, int32_t mapping);
 int ffs_get_mapping(ffs_ctx *ctx, int32_t *used);
 
+/* Launch chains (islands are independent between migration epochs, Section
+ * 4.3): with 2, the islands of every instance alternate between two groups
+ * whose generations of a migration epoch run as two launch sequences side by
+ * side (two branches of the captured epoch graph, joined before the epoch's
+ * migration), so one group's next generation fills the GPU while the other's
+ * last workgroups finish.  Each group keeps its own best-ever record per
+ * instance; ffs_best returns the better of the two by (makespan, generation,
+ * island, slot), which is the record a single sequence keeps.  1 = one
+ * sequence.  -1 (default) = automatic: 2 when allowed and the context holds
+ * at least 131072 individuals (a generation larger than one round of
+ * resident waves; smaller ones only pay a second launch).  Two chains need
+ * a single launch class (all instances with the same tile and LDS class), no
+ * line-sweep island and no pre-screen; otherwise one is used whatever the
+ * request.  Results never depend on it.  Eager generations (no graph) launch
+ * the two groups in turn.  May be called before or after ffs_bind_workspace
+ * (after: waits for the stream and re-plans).  ffs_get_chains reports the
+ * number in use.                                                            */
+int ffs_set_chains(ffs_ctx *ctx, int32_t chains);
+int ffs_get_chains(ffs_ctx *ctx, int32_t *used);
+
 /* Tile of one instance (overrides the context's for it): mapping -1 / 0 / 1
  * as in ffs_set_mapping (-1: the context's), waves per workgroup 1, 2, 4, 8
  * (0: the context's; narrowed automatically while a workgroup would exceed

@@ -27,7 +27,7 @@ EXPORTS = [
     "ffs_mlp_train_step", "ffs_surrogate_candidates", "ffs_surrogate_choices", "ffs_surrogate_ring",
     "ffs_evaluate_host", "ffs_checkpoint_size", "ffs_checkpoint_save", "ffs_checkpoint_load",
     "ffs_set_mapping", "ffs_get_mapping", "ffs_evaluate_noalloc", "ffs_set_instance_tile",
-    "ffs_set_concurrent",
+    "ffs_set_concurrent", "ffs_set_chains", "ffs_get_chains",
 ]
 
 N_PARAMS = 394753
@@ -287,6 +287,15 @@ class Context:
     def set_concurrent(self, enable: bool):
         """Run a generation's launches side by side (True, the default) or in turn."""
         self._check(self.lib.ffs_set_concurrent(self._h, 1 if enable else 0))
+
+    def set_chains(self, chains: int):
+        """Launch chains of island groups: 1, 2 or -1 (automatic)."""
+        self._check(self.lib.ffs_set_chains(self._h, int(chains)))
+
+    def chains(self) -> int:
+        used = ctypes.c_int32()
+        self._check(self.lib.ffs_get_chains(self._h, ctypes.byref(used)))
+        return int(used.value)
 
     def mapping(self) -> int:
         """Mapping the generation launches use: 0 per stage, 1 per lane, 2 mixed."""

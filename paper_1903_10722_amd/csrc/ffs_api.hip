@@ -50,6 +50,7 @@ struct HostIsland {
     ffs_island_spec spec;
     int size;
     int cell_base;
+    int chain = 0;                // launch chain of its generations
     size_t off_genes[2], off_mk[2], off_genkey, off_minmax, off_sorted, off_sortbest;
 };
 
@@ -151,6 +152,7 @@ void* pick_eval_lane(int mm, int ptb)
 // SIMDs idle (one wave per 64 individuals), and the per-stage lane mapping
 // of k_generation is chosen when the mapping is automatic.
 constexpr long long kLaneAutoMin = 131072;
+constexpr long long kChainAutoMin = 131072;   // individuals per context for two launch chains
 // ffs_evaluate takes the lane mapping from this many rows of at least this
 // many stages (a million random rows: 1.45x and 1.65x faster at 10 and 20
 // stages, 2.3x slower at 5, where the per-stage groups fill the wave too)
@@ -216,6 +218,12 @@ struct ffs_ctx {
     // line-sweep islands: one work item each, launched one anti-diagonal at a
     // time after every generation launch
     std::vector<WorkItem> sweep;
+    // launch chains: with two, the islands form two groups whose generations
+    // of an epoch run as two launch sequences side by side (graph branches),
+    // joined before the epoch's migration
+    int chains = -1;               // requested: -1 automatic, 1, 2
+    int nchain = 1;                // in use
+    int chain_w0[3] = {0, 0, 0};   // work ranges of the chains (single class)
     int sweep_diags = 0;
     size_t off_sweep = 0, sweep_lds = 0;
     void* sweep_kern = nullptr;
@@ -324,6 +332,31 @@ void layout(ffs_ctx* c)
     std::sort(keys.begin(), keys.end(), std::greater<long long>());
     for (auto& I : c->inst) I.cls = (int)(std::find(keys.begin(), keys.end(), class_key(I)) - keys.begin());
     c->n_cls = (int)keys.size();
+    // launch chains: possible when a single class holds every instance, no
+    // island is swept and no instance has the pre-screen (those launches
+    // read the context-wide generation count); automatic from 131072
+    // individuals, where a generation needs more than one round of resident
+    // waves and the other chain's next generation fills the last round (a
+    // smaller generation only pays a second launch).  Islands alternate
+    // between the chains in index order.
+    {
+        bool can = c->n_cls == 1;
+        int islands = 0;
+        long long total = 0;
+        for (auto& I : c->inst) {
+            islands += (int)I.isl.size();
+            if (I.cfg.surrogate_k > 1) can = false;
+            for (auto& L : I.isl) {
+                total += L.size;
+                if (L.spec.kind == 0 && L.spec.sweep) can = false;
+            }
+        }
+        can = can && islands >= 2;
+        const bool want = c->chains == 2 || (c->chains < 0 && total >= kChainAutoMin);
+        c->nchain = (can && want) ? 2 : 1;
+        for (auto& I : c->inst)
+            for (size_t x = 0; x < I.isl.size(); ++x) I.isl[x].chain = (c->nchain == 2) ? (int)(x % 2) : 0;
+    }
     // work items: per island, chunks of (waves per block) x G chromosomes,
     // ordered by cost (n * S * count), largest first
     c->work.clear();
@@ -380,13 +413,29 @@ void layout(ffs_ctx* c)
         I.n_edges = edges;
         c->max_edges = std::max(c->max_edges, edges);
     }
+    auto chain_of = [&](const WorkItem& w) { return c->inst[w.inst].isl[w.island - c->inst[w.inst].isl_base].chain; };
     std::stable_sort(c->work.begin(), c->work.end(), [&](const WorkItem& a, const WorkItem& b) {
         const auto& A = c->inst[a.inst];
         const auto& B = c->inst[b.inst];
         if (A.cls != B.cls) return A.cls < B.cls;
+        if (chain_of(a) != chain_of(b)) return chain_of(a) < chain_of(b);
         return (long long)A.n * A.S * a.count > (long long)B.n * B.S * b.count;
     });
     c->n_work = (int)c->work.size();
+    c->chain_w0[0] = 0;
+    c->chain_w0[1] = c->chain_w0[2] = c->n_work;
+    if (c->nchain == 2) {
+        for (int i = 0; i < c->n_work; ++i)
+            if (chain_of(c->work[i]) == 1) {
+                c->chain_w0[1] = i;
+                break;
+            }
+        if (c->chain_w0[1] == c->n_work) {   // nothing in chain 1: one chain
+            c->nchain = 1;
+            for (auto& I : c->inst)
+                for (auto& L : I.isl) L.chain = 0;
+        }
+    }
     // one launch per class: its work range, LDS bytes and launch-count slots
     // (the first class's launch also carries the best-ever workgroup)
     c->cls_w0.assign(c->n_cls + 1, 0);
@@ -421,8 +470,8 @@ void layout(ffs_ctx* c)
     c->lds_gen = 0;
     for (auto& I : c->inst) {
         I.off_pT = take((size_t)I.S * I.n_pad * c->ptb);
-        I.off_best_perm = take((size_t)I.n_pad * 2);
-        I.off_best_rec = take(4 * sizeof(int));
+        I.off_best_perm = take((size_t)kChains * I.n_pad * 2);
+        I.off_best_rec = take((size_t)kChains * 4 * sizeof(int));
         I.off_counters = take(2 * sizeof(long long));
         for (auto& L : I.isl) {
             for (int b = 0; b < 2; ++b) {
@@ -511,7 +560,11 @@ int check_faults(ffs_ctx* c)
     return FFS_OK;
 }
 
-int launch_generation(ffs_ctx* c, int mode)
+// One generation of every island (mode 0; mode 1: generation 0).  With two
+// launch chains, chain >= 0 launches only that chain's islands, chain 1 on the
+// first auxiliary stream (the caller forks and joins it); chain < 0 launches
+// both in turn on the context's stream.
+int launch_generation(ffs_ctx* c, int mode, int chain = -1)
 {
     const InstDesc* di = reinterpret_cast<const InstDesc*>(c->ws + c->off_insts);
     const IslandDesc* dl = reinterpret_cast<const IslandDesc*>(c->ws + c->off_isls);
@@ -534,6 +587,25 @@ int launch_generation(ffs_ctx* c, int mode)
         e1 = c->ev_pool.back();
         c->ev_pool.pop_back();
         HIP_TRY(c, hipEventRecord(e0, c->stream));
+    }
+    if (mode == 0 && c->nchain == 2) {
+        // a launch per chain, each with one workgroup more than its work
+        // items, which folds the chain's previous generation
+        for (int ch = 0; ch < 2; ++ch) {
+            if (chain >= 0 && ch != chain) continue;
+            const int nw = c->chain_w0[ch + 1] - c->chain_w0[ch];
+            extra = 1 + ch;
+            cnt_off = ch == 0 ? 0 : (c->chain_w0[1] - c->chain_w0[0]) + 1;
+            dwk = dw + c->chain_w0[ch];
+            hipStream_t st = (chain == 1) ? c->aux[0] : c->stream;
+            HIP_TRY(c, hipLaunchKernel(c->cls_kern[0], dim3((unsigned)(nw + 1)), dim3(64 * c->cls_wpb[0]), args,
+                                       c->cls_lds[0], st));
+        }
+        if (e0) {
+            HIP_TRY(c, hipEventRecord(e1, c->stream));
+            c->ev_used.emplace_back(e0, e1);
+        }
+        return FFS_OK;
     }
     // one launch per class; the first has one workgroup more than work
     // items, which folds the previous generation into the best-ever records.
@@ -658,12 +730,12 @@ int prepare_classes(ffs_ctx* c)
         if (!c->sweep_kern) return fail(c, FFS_EUNSUPPORTED, "the line sweep needs at most 8 machines per stage");
         HIP_TRY(c, hipFuncSetAttribute(c->sweep_kern, hipFuncAttributeMaxDynamicSharedMemorySize, (int)c->lds_gen));
     }
-    while ((int)c->aux.size() < c->n_cls - 1) {
+    while ((int)c->aux.size() < std::max(c->n_cls, c->nchain) - 1) {
         hipStream_t st = nullptr;
         HIP_TRY(c, hipStreamCreateWithFlags(&st, hipStreamNonBlocking));
         c->aux.push_back(st);
     }
-    while ((int)c->fork_ev.size() < c->n_cls) {
+    while ((int)c->fork_ev.size() < std::max(c->n_cls, c->nchain)) {
         hipEvent_t e = nullptr;
         HIP_TRY(c, hipEventCreateWithFlags(&e, hipEventDisableTiming));
         c->fork_ev.push_back(e);
@@ -687,11 +759,23 @@ int apply_tile(ffs_ctx* c)
                              hipMemcpyHostToDevice));
     if (c->bound) {
         // new launch width: count launches afresh from the current generation
+        // (its best individuals folded first), and the islands' chains
+        rc = flush_best(c);
+        if (rc) return rc;
         HIP_TRY(c, hipStreamSynchronize(c->stream));
         std::vector<int> zeros(c->max_work + 16, 0);
         HIP_TRY(c, hipMemcpy(c->ws + c->off_counts, zeros.data(), zeros.size() * sizeof(int), hipMemcpyHostToDevice));
         const int base = c->gen;
         HIP_TRY(c, hipMemcpy(c->ws + c->off_ctl + offsetof(Control, base), &base, sizeof base, hipMemcpyHostToDevice));
+        const int bg[2] = {base, base};
+        HIP_TRY(c, hipMemcpy(c->ws + c->off_ctl + offsetof(Control, best_gen), bg, sizeof bg, hipMemcpyHostToDevice));
+        int x = 0;
+        for (auto& I : c->inst)
+            for (auto& L : I.isl) {
+                HIP_TRY(c, hipMemcpy(c->ws + c->off_isls + sizeof(IslandDesc) * x + offsetof(IslandDesc, chain),
+                                     &L.chain, sizeof(int), hipMemcpyHostToDevice));
+                ++x;
+            }
     }
     drop_graph(c);
     return FFS_OK;
@@ -933,7 +1017,7 @@ size_t ckpt_bytes(const ffs_ctx* c)
 {
     size_t b = sizeof(CkptHeader);
     for (const auto& I : c->inst) {
-        b += 4 * sizeof(int32_t) + (size_t)I.n_pad * 2 + 2 * sizeof(int64_t);
+        b += (size_t)kChains * (4 * sizeof(int32_t) + (size_t)I.n_pad * 2) + 2 * sizeof(int64_t);
         for (const auto& L : I.isl) b += (size_t)L.size * I.n_pad * 2 + (size_t)L.size * 4;
     }
     if (c->surr >= 0)
@@ -956,8 +1040,8 @@ std::vector<CkptPiece> ckpt_pieces(const ffs_ctx* c)
     std::vector<CkptPiece> v;
     const int par = c->gen & 1;
     for (const auto& I : c->inst) {
-        v.emplace_back(I.off_best_rec, 4 * sizeof(int32_t));
-        v.emplace_back(I.off_best_perm, (size_t)I.n_pad * 2, I.n, I.n_pad);
+        v.emplace_back(I.off_best_rec, (size_t)kChains * 4 * sizeof(int32_t));
+        v.emplace_back(I.off_best_perm, (size_t)kChains * I.n_pad * 2, I.n, I.n_pad);
         v.emplace_back(I.off_counters, 2 * sizeof(int64_t));
         for (const auto& L : I.isl) {
             v.emplace_back(L.off_genes[par], (size_t)L.size * I.n_pad * 2, I.n, I.n_pad);
@@ -1183,6 +1267,34 @@ int ffs_set_mapping(ffs_ctx* c, int32_t mapping)
     return FFS_OK;
 }
 
+int ffs_set_chains(ffs_ctx* c, int32_t chains)
+{
+    if (!c) return FFS_EINVAL;
+    if (chains != -1 && chains != 1 && chains != 2) return fail(c, FFS_EINVAL, "chains must be -1, 1 or 2");
+    if (!c->bound) {
+        c->chains = chains;
+        return FFS_OK;
+    }
+    HIP_TRY(c, hipStreamSynchronize(c->stream));
+    const int old = c->chains;
+    c->chains = chains;
+    int rc = apply_tile(c);
+    if (rc) {
+        c->chains = old;
+        (void)apply_tile(c);
+        return rc;
+    }
+    return FFS_OK;
+}
+
+int ffs_get_chains(ffs_ctx* c, int32_t* used)
+{
+    if (!c || !used) return FFS_EINVAL;
+    if (!c->inst.empty()) layout(c);
+    *used = c->nchain;
+    return FFS_OK;
+}
+
 int ffs_get_mapping(ffs_ctx* c, int32_t* used)
 {
     if (!c || !used) return FFS_EINVAL;
@@ -1337,6 +1449,7 @@ int ffs_bind_workspace(ffs_ctx* c, void* dptr, size_t bytes)
             e.cell_base = L.cell_base;
             e.sel = L.spec.kind == 0 ? L.spec.selection : 0;
             e.sweep = L.spec.kind == 0 ? L.spec.sweep : 0;
+            e.chain = L.chain;
             hl.push_back(e);
         }
         isl_base += (int)I.isl.size();
@@ -1344,7 +1457,7 @@ int ffs_bind_workspace(ffs_ctx* c, void* dptr, size_t bytes)
     Control ctl;
     memset(&ctl, 0, sizeof ctl);
     ctl.counts = reinterpret_cast<int*>(c->ws + c->off_counts);
-    ctl.best_gen = -1;
+    ctl.best_gen[0] = ctl.best_gen[1] = -1;
     {
         std::vector<int> zeros(c->max_work + 16, 0);
         HIP_TRY(c, hipMemcpy(c->ws + c->off_counts, zeros.data(), zeros.size() * sizeof(int), hipMemcpyHostToDevice));
@@ -1371,7 +1484,7 @@ int ffs_bind_workspace(ffs_ctx* c, void* dptr, size_t bytes)
                 else reinterpret_cast<uint16_t*>(pt.data())[(size_t)k * I.n_pad + j] = (uint16_t)v;
             }
         HIP_TRY(c, hipMemcpy(c->ws + I.off_pT, pt.data(), pt.size(), hipMemcpyHostToDevice));
-        const int rec[4] = {INT_MAX, -1, -1, -1};
+        const int rec[4 * kChains] = {INT_MAX, -1, -1, -1, INT_MAX, -1, -1, -1};
         HIP_TRY(c, hipMemcpy(c->ws + I.off_best_rec, rec, sizeof rec, hipMemcpyHostToDevice));
         const long long cnt[2] = {0, 0};
         HIP_TRY(c, hipMemcpy(c->ws + I.off_counters, cnt, sizeof cnt, hipMemcpyHostToDevice));
@@ -1501,10 +1614,22 @@ int ffs_evolve(ffs_ctx* c, int32_t generations)
                 hipGraph_t graph = nullptr;
                 HIP_TRY(c, hipStreamBeginCapture(c->stream, hipStreamCaptureModeRelaxed));
                 int crc = FFS_OK;
-                for (int t = 0; t < L && crc == FFS_OK; ++t) {
-                    if (c->surr >= 0) crc = surrogate_score(c, nullptr);
-                    if (crc == FFS_OK) crc = launch_generation(c, 0);
-                    if (crc == FFS_OK && c->surr >= 0) crc = surrogate_train(c);
+                if (c->nchain == 2) {
+                    // the chains' generations of the epoch as two branches
+                    HIP_TRY(c, hipEventRecord(c->fork_ev[0], c->stream));
+                    HIP_TRY(c, hipStreamWaitEvent(c->aux[0], c->fork_ev[0], 0));
+                    for (int t = 0; t < L && crc == FFS_OK; ++t) {
+                        crc = launch_generation(c, 0, 0);
+                        if (crc == FFS_OK) crc = launch_generation(c, 0, 1);
+                    }
+                    HIP_TRY(c, hipEventRecord(c->fork_ev[1], c->aux[0]));
+                    HIP_TRY(c, hipStreamWaitEvent(c->stream, c->fork_ev[1], 0));
+                } else {
+                    for (int t = 0; t < L && crc == FFS_OK; ++t) {
+                        if (c->surr >= 0) crc = surrogate_score(c, nullptr);
+                        if (crc == FFS_OK) crc = launch_generation(c, 0);
+                        if (crc == FFS_OK && c->surr >= 0) crc = surrogate_train(c);
+                    }
                 }
                 if (crc == FFS_OK && I > 0) crc = launch_migration(c, -1);
                 hipError_t ec = hipStreamEndCapture(c->stream, &graph);
@@ -1565,16 +1690,23 @@ int ffs_best(ffs_ctx* c, int32_t inst, int32_t* out_mk, int32_t* out_gen, int32_
     const auto& I = c->inst[inst];
     rc = flush_best(c);
     if (rc) return rc;
-    int rec[4];
-    std::vector<uint16_t> perm((size_t)I.n_pad);
+    // the chains' records: the better by (makespan, generation, island, slot)
+    int rec[4 * kChains];
+    std::vector<uint16_t> perm((size_t)kChains * I.n_pad);
     HIP_TRY(c, hipMemcpyAsync(rec, c->ws + I.off_best_rec, sizeof rec, hipMemcpyDeviceToHost, c->stream));
     HIP_TRY(c, hipMemcpyAsync(perm.data(), c->ws + I.off_best_perm, perm.size() * 2, hipMemcpyDeviceToHost, c->stream));
     rc = check_faults(c);
     if (rc) return rc;
-    if (out_mk) *out_mk = rec[0];
-    if (out_gen) *out_gen = rec[1];
+    int b = 0;
+    for (int ch = 1; ch < kChains; ++ch) {
+        const int* x = rec + 4 * ch;
+        const int* y = rec + 4 * b;
+        if (std::lexicographical_compare(x, x + 4, y, y + 4)) b = ch;
+    }
+    if (out_mk) *out_mk = rec[4 * b];
+    if (out_gen) *out_gen = rec[4 * b + 1];
     if (out_perm)
-        for (int j = 0; j < I.n; ++j) out_perm[j] = perm[j];
+        for (int j = 0; j < I.n; ++j) out_perm[j] = perm[(size_t)b * I.n_pad + j];
     return FFS_OK;
 }
 
@@ -1862,7 +1994,7 @@ int ffs_checkpoint_load(ffs_ctx* c, const void* host, size_t bytes)
     HIP_TRY(c, hipMemcpyAsync(&ctl, c->ws + c->off_ctl, sizeof ctl, hipMemcpyDeviceToHost, c->stream));
     HIP_TRY(c, hipStreamSynchronize(c->stream));
     ctl.base = c->gen;
-    ctl.best_gen = c->gen;
+    ctl.best_gen[0] = ctl.best_gen[1] = c->gen;
     ctl.err = 0;
     HIP_TRY(c, hipMemcpyAsync(c->ws + c->off_ctl, &ctl, sizeof ctl, hipMemcpyHostToDevice, c->stream));
     const unsigned long long gk[2] = {~0ull, ~0ull};

@@ -30,10 +30,16 @@ constexpr int kWave = 64;
 constexpr int kMaxStages = 64;
 constexpr int kMaxMachines = 16;
 
+// Islands of a context may form two launch chains whose generations run as
+// independent launch sequences between migration epochs; each chain keeps its
+// own best-ever record per instance, and the instance's record is the better
+// of the two by (makespan, generation, island, slot).
+constexpr int kChains = 2;
+
 struct InstDesc {
     const void* pT;          // [S][n_pad] processing times, uint8 or uint16
-    uint16_t* best_perm;     // [n_pad]
-    int* best_rec;           // makespan, generation, island (local), slot
+    uint16_t* best_perm;     // [kChains][n_pad]
+    int* best_rec;           // [kChains][4]: makespan, generation, island (local), slot
     long long* counters;     // migration epochs with moves, migrants
     unsigned long long seed;
     unsigned long long theta_T;  // floor(theta * 2^32)
@@ -70,6 +76,7 @@ struct IslandDesc {
     int cell_base;               // index of slot 0 among the instance's cellular cells
     int sel;                     // cellular parent selection variant (0, 1, 2)
     int sweep;                   // cellular update: 0 synchronous, 1 line sweep
+    int chain;                   // launch chain (island group) of the island's generations
 };
 
 struct WorkItem {
@@ -88,9 +95,8 @@ struct PairDesc {
 struct Control {
     int* counts;                 // [workgroups per generation launch]
     int base;                    // completed generation when the counts were zero
-    int best_gen;                // last generation folded into the best-ever records
+    int best_gen[2];             // per chain: last generation folded into its best-ever records
     int err;                     // bit 0: invalid permutation, bit 1: decode fault
-    int pad;
 };
 
 __device__ __forceinline__ int completed_gen(const Control* c)
@@ -933,7 +939,7 @@ __device__ __forceinline__ CellMeta make_child(const InstDesc* I, const IslandDe
 __host__ __device__ inline size_t fold_lds_bytes(int threads) { return (size_t)3 * sizeof(int) * threads; }
 
 __device__ void fold_best(const InstDesc* __restrict__ insts, const IslandDesc* __restrict__ isls, int n_inst,
-                          int g, Control* ctl, int* s_tmp)
+                          int g, Control* ctl, int* s_tmp, int chain)
 {
     const int par = g & 1;
     int* s_imp = s_tmp;
@@ -946,6 +952,7 @@ __device__ void fold_best(const InstDesc* __restrict__ insts, const IslandDesc* 
             const InstDesc* J = insts + ii;
             unsigned long long bkey = ~0ull;
             for (int x = 0; x < J->n_islands; ++x) {
+                if (isls[J->island0 + x].chain != chain) continue;
                 unsigned long long* gk = isls[J->island0 + x].genkey + par;
                 const unsigned long long v = __hip_atomic_load(gk, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
                 if (bisl < 0 || (v >> 32) < (bkey >> 32)) {
@@ -954,14 +961,17 @@ __device__ void fold_best(const InstDesc* __restrict__ insts, const IslandDesc* 
                 }
                 __hip_atomic_store(gk, ~0ull, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
             }
-            bslot = (int)(bkey & 0xFFFFFFFFu);
-            const int bmk = (int)(bkey >> 32);
-            if (bmk < J->best_rec[0]) {
-                J->best_rec[0] = bmk;
-                J->best_rec[1] = g;
-                J->best_rec[2] = bisl;
-                J->best_rec[3] = bslot;
-                imp = 1;
+            if (bisl >= 0) {
+                int* rec = J->best_rec + 4 * chain;
+                bslot = (int)(bkey & 0xFFFFFFFFu);
+                const int bmk = (int)(bkey >> 32);
+                if (bmk < rec[0]) {
+                    rec[0] = bmk;
+                    rec[1] = g;
+                    rec[2] = bisl;
+                    rec[3] = bslot;
+                    imp = 1;
+                }
             }
         }
         s_imp[threadIdx.x] = imp;
@@ -974,23 +984,23 @@ __device__ void fold_best(const InstDesc* __restrict__ insts, const IslandDesc* 
             const InstDesc* J = insts + base + t;
             const IslandDesc* X = isls + J->island0 + s_isl[t];
             const uint4* s4 = reinterpret_cast<const uint4*>(X->genes[par] + (size_t)s_slot[t] * J->n_pad);
-            uint4* d4 = reinterpret_cast<uint4*>(J->best_perm);
+            uint4* d4 = reinterpret_cast<uint4*>(J->best_perm + (size_t)chain * J->n_pad);
             for (int v = threadIdx.x; v < (J->n_pad >> 3); v += blockDim.x) d4[v] = s4[v];
         }
         __syncthreads();
     }
-    if (threadIdx.x == 0) ctl->best_gen = g;
+    if (threadIdx.x == 0) ctl->best_gen[chain] = g;
 }
 
-// Folds the completed generation into the best-ever records unless that was
-// done already (one workgroup).
+// Folds the completed generation into the best-ever records of every chain
+// that has not done so yet (one workgroup).
 __global__ void __launch_bounds__(256) k_best_flush(const InstDesc* __restrict__ insts,
                                                     const IslandDesc* __restrict__ isls, Control* ctl, int n_inst)
 {
     __shared__ int s_tmp[3 * 256];
     const int g = completed_gen(ctl);
-    if (ctl->best_gen >= g) return;
-    fold_best(insts, isls, n_inst, g, ctl, s_tmp);
+    for (int chain = 0; chain < kChains; ++chain)
+        if (ctl->best_gen[chain] < g) fold_best(insts, isls, n_inst, g, ctl, s_tmp, chain);
 }
 
 // ---- one generation (mode 0) or generation 0 (mode 1) of every island -----
@@ -1014,17 +1024,19 @@ __global__ void __launch_bounds__(512) k_generation(const InstDesc* __restrict__
     }
     // the workgroup after the work items folds the previous generation into
     // the best-ever records while the others run this one
+    // has_extra = 1 + chain: the last workgroup folds that chain's previous generation
     if (has_extra && blockIdx.x == gridDim.x - 1) {
         __syncthreads();
-        const int prev = s_gen - 1;
-        if (ctl->best_gen < prev) fold_best(insts, isls, n_inst, prev, ctl, reinterpret_cast<int*>(ffs_smem));
+        const int prev = s_gen - 1, chain = has_extra - 1;
+        if (ctl->best_gen[chain] < prev)
+            fold_best(insts, isls, n_inst, prev, ctl, reinterpret_cast<int*>(ffs_smem), chain);
         return;
     }
     // When every workgroup is resident at once, give each XCD (the hardware
     // places workgroup b on XCD b % 8) a contiguous run of work items, so
     // that neighbouring cells share an L2; larger grids keep the
     // largest-first order.
-    const int nw = (int)gridDim.x - has_extra;
+    const int nw = (int)gridDim.x - (has_extra ? 1 : 0);
     int widx = (int)blockIdx.x;
     if (nw <= 256) {
         const int per = (nw + 7) / 8, full = nw - 8 * (per - 1);

@@ -255,13 +255,15 @@ __global__ void __launch_bounds__(512) k_generation_lane(const InstDesc* __restr
         }
         s_gen = gg;
     }
+    // has_extra = 1 + chain: the last workgroup folds that chain's previous generation
     if (has_extra && blockIdx.x == gridDim.x - 1) {
         __syncthreads();
-        const int prev = s_gen - 1;
-        if (ctl->best_gen < prev) fold_best(insts, isls, n_inst, prev, ctl, reinterpret_cast<int*>(ffs_smem));
+        const int prev = s_gen - 1, chain = has_extra - 1;
+        if (ctl->best_gen[chain] < prev)
+            fold_best(insts, isls, n_inst, prev, ctl, reinterpret_cast<int*>(ffs_smem), chain);
         return;
     }
-    const int nw = (int)gridDim.x - has_extra;
+    const int nw = (int)gridDim.x - (has_extra ? 1 : 0);
     int widx = sweep ? (int)blockIdx.y : (int)blockIdx.x;
     if (!sweep && nw <= 256) {
         const int per = (nw + 7) / 8, full = nw - 8 * (per - 1);
