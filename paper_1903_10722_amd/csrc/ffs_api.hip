@@ -50,7 +50,8 @@ struct HostIsland {
     ffs_island_spec spec;
     int size;
     int cell_base;
-    int chain = 0;                // launch chain of its generations
+    int chain = 0;                // fold group of its generations
+    int rec = 0;                  // its instance's record slot
     size_t off_genes[2], off_mk[2], off_genkey, off_minmax, off_sorted, off_sortbest;
 };
 
@@ -224,6 +225,10 @@ struct ffs_ctx {
     int chains = -1;               // requested: -1 automatic, 1, 2
     int nchain = 1;                // in use
     int chain_w0[3] = {0, 0, 0};   // work ranges of the chains (single class)
+    // with several launch classes, each class is a fold group whose
+    // generations of an epoch run as one branch of the epoch graph
+    bool class_groups = false;
+    int ngroup = 1;                // fold groups
     int sweep_diags = 0;
     size_t off_sweep = 0, sweep_lds = 0;
     void* sweep_kern = nullptr;
@@ -332,15 +337,16 @@ void layout(ffs_ctx* c)
     std::sort(keys.begin(), keys.end(), std::greater<long long>());
     for (auto& I : c->inst) I.cls = (int)(std::find(keys.begin(), keys.end(), class_key(I)) - keys.begin());
     c->n_cls = (int)keys.size();
-    // launch chains: possible when a single class holds every instance, no
-    // island is swept and no instance has the pre-screen (those launches
-    // read the context-wide generation count); automatic from 131072
-    // individuals, where a generation needs more than one round of resident
-    // waves and the other chain's next generation fills the last round (a
-    // smaller generation only pays a second launch).  Islands alternate
-    // between the chains in index order.
+    // fold groups.  Launch chains: possible when a single class holds every
+    // instance, no island is swept and no instance has the pre-screen (those
+    // launches read the context-wide generation count); automatic from
+    // 131072 individuals, where a generation needs more than one round of
+    // resident waves and the other chain's next generation fills the last
+    // round (a smaller generation only pays a second launch).  Islands
+    // alternate between the chains in index order.  Several classes (at
+    // most kMaxGroups, no swept island): one group per class.
     {
-        bool can = c->n_cls == 1;
+        bool can = true;
         int islands = 0;
         long long total = 0;
         for (auto& I : c->inst) {
@@ -351,11 +357,15 @@ void layout(ffs_ctx* c)
                 if (L.spec.kind == 0 && L.spec.sweep) can = false;
             }
         }
-        can = can && islands >= 2;
         const bool want = c->chains == 2 || (c->chains < 0 && total >= kChainAutoMin);
-        c->nchain = (can && want) ? 2 : 1;
+        c->nchain = (can && c->n_cls == 1 && islands >= 2 && want) ? 2 : 1;
+        c->class_groups = can && c->n_cls > 1 && c->n_cls <= kMaxGroups;
         for (auto& I : c->inst)
-            for (size_t x = 0; x < I.isl.size(); ++x) I.isl[x].chain = (c->nchain == 2) ? (int)(x % 2) : 0;
+            for (size_t x = 0; x < I.isl.size(); ++x) {
+                auto& L = I.isl[x];
+                L.chain = c->class_groups ? I.cls : ((c->nchain == 2) ? (int)(x % 2) : 0);
+                L.rec = (c->nchain == 2) ? L.chain : 0;
+            }
     }
     // work items: per island, chunks of (waves per block) x G chromosomes,
     // ordered by cost (n * S * count), largest first
@@ -433,9 +443,10 @@ void layout(ffs_ctx* c)
         if (c->chain_w0[1] == c->n_work) {   // nothing in chain 1: one chain
             c->nchain = 1;
             for (auto& I : c->inst)
-                for (auto& L : I.isl) L.chain = 0;
+                for (auto& L : I.isl) L.chain = L.rec = 0;
         }
     }
+    c->ngroup = c->class_groups ? c->n_cls : c->nchain;
     // one launch per class: its work range, LDS bytes and launch-count slots
     // (the first class's launch also carries the best-ever workgroup)
     c->cls_w0.assign(c->n_cls + 1, 0);
@@ -560,10 +571,13 @@ int check_faults(ffs_ctx* c)
     return FFS_OK;
 }
 
-// One generation of every island (mode 0; mode 1: generation 0).  With two
-// launch chains, chain >= 0 launches only that chain's islands, chain 1 on the
-// first auxiliary stream (the caller forks and joins it); chain < 0 launches
-// both in turn on the context's stream.
+// One generation of every island (mode 0; mode 1: generation 0).  chain >= 0
+// (a fold group, for the branches of a captured epoch) launches only that
+// group's work: with two launch chains that chain's islands, chain 1 on the
+// first auxiliary stream; with class groups that class, class k on auxiliary
+// stream k - 1 (the caller forks and joins the streams).  chain < 0 launches
+// everything: both chains in turn on the context's stream, or the classes
+// side by side, forked and joined here.
 int launch_generation(ffs_ctx* c, int mode, int chain = -1)
 {
     const InstDesc* di = reinterpret_cast<const InstDesc*>(c->ws + c->off_insts);
@@ -612,26 +626,34 @@ int launch_generation(ffs_ctx* c, int mode, int chain = -1)
     // Classes touch disjoint islands, so with several of them the launches
     // after the first go to their own streams, forked from and joined back
     // into the context's stream (parallel branches when captured in a graph)
-    const bool fork = c->concurrent && c->n_cls > 1 && (int)c->aux.size() >= c->n_cls - 1;
+    // (with class groups every class's launch carries the workgroup that
+    // folds its own group; a group >= 0 launches only that class, class k on
+    // auxiliary stream k - 1, for the caller's epoch branches)
+    const bool fork = chain < 0 && c->concurrent && c->n_cls > 1 && (int)c->aux.size() >= c->n_cls - 1;
     if (fork) HIP_TRY(c, hipEventRecord(c->fork_ev[0], c->stream));
     cnt_off = 0;
     for (int k = 0; k < c->n_cls; ++k) {
         const int nw = c->cls_w0[k + 1] - c->cls_w0[k];
-        extra = (mode == 0 && k == 0) ? 1 : 0;
-        if (nw + extra == 0) continue;
+        extra = (mode != 0) ? 0 : (c->class_groups ? 1 + k : (k == 0 ? 1 : 0));
+        if (nw + (extra ? 1 : 0) == 0) continue;
+        if (chain >= 0 && k != chain) {
+            cnt_off += nw + (extra ? 1 : 0);
+            continue;
+        }
         dwk = dw + c->cls_w0[k];
         hipStream_t st = c->stream;
+        if (chain >= 0 && k > 0) st = c->aux[k - 1];
         if (fork && k > 0) {
             st = c->aux[k - 1];
             HIP_TRY(c, hipStreamWaitEvent(st, c->fork_ev[0], 0));
         }
-        HIP_TRY(c, hipLaunchKernel(c->cls_kern[k], dim3((unsigned)(nw + extra)), dim3(64 * c->cls_wpb[k]), args,
-                                   c->cls_lds[k], st));
+        HIP_TRY(c, hipLaunchKernel(c->cls_kern[k], dim3((unsigned)(nw + (extra ? 1 : 0))), dim3(64 * c->cls_wpb[k]),
+                                   args, c->cls_lds[k], st));
         if (fork && k > 0) {
             HIP_TRY(c, hipEventRecord(c->fork_ev[k], st));
             HIP_TRY(c, hipStreamWaitEvent(c->stream, c->fork_ev[k], 0));
         }
-        cnt_off += nw + extra;
+        cnt_off += nw + (extra ? 1 : 0);
     }
     if (mode == 0 && !c->sweep.empty()) {
         // line sweep: anti-diagonal d of every line-sweep island, d in order
@@ -657,7 +679,7 @@ int flush_best(ffs_ctx* c)
     const InstDesc* di = reinterpret_cast<const InstDesc*>(c->ws + c->off_insts);
     const IslandDesc* dl = reinterpret_cast<const IslandDesc*>(c->ws + c->off_isls);
     Control* ctl = reinterpret_cast<Control*>(c->ws + c->off_ctl);
-    hipLaunchKernelGGL(k_best_flush, dim3(1), dim3(256), 0, c->stream, di, dl, ctl, (int)c->inst.size());
+    hipLaunchKernelGGL(k_best_flush, dim3(1), dim3(256), 0, c->stream, di, dl, ctl, (int)c->inst.size(), c->ngroup);
     HIP_TRY(c, hipGetLastError());
     return FFS_OK;
 }
@@ -767,13 +789,15 @@ int apply_tile(ffs_ctx* c)
         HIP_TRY(c, hipMemcpy(c->ws + c->off_counts, zeros.data(), zeros.size() * sizeof(int), hipMemcpyHostToDevice));
         const int base = c->gen;
         HIP_TRY(c, hipMemcpy(c->ws + c->off_ctl + offsetof(Control, base), &base, sizeof base, hipMemcpyHostToDevice));
-        const int bg[2] = {base, base};
+        int bg[kMaxGroups];
+        std::fill(bg, bg + kMaxGroups, base);
         HIP_TRY(c, hipMemcpy(c->ws + c->off_ctl + offsetof(Control, best_gen), bg, sizeof bg, hipMemcpyHostToDevice));
         int x = 0;
         for (auto& I : c->inst)
             for (auto& L : I.isl) {
-                HIP_TRY(c, hipMemcpy(c->ws + c->off_isls + sizeof(IslandDesc) * x + offsetof(IslandDesc, chain),
-                                     &L.chain, sizeof(int), hipMemcpyHostToDevice));
+                const int cr[2] = {L.chain, L.rec};
+                HIP_TRY(c, hipMemcpy(c->ws + c->off_isls + sizeof(IslandDesc) * x + offsetof(IslandDesc, chain), cr,
+                                     sizeof cr, hipMemcpyHostToDevice));
                 ++x;
             }
     }
@@ -1450,6 +1474,7 @@ int ffs_bind_workspace(ffs_ctx* c, void* dptr, size_t bytes)
             e.sel = L.spec.kind == 0 ? L.spec.selection : 0;
             e.sweep = L.spec.kind == 0 ? L.spec.sweep : 0;
             e.chain = L.chain;
+            e.rec = L.rec;
             hl.push_back(e);
         }
         isl_base += (int)I.isl.size();
@@ -1457,7 +1482,7 @@ int ffs_bind_workspace(ffs_ctx* c, void* dptr, size_t bytes)
     Control ctl;
     memset(&ctl, 0, sizeof ctl);
     ctl.counts = reinterpret_cast<int*>(c->ws + c->off_counts);
-    ctl.best_gen[0] = ctl.best_gen[1] = -1;
+    for (int gi = 0; gi < kMaxGroups; ++gi) ctl.best_gen[gi] = -1;
     {
         std::vector<int> zeros(c->max_work + 16, 0);
         HIP_TRY(c, hipMemcpy(c->ws + c->off_counts, zeros.data(), zeros.size() * sizeof(int), hipMemcpyHostToDevice));
@@ -1624,6 +1649,16 @@ int ffs_evolve(ffs_ctx* c, int32_t generations)
                     }
                     HIP_TRY(c, hipEventRecord(c->fork_ev[1], c->aux[0]));
                     HIP_TRY(c, hipStreamWaitEvent(c->stream, c->fork_ev[1], 0));
+                } else if (c->class_groups && c->concurrent && (int)c->aux.size() >= c->n_cls - 1) {
+                    // each class's generations of the epoch as one branch
+                    HIP_TRY(c, hipEventRecord(c->fork_ev[0], c->stream));
+                    for (int k = 1; k < c->n_cls; ++k) HIP_TRY(c, hipStreamWaitEvent(c->aux[k - 1], c->fork_ev[0], 0));
+                    for (int t = 0; t < L && crc == FFS_OK; ++t)
+                        for (int k = 0; k < c->n_cls && crc == FFS_OK; ++k) crc = launch_generation(c, 0, k);
+                    for (int k = 1; k < c->n_cls; ++k) {
+                        HIP_TRY(c, hipEventRecord(c->fork_ev[k], c->aux[k - 1]));
+                        HIP_TRY(c, hipStreamWaitEvent(c->stream, c->fork_ev[k], 0));
+                    }
                 } else {
                     for (int t = 0; t < L && crc == FFS_OK; ++t) {
                         if (c->surr >= 0) crc = surrogate_score(c, nullptr);
@@ -1994,7 +2029,7 @@ int ffs_checkpoint_load(ffs_ctx* c, const void* host, size_t bytes)
     HIP_TRY(c, hipMemcpyAsync(&ctl, c->ws + c->off_ctl, sizeof ctl, hipMemcpyDeviceToHost, c->stream));
     HIP_TRY(c, hipStreamSynchronize(c->stream));
     ctl.base = c->gen;
-    ctl.best_gen[0] = ctl.best_gen[1] = c->gen;
+    for (int gi = 0; gi < kMaxGroups; ++gi) ctl.best_gen[gi] = c->gen;
     ctl.err = 0;
     HIP_TRY(c, hipMemcpyAsync(c->ws + c->off_ctl, &ctl, sizeof ctl, hipMemcpyHostToDevice, c->stream));
     const unsigned long long gk[2] = {~0ull, ~0ull};

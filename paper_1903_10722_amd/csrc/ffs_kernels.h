@@ -30,11 +30,15 @@ constexpr int kWave = 64;
 constexpr int kMaxStages = 64;
 constexpr int kMaxMachines = 16;
 
-// Islands of a context may form two launch chains whose generations run as
-// independent launch sequences between migration epochs; each chain keeps its
-// own best-ever record per instance, and the instance's record is the better
-// of the two by (makespan, generation, island, slot).
-constexpr int kChains = 2;
+// The islands of a context form fold groups: the islands whose generations
+// one launch sequence runs (a launch chain of a large instance's islands, or
+// a launch class's instances), whose best individuals the extra workgroup of
+// that sequence's launches folds into the best-ever records.  Between
+// migration epochs the groups' sequences are independent.  An instance split
+// over two chains keeps a record per chain (record slot); its record is the
+// better of the two by (makespan, generation, island, slot).
+constexpr int kChains = 2;      // record slots per instance
+constexpr int kMaxGroups = 16;  // fold groups per context
 
 struct InstDesc {
     const void* pT;          // [S][n_pad] processing times, uint8 or uint16
@@ -76,7 +80,8 @@ struct IslandDesc {
     int cell_base;               // index of slot 0 among the instance's cellular cells
     int sel;                     // cellular parent selection variant (0, 1, 2)
     int sweep;                   // cellular update: 0 synchronous, 1 line sweep
-    int chain;                   // launch chain (island group) of the island's generations
+    int chain;                   // fold group of the island's generations
+    int rec;                     // its instance's record slot for that group
 };
 
 struct WorkItem {
@@ -95,7 +100,7 @@ struct PairDesc {
 struct Control {
     int* counts;                 // [workgroups per generation launch]
     int base;                    // completed generation when the counts were zero
-    int best_gen[2];             // per chain: last generation folded into its best-ever records
+    int best_gen[kMaxGroups];    // per fold group: last generation folded into the records
     int err;                     // bit 0: invalid permutation, bit 1: decode fault
 };
 
@@ -939,7 +944,7 @@ __device__ __forceinline__ CellMeta make_child(const InstDesc* I, const IslandDe
 __host__ __device__ inline size_t fold_lds_bytes(int threads) { return (size_t)3 * sizeof(int) * threads; }
 
 __device__ void fold_best(const InstDesc* __restrict__ insts, const IslandDesc* __restrict__ isls, int n_inst,
-                          int g, Control* ctl, int* s_tmp, int chain)
+                          int g, Control* ctl, int* s_tmp, int group)
 {
     const int par = g & 1;
     int* s_imp = s_tmp;
@@ -952,7 +957,7 @@ __device__ void fold_best(const InstDesc* __restrict__ insts, const IslandDesc* 
             const InstDesc* J = insts + ii;
             unsigned long long bkey = ~0ull;
             for (int x = 0; x < J->n_islands; ++x) {
-                if (isls[J->island0 + x].chain != chain) continue;
+                if (isls[J->island0 + x].chain != group) continue;
                 unsigned long long* gk = isls[J->island0 + x].genkey + par;
                 const unsigned long long v = __hip_atomic_load(gk, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
                 if (bisl < 0 || (v >> 32) < (bkey >> 32)) {
@@ -962,7 +967,8 @@ __device__ void fold_best(const InstDesc* __restrict__ insts, const IslandDesc* 
                 __hip_atomic_store(gk, ~0ull, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
             }
             if (bisl >= 0) {
-                int* rec = J->best_rec + 4 * chain;
+                const int slot = isls[J->island0 + bisl].rec;
+                int* rec = J->best_rec + 4 * slot;
                 bslot = (int)(bkey & 0xFFFFFFFFu);
                 const int bmk = (int)(bkey >> 32);
                 if (bmk < rec[0]) {
@@ -984,23 +990,24 @@ __device__ void fold_best(const InstDesc* __restrict__ insts, const IslandDesc* 
             const InstDesc* J = insts + base + t;
             const IslandDesc* X = isls + J->island0 + s_isl[t];
             const uint4* s4 = reinterpret_cast<const uint4*>(X->genes[par] + (size_t)s_slot[t] * J->n_pad);
-            uint4* d4 = reinterpret_cast<uint4*>(J->best_perm + (size_t)chain * J->n_pad);
+            uint4* d4 = reinterpret_cast<uint4*>(J->best_perm + (size_t)X->rec * J->n_pad);
             for (int v = threadIdx.x; v < (J->n_pad >> 3); v += blockDim.x) d4[v] = s4[v];
         }
         __syncthreads();
     }
-    if (threadIdx.x == 0) ctl->best_gen[chain] = g;
+    if (threadIdx.x == 0) ctl->best_gen[group] = g;
 }
 
-// Folds the completed generation into the best-ever records of every chain
-// that has not done so yet (one workgroup).
+// Folds the completed generation into the best-ever records of every fold
+// group that has not done so yet (one workgroup).
 __global__ void __launch_bounds__(256) k_best_flush(const InstDesc* __restrict__ insts,
-                                                    const IslandDesc* __restrict__ isls, Control* ctl, int n_inst)
+                                                    const IslandDesc* __restrict__ isls, Control* ctl, int n_inst,
+                                                    int groups)
 {
     __shared__ int s_tmp[3 * 256];
     const int g = completed_gen(ctl);
-    for (int chain = 0; chain < kChains; ++chain)
-        if (ctl->best_gen[chain] < g) fold_best(insts, isls, n_inst, g, ctl, s_tmp, chain);
+    for (int group = 0; group < groups; ++group)
+        if (ctl->best_gen[group] < g) fold_best(insts, isls, n_inst, g, ctl, s_tmp, group);
 }
 
 // ---- one generation (mode 0) or generation 0 (mode 1) of every island -----
@@ -1024,12 +1031,13 @@ __global__ void __launch_bounds__(512) k_generation(const InstDesc* __restrict__
     }
     // the workgroup after the work items folds the previous generation into
     // the best-ever records while the others run this one
-    // has_extra = 1 + chain: the last workgroup folds that chain's previous generation
+    // has_extra = 1 + group: the last workgroup folds that fold group's
+    // previous generation
     if (has_extra && blockIdx.x == gridDim.x - 1) {
         __syncthreads();
-        const int prev = s_gen - 1, chain = has_extra - 1;
-        if (ctl->best_gen[chain] < prev)
-            fold_best(insts, isls, n_inst, prev, ctl, reinterpret_cast<int*>(ffs_smem), chain);
+        const int prev = s_gen - 1, group = has_extra - 1;
+        if (ctl->best_gen[group] < prev)
+            fold_best(insts, isls, n_inst, prev, ctl, reinterpret_cast<int*>(ffs_smem), group);
         return;
     }
     // When every workgroup is resident at once, give each XCD (the hardware

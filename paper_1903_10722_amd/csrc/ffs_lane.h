@@ -255,12 +255,13 @@ __global__ void __launch_bounds__(512) k_generation_lane(const InstDesc* __restr
         }
         s_gen = gg;
     }
-    // has_extra = 1 + chain: the last workgroup folds that chain's previous generation
+    // has_extra = 1 + group: the last workgroup folds that fold group's
+    // previous generation
     if (has_extra && blockIdx.x == gridDim.x - 1) {
         __syncthreads();
-        const int prev = s_gen - 1, chain = has_extra - 1;
-        if (ctl->best_gen[chain] < prev)
-            fold_best(insts, isls, n_inst, prev, ctl, reinterpret_cast<int*>(ffs_smem), chain);
+        const int prev = s_gen - 1, group = has_extra - 1;
+        if (ctl->best_gen[group] < prev)
+            fold_best(insts, isls, n_inst, prev, ctl, reinterpret_cast<int*>(ffs_smem), group);
         return;
     }
     const int nw = (int)gridDim.x - (has_extra ? 1 : 0);

@@ -105,3 +105,32 @@ def test_chains_checkpoint_restore():
     assert a.checkpoint() == b.checkpoint()
     a.close()
     b.close()
+
+
+@pytest.mark.parametrize("concurrent", [True, False])
+def test_class_groups_epoch_branches(concurrent):
+    """Twelve uneven batched instances (grids shrunk eightfold) with tiles
+    that put them in several launch classes: with the classes side by side,
+    each class's generations of an epoch are one branch of the epoch graph
+    (the classes run out of step between migrations) and fold their own
+    best-ever records.  Whole epochs, an eager stretch and epochs again,
+    every instance compared with its oracle run and its best record."""
+    ensure_built()
+    ws = inputs.batched_workloads(count=12, batch_seed=11, scale=8)
+    for w in ws:
+        w["interval"] = 5
+    say(f"[chains] class groups, concurrent={concurrent}")
+    ctx = make_ctx(ws, mapping=1)
+    for i in range(len(ws)):
+        ctx.set_instance_tile(i, i % 2, (1, 2, 4)[i % 3])
+    ctx.set_concurrent(concurrent)
+    gas = [oracle_ga(w, inst=i) for i, w in enumerate(ws)]
+    for g in (5, 10, 3, 2, 10):
+        ctx.evolve(g)
+        for i, ga in enumerate(gas):
+            ga.evolve(g)
+            assert_same_state(ctx, ga, i, 2, f"instance {i} generation {ctx.generation}")
+            _check_best(ctx, ga, i, f"instance {i} generation {ctx.generation}")
+        for i, ga in enumerate(gas):
+            assert ctx.migration_counters(i) == ga.counters()
+    ctx.close()
