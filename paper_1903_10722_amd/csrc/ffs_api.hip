@@ -460,9 +460,11 @@ void layout(ffs_ctx* c)
         c->cls_kern[I.cls] = I.map_eff ? pick_gen_lane(c->mm, c->ptb) : pick_gen(c->mm, c->ptb);
         c->cls_wpb[I.cls] = I.wpb_eff;
     }
-    // the first class's launch carries the best-ever workgroup, whose scratch
-    // is dynamic LDS too
-    if (c->n_cls > 0) c->cls_lds[0] = std::max(c->cls_lds[0], fold_lds_bytes(64 * c->cls_wpb[0]));
+    // a class's launch can carry a best-ever workgroup (the first class's
+    // always, every class's with one fold group per class), whose scratch is
+    // dynamic LDS too
+    for (int k = 0; k < c->n_cls; ++k)
+        c->cls_lds[k] = std::max(c->cls_lds[k], fold_lds_bytes(64 * c->cls_wpb[k]));
 
     c->off_ctl = take(sizeof(Control));
     c->off_insts = take(sizeof(InstDesc) * c->inst.size());

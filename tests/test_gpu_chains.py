@@ -134,3 +134,30 @@ def test_class_groups_epoch_branches(concurrent):
         for i, ga in enumerate(gas):
             assert ctx.migration_counters(i) == ga.counters()
     ctx.close()
+
+
+def test_class_groups_small_class_fold_scratch():
+    """Two launch classes; the second holds an instance whose own LDS is
+    smaller than the best-ever workgroup's scratch at 8 waves per workgroup
+    (n = 20, S = 40, per-stage mapping: 3104 bytes against 6144).  With one
+    fold group per class that class's launch folds its own best-ever record,
+    so its LDS must cover the scratch.  Every instance, its best makespan,
+    generation and permutation against the oracle."""
+    ensure_built()
+    ws = []
+    for j, (n, S) in enumerate([(20, 40), (500, 10)]):
+        m, p = inputs.make_instance(n, S, 1, 3, seed=30 + j)
+        ws.append(dict(m=m, p=p, islands=[inputs.cellular(4, 4, 0.9, 0.2), inputs.pseudo(16, 0.75, 0.05)],
+                       interval=4, theta=1.0, topology=0))
+    say("[chains] class groups with a small class at 8 waves per workgroup")
+    ctx = make_ctx(ws)
+    ctx.set_instance_tile(0, 0, 8)
+    ctx.set_instance_tile(1, 1, 1)
+    gas = [oracle_ga(w, inst=i) for i, w in enumerate(ws)]
+    for g in (1, 3, 4, 8):
+        ctx.evolve(g)
+        for i, ga in enumerate(gas):
+            ga.evolve(g)
+            assert_same_state(ctx, ga, i, 2, f"instance {i} generation {ctx.generation}")
+            _check_best(ctx, ga, i, f"instance {i} generation {ctx.generation}")
+    ctx.close()

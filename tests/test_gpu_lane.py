@@ -117,6 +117,29 @@ def test_lane_tiny_trajectory(inst_seed):
     ctx.close()
 
 
+@pytest.mark.parametrize("n", [20, 500, 520])
+def test_lane_odd_counts(n):
+    """Islands whose waves hold an odd number of chromosomes (a 7x9 torus,
+    30 pairs) on the lane mapping, with rows of 32, 512 and 544 genes: 30
+    generations with adaptive migration every 10, compared with the oracle
+    after every chunk."""
+    ensure_built()
+    m, p = inputs.make_instance(n, 6, 1, 4, seed=7)
+    isl = [inputs.cellular(7, 9, 0.9, 0.2), inputs.pseudo(30, 0.75, 0.05)]
+    w = dict(m=m, p=p, islands=isl, interval=10, theta=1.0, topology=0)
+    say(f"[lane] odd counts n={n}")
+    ctx = make_ctx([w], mapping=1)
+    assert ctx.mapping() == 1
+    ga = oracle_ga(w)
+    for g in (1, 9, 10, 10):
+        ctx.evolve(g)
+        ga.evolve(g)
+        assert_same_state(ctx, ga, 0, 2, f"n={n} generation {ctx.generation}")
+    assert ctx.best(0)["makespan"] == ga.best()["makespan"]
+    assert ctx.migration_counters(0) == ga.counters()
+    ctx.close()
+
+
 def test_lane_medium_scaled_trajectory():
     """Medium instance (n=100, S=5, m in [1,5]) on 32x32 + 1024 islands,
     60 generations with adaptive migration every 20, lane mapping."""
