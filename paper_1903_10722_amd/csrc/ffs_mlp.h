@@ -80,7 +80,7 @@ struct GemmStage {
             }
         } else {
             if ((tid >> 7) == half) {
-                const int q = tid & 127, kb = (q >> 4) * 8, xb = (q & 15) * 8;
+                const int q = tid & 127, kb = (q & 7) * 8, xb = (q >> 3) * 8;
 #pragma unroll
                 for (int t = 0; t < 8; ++t)
                     r[t] = *reinterpret_cast<const gu32x4_t*>(&X[(size_t)(k0 + kb + t) * ld + x0 + xb]);
@@ -98,7 +98,9 @@ struct GemmStage {
             }
         } else {
             if ((tid >> 7) == half) {
-                const int q = tid & 127, kb = (q >> 4) * 8, xb = (q & 15) * 8;
+                // eight consecutive threads fill the eight 16-byte k-chunks of
+                // one LDS row: no bank conflicts
+                const int q = tid & 127, kb = (q & 7) * 8, xb = (q >> 3) * 8;
                 gu32x4_t y[8];
                 transpose8x8_u16(r, y);
 #pragma unroll
@@ -128,6 +130,21 @@ __global__ void __launch_bounds__(256) k_gemm(const uint16_t* __restrict__ A, co
 #pragma unroll
             for (int r = 0; r < 16; ++r) acc[a][b][r] = 0.f;
 
+    // the mask of this thread's outputs, read before the K loop so that its
+    // latency hides behind the MFMAs
+    uint32_t mk[EPI == EPI_MASK_BF16 ? 64 : 1];
+    if constexpr (EPI == EPI_MASK_BF16) {
+#pragma unroll
+        for (int ti = 0; ti < 2; ++ti)
+#pragma unroll
+            for (int tj = 0; tj < 2; ++tj)
+#pragma unroll
+                for (int r = 0; r < 16; ++r) {
+                    const int i = bm + wm + ti * 32 + 8 * (r >> 2) + 4 * (lane >> 5) + (r & 3);
+                    const int j = bn + wn + tj * 32 + (lane & 31);
+                    mk[(ti * 2 + tj) * 16 + r] = mask[(size_t)i * ldc + j];
+                }
+    }
     // k-major operands: A by threads 0..127, B by threads 128..255
     GemmStage<TA> sa;
     GemmStage<!TB> sb;
@@ -182,7 +199,7 @@ __global__ void __launch_bounds__(256) k_gemm(const uint16_t* __restrict__ A, co
                     const float z = v + bias[j];
                     Cb[o] = f32_to_bf16(z > 0.f ? z : 0.f);
                 } else {
-                    Cb[o] = (bf16_to_f32(mask[o]) > 0.f) ? f32_to_bf16(v) : (uint16_t)0;
+                    Cb[o] = (bf16_to_f32((uint16_t)mk[(ti * 2 + tj) * 16 + r]) > 0.f) ? f32_to_bf16(v) : (uint16_t)0;
                 }
             }
 }
