@@ -1427,6 +1427,10 @@ int ffs_bind_workspace(ffs_ctx* c, void* dptr, size_t bytes)
         d.n_pad = I.n_pad;
         d.jb = I.jb;
         d.G = I.G;
+        // the lane decode's three-field key (completion, dispatch index,
+        // job) where its completion field holds 1.5 times the lower bound
+        // (makespans above it fall back to the two-field key)
+        d.fsh = (2 * I.jb <= 30 && 3 * I.LB < 2 * (1ll << (32 - 2 * I.jb))) ? 2 * I.jb : 0;
         d.island0 = isl_base;
         d.n_islands = (int)I.isl.size();
         d.interval = (I.isl.size() >= 2) ? I.cfg.migration_interval : 0;

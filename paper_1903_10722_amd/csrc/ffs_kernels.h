@@ -50,6 +50,7 @@ struct InstDesc {
     long long E;                 // sum of all processing times
     int inst_id;
     int n, S, n_pad, jb, G;
+    int fsh;                     // lane decode: completion shift of the three-field key (2 jb), 0: not used
     int island0, n_islands;
     int interval, topology;
     // learned pre-screen (surr_k > 1): candidate streams per cell, replay ring

@@ -57,15 +57,33 @@ __host__ __device__ inline size_t lane_eval_wave_lds(int n, int msum)
     return align16(st > seen ? st : seen);
 }
 
-// One stage over one window.  r[i] holds slot lo + i: a key
-// (completion << jb | job) from the previous stage, or a gene at stage 0
-// (completion 0).  With GUARD, slot i dispatches only if bit i of `act` is
-// set, and if bit i of `fl` is set it receives the list's first entry,
-// which leaves the list (the flush after the last dispatch); job indices
-// are clamped to n - 1 for the table read.
-template <int M, bool GUARD, typename PT>
+// Median of three unsigned words (one VALU operation).
+__device__ __forceinline__ uint32_t umed3(uint32_t a, uint32_t b, uint32_t c)
+{
+    uint32_t r;
+    asm("v_med3_u32 %0, %1, %2, %3" : "=v"(r) : "v"(a), "v"(b), "v"(c));
+    return r;
+}
+
+// One stage over one window.  r[i] holds slot lo + i: a key from the
+// previous stage, or a gene at stage 0 (completion 0).  Key formats:
+//   F = false: completion << jb | job.  A new key goes after every entry
+//     with the same completion (those were dispatched earlier), by a
+//     threshold compare per entry.
+//   F = true:  completion << sh | dispatch index << jb | job (sh = 2 jb),
+//     the dispatch index counting this stage's dispatches.  Keys of one
+//     list are then distinct and their numeric order is (completion,
+//     dispatch order), so the new key goes in by one min, max or median
+//     per entry.  The completions must stay below 2^(32 - sh): cor
+//     collects the bits of every completion for the caller's check.
+// With GUARD, slot i dispatches only if bit i of `act` is set, and if bit i
+// of `fl` is set it receives the list's first entry, which leaves the list
+// (the flush after the last dispatch); job indices are clamped to n - 1 for
+// the table read.
+template <int M, bool GUARD, bool F, typename PT>
 __device__ __forceinline__ void lane_stage(uint32_t (&r)[kLaneD], uint32_t (&key)[M], const PT* prow,
-                                           uint32_t jb, uint32_t jmask, uint32_t act, uint32_t fl, uint32_t nmax)
+                                           uint32_t jb, uint32_t jmask, uint32_t act, uint32_t fl, uint32_t nmax,
+                                           uint32_t sh, int dbase, uint32_t& cor)
 {
     uint32_t jj[kLaneD], pj[kLaneD];
 #pragma unroll
@@ -82,24 +100,42 @@ __device__ __forceinline__ void lane_stage(uint32_t (&r)[kLaneD], uint32_t (&key
             // larger (or equal) time in its high bits
             const uint32_t o = key[0];
             const uint32_t mx = o > r[i] ? o : r[i];
-            const uint32_t c = (mx >> jb) + pj[i];
-            const uint32_t nk = (c << jb) | jj[i];
-            if (M == 1) {
-                key[0] = nk;
-            } else {
-                // drop entry 0, insert nk after every entry with completion <= c
-                const uint32_t thr = (c + 1u) << jb;
-                uint32_t nkey[M];
-                bool prev = true;
+            if (F) {
+                const uint32_t c = (mx >> sh) + pj[i];
+                cor |= c;
+                if (M == 1) {
+                    key[0] = (c << sh) | jj[i];
+                } else {
+                    const uint32_t nk = (c << sh) | ((uint32_t)(dbase + i) << jb) | jj[i];
+                    // sorted list key[1 .. M-1] with nk added
+                    uint32_t nkey[M];
+                    nkey[0] = key[1] < nk ? key[1] : nk;
 #pragma unroll
-                for (int q = 0; q + 1 < M; ++q) {
-                    const bool lt = key[q + 1] < thr;
-                    nkey[q] = lt ? key[q + 1] : (prev ? nk : key[q]);
-                    prev = lt;
+                    for (int q = 1; q + 1 < M; ++q) nkey[q] = umed3(key[q], nk, key[q + 1]);
+                    nkey[M - 1] = key[M - 1] > nk ? key[M - 1] : nk;
+#pragma unroll
+                    for (int q = 0; q < M; ++q) key[q] = nkey[q];
                 }
-                nkey[M - 1] = prev ? nk : key[M - 1];
+            } else {
+                const uint32_t c = (mx >> jb) + pj[i];
+                const uint32_t nk = (c << jb) | jj[i];
+                if (M == 1) {
+                    key[0] = nk;
+                } else {
+                    // drop entry 0, insert nk after every entry with completion <= c
+                    const uint32_t thr = (c + 1u) << jb;
+                    uint32_t nkey[M];
+                    bool prev = true;
 #pragma unroll
-                for (int q = 0; q < M; ++q) key[q] = nkey[q];
+                    for (int q = 0; q + 1 < M; ++q) {
+                        const bool lt = key[q + 1] < thr;
+                        nkey[q] = lt ? key[q + 1] : (prev ? nk : key[q]);
+                        prev = lt;
+                    }
+                    nkey[M - 1] = prev ? nk : key[M - 1];
+#pragma unroll
+                    for (int q = 0; q < M; ++q) key[q] = nkey[q];
+                }
             }
             r[i] = o;
         } else if (GUARD && ((fl >> i) & 1u)) {
@@ -115,9 +151,10 @@ __device__ __forceinline__ void lane_stage(uint32_t (&r)[kLaneD], uint32_t (&key
 // stage.  Keys live at st[q * 64] (q < M) between windows (during a flush
 // that spans two windows, the entries not yet written, first at q = 0).  Returns the
 // makespan on the last window of the last stage, else 0.
-template <int M, typename PT>
+template <int M, bool F, typename PT>
 __device__ __forceinline__ uint32_t lane_stage_window(uint32_t (&r)[kLaneD], uint32_t* st, const PT* prow, int lo,
-                                                      int d0, int n, bool last, uint32_t jb, uint32_t jmask)
+                                                      int d0, int n, bool last, uint32_t jb, uint32_t jmask,
+                                                      uint32_t sh, uint32_t& cor)
 {
     const int d1 = d0 + n, end = last ? d1 : d1 + M;
     uint32_t key[M];
@@ -129,7 +166,7 @@ __device__ __forceinline__ uint32_t lane_stage_window(uint32_t (&r)[kLaneD], uin
         for (int q = 0; q < M; ++q) key[q] = st[q * 64];
     }
     if (d0 <= lo && lo + kLaneD <= d1) {
-        lane_stage<M, false, PT>(r, key, prow, jb, jmask, 0u, 0u, 0u);
+        lane_stage<M, false, F, PT>(r, key, prow, jb, jmask, 0u, 0u, 0u, sh, lo - d0, cor);
     } else {
         const int a0 = d0 > lo ? d0 - lo : 0, a1 = (d1 < lo + kLaneD ? d1 : lo + kLaneD) - lo;
         const uint32_t act = (a1 > a0) ? ((0xFFFFFFFFu >> (32 - (a1 - a0))) << a0) : 0u;
@@ -138,9 +175,9 @@ __device__ __forceinline__ uint32_t lane_stage_window(uint32_t (&r)[kLaneD], uin
             const int f0 = (d1 > lo ? d1 : lo) - lo, f1 = (end < lo + kLaneD ? end : lo + kLaneD) - lo;
             fl = (f1 > f0) ? ((0xFFFFFFFFu >> (32 - (f1 - f0))) << f0) : 0u;
         }
-        lane_stage<M, true, PT>(r, key, prow, jb, jmask, act, fl, (uint32_t)(n - 1));
+        lane_stage<M, true, F, PT>(r, key, prow, jb, jmask, act, fl, (uint32_t)(n - 1), sh, lo - d0, cor);
     }
-    if (end <= lo + kLaneD) return last ? (key[M - 1] >> jb) : 0u;
+    if (end <= lo + kLaneD) return last ? (key[M - 1] >> (F ? sh : jb)) : 0u;
 #pragma unroll
     for (int q = 0; q < M; ++q) st[q * 64] = key[q];
     return 0u;
@@ -180,12 +217,12 @@ struct GenesI32 {
     }
 };
 
-// Makespan of one chromosome per lane.  pT is the LDS table (row stride
-// pts), mach the stage machine counts, st this wave's LDS state (msum keys
-// per lane, lane-interleaved).
-template <int MMAX, typename PT, typename Src>
-__device__ uint32_t lane_decode(const Src& src, const PT* pT, int pts, const int* mach, int S, int n, int jb,
-                                uint32_t* st, int lane)
+// Makespan of one chromosome per lane with the key format F (see
+// lane_stage).  pT is the LDS table (row stride pts), mach the stage machine
+// counts, st this wave's LDS state (msum keys per lane, lane-interleaved).
+template <int MMAX, bool F, typename PT, typename Src>
+__device__ uint32_t lane_decode_keys(const Src& src, const PT* pT, int pts, const int* mach, int S, int n, int jb,
+                                     uint32_t sh, uint32_t* st, int lane, uint32_t& cor)
 {
     const uint32_t ujb = (uint32_t)jb, jmask = (1u << jb) - 1u;
     int off_last = 0;
@@ -213,7 +250,8 @@ __device__ uint32_t lane_decode(const Src& src, const PT* pT, int pts, const int
                 switch (M) {
 #define FFS_LANE_CASE(MM)                                                                       \
     case MM:                                                                                    \
-        if (MM <= MMAX) cm = lane_stage_window<(MM <= MMAX ? MM : 1), PT>(r, sk, prow, lo, off, n, last, ujb, jmask); \
+        if (MM <= MMAX)                                                                         \
+            cm = lane_stage_window<(MM <= MMAX ? MM : 1), F, PT>(r, sk, prow, lo, off, n, last, ujb, jmask, sh, cor); \
         break;
                     FFS_LANE_CASE(1) FFS_LANE_CASE(2) FFS_LANE_CASE(3) FFS_LANE_CASE(4)
                     FFS_LANE_CASE(5) FFS_LANE_CASE(6) FFS_LANE_CASE(7) FFS_LANE_CASE(8)
@@ -226,6 +264,25 @@ __device__ uint32_t lane_decode(const Src& src, const PT* pT, int pts, const int
         }
     }
     return cmax;
+}
+
+// Makespan of one chromosome per lane.  With fsh > 0 (the instance's
+// completions can fit below 2^(32 - fsh), fsh = 2 jb) the three-field key
+// goes first; if any lane's completions outgrow it, the wave decodes again
+// with the two-field key and those lanes take that result.
+template <int MMAX, typename PT, typename Src>
+__device__ uint32_t lane_decode(const Src& src, const PT* pT, int pts, const int* mach, int S, int n, int jb,
+                                int fsh, uint32_t* st, int lane)
+{
+    uint32_t cor = 0u;
+    if (fsh > 0) {
+        const uint32_t cm = lane_decode_keys<MMAX, true, PT>(src, pT, pts, mach, S, n, jb, (uint32_t)fsh, st, lane, cor);
+        const bool ovf = (cor >> (32 - fsh)) != 0u;
+        if (__ballot(ovf) == 0ull) return cm;
+        const uint32_t cm2 = lane_decode_keys<MMAX, false, PT>(src, pT, pts, mach, S, n, jb, 0u, st, lane, cor);
+        return ovf ? cm2 : cm;
+    }
+    return lane_decode_keys<MMAX, false, PT>(src, pT, pts, mach, S, n, jb, 0u, st, lane, cor);
 }
 
 // ---- one generation (mode 0) or generation 0 (mode 1), lane mapping --------
@@ -399,7 +456,7 @@ __global__ void __launch_bounds__(512) k_generation_lane(const InstDesc* __restr
     unsigned long long wkey = ~0ull;
     if (wcount > 0) {
         const GenesU16 src{L->genes[nxt] + (size_t)slot * n_pad};
-        const uint32_t cm = lane_decode<MMAX, PT>(src, pT, pt_stride<PT>(n_pad), I->mach, S, n, jb,
+        const uint32_t cm = lane_decode<MMAX, PT>(src, pT, pt_stride<PT>(n_pad), I->mach, S, n, jb, I->fsh,
                                                   reinterpret_cast<uint32_t*>(wbase), lane);
         bool keep_old = false;
         if (active) {
@@ -462,7 +519,7 @@ __global__ void __launch_bounds__(512) k_generation_lane(const InstDesc* __restr
 // repeats (per-lane bit set in LDS); its makespan is then -1 and bit 0 of
 // the control block's error word is set.
 template <int MMAX, typename PT>
-__global__ void __launch_bounds__(512) k_evaluate_lane(const InstDesc* __restrict__ I, const int* __restrict__ perms,
+__global__ void __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(4))) k_evaluate_lane(const InstDesc* __restrict__ I, const int* __restrict__ perms,
                                                        int count, int* __restrict__ out, Control* ctl)
 {
     const int n = I->n, S = I->S, n_pad = I->n_pad, jb = I->jb;
@@ -497,7 +554,7 @@ __global__ void __launch_bounds__(512) k_evaluate_lane(const InstDesc* __restric
     }
     wave_sync();
     const GenesI32 src{row, n};
-    const uint32_t cm = lane_decode<MMAX, PT>(src, pT, pt_stride<PT>(n_pad), I->mach, S, n, jb, wbase, lane);
+    const uint32_t cm = lane_decode<MMAX, PT>(src, pT, pt_stride<PT>(n_pad), I->mach, S, n, jb, I->fsh, wbase, lane);
     if (active) out[idx] = bad ? -1 : (int)cm;
     if (active && bad) atomicOr(&ctl->err, 1);
 }

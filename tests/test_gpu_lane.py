@@ -65,6 +65,46 @@ def test_lane_decode_parity(shape):
     ctx.close()
 
 
+def test_lane_decode_key_overflow_falls_back():
+    """The three-field key (completion, dispatch index, job) holds
+    completions below 2^(32 - 2 jb): 16384 at n = 300.  Three job types,
+    each with processing time 60 on its own stage and 1 elsewhere, one
+    machine per stage: the lower bound is 6200, so the instance takes the
+    three-field key, but permutations sorted by type take about 18000.  Rows
+    of both kinds share waves; every makespan matches the oracle (the lanes
+    past the limit are decoded again with the two-field key)."""
+    ensure_built()
+    n, S = 300, 3
+    m = np.ones(S, dtype=np.int32)
+    p = np.ones((n, S), dtype=np.int32)
+    p[np.arange(n), np.arange(n) % S] = 60
+    lb = max(int(p.sum(1).max()), int(p.sum(0).max()))
+    jb = int(np.ceil(np.log2(n)))
+    assert 3 * lb < 2 * (1 << (32 - 2 * jb))       # the three-field key is taken
+    rng = np.random.default_rng(11)
+    by_type = np.argsort(np.arange(n) % S, kind="stable")
+    rows = []
+    for r in range(256):
+        if r % 5 == 0:
+            q = by_type.copy()
+            # a few swaps keep it far above the limit
+            for _ in range(3):
+                a, b = rng.integers(0, n, 2)
+                q[a], q[b] = q[b], q[a]
+            rows.append(q)
+        else:
+            rows.append(rng.permutation(n))
+    perms = np.asarray(rows, dtype=np.int32)
+    want = oracle.decode_many(m, p, perms)
+    assert (want[::5] > 16384).all() and (want[1::5] < 16384).all()
+    w = dict(m=m, p=p, islands=SMALL_ISLANDS, interval=0)
+    say("[lane] key overflow fallback n=300")
+    ctx = make_ctx([w], mapping=1)
+    got = ctx.evaluate(0, perms).cpu().numpy()
+    assert np.array_equal(got, want), f"first mismatch at row {np.argmax(got != want)}"
+    ctx.close()
+
+
 def test_lane_decode_rejects_non_permutations():
     """Out-of-range values and repeated values give -1 on their rows only."""
     ensure_built()
