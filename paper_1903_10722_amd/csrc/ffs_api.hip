@@ -1431,6 +1431,9 @@ int ffs_bind_workspace(ffs_ctx* c, void* dptr, size_t bytes)
         // job) where its completion field holds 1.5 times the lower bound
         // (makespans above it fall back to the two-field key)
         d.fsh = (2 * I.jb <= 30 && 3 * I.LB < 2 * (1ll << (32 - 2 * I.jb))) ? 2 * I.jb : 0;
+        // the pipelined decode's where every completion (at most the sum of
+        // all processing times) fits, the key 0xFFFFFFFF staying padding
+        d.psh = (2 * I.jb <= 30 && I.E < (1ll << (32 - 2 * I.jb)) - 1) ? 2 * I.jb : 0;
         d.island0 = isl_base;
         d.n_islands = (int)I.isl.size();
         d.interval = (I.isl.size() >= 2) ? I.cfg.migration_interval : 0;

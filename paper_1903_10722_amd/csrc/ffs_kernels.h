@@ -51,6 +51,7 @@ struct InstDesc {
     int inst_id;
     int n, S, n_pad, jb, G;
     int fsh;                     // lane decode: completion shift of the three-field key (2 jb), 0: not used
+    int psh;                     // pipelined decode: the same where every completion fits, 0: not used
     int island0, n_islands;
     int interval, topology;
     // learned pre-screen (surr_k > 1): candidate streams per cell, replay ring
@@ -269,10 +270,25 @@ __device__ __forceinline__ uint32_t from_prev_lane(uint32_t x)
 // One step of stage k (see decode_pipelined).  With PRED the lane acts only
 // while rel < n_act and takes a job only while rel < n; without it the caller
 // guarantees both for every lane that matters.
-template <int MMAX, bool PRED, typename PT>
+// Median of three unsigned words (one VALU operation).
+__device__ __forceinline__ uint32_t umed3(uint32_t a, uint32_t b, uint32_t c)
+{
+    uint32_t r;
+    asm("v_med3_u32 %0, %1, %2, %3" : "=v"(r) : "v"(a), "v"(b), "v"(c));
+    return r;
+}
+
+// Key formats: F = false, completion << jb | job, a new key entering after
+// the entries of equal completion by a threshold compare per entry; F =
+// true, completion << sh | dispatch index << jb | job (sh = 2 jb, the
+// dispatch index counting stage k's dispatches, dsh = that index << jb), whose
+// numeric order is (completion, dispatch order), so the new key enters by
+// one min, median or max per entry.
+template <int MMAX, bool PRED, bool F, typename PT>
 __device__ __forceinline__ void pipe_step(uint32_t (&key)[MMAX], uint32_t& o_key, uint32_t& o_p, uint32_t& pn_pre,
                                           uint32_t ap, uint32_t rel, uint32_t n_act, uint32_t un, bool first,
-                                          uint32_t jb, uint32_t jmask, const PT* prow_next)
+                                          uint32_t jb, uint32_t jmask, const PT* prow_next, uint32_t sh,
+                                          uint32_t dsh)
 {
     constexpr uint32_t PAD = 0xFFFFFFFFu;
     const uint32_t in_key = from_prev_lane(o_key);
@@ -280,25 +296,40 @@ __device__ __forceinline__ void pipe_step(uint32_t (&key)[MMAX], uint32_t& o_key
     if (!PRED || rel < n_act) {
         const bool have = !PRED || rel < un;
         // stage 0 takes its job word (p << jb | job) from AP, the others the
-        // handed-on key (completion << jb | job) and processing time
+        // handed-on key and processing time
         const uint32_t x = first ? ap : in_key;
         const uint32_t j = x & jmask;
-        const uint32_t hi = x >> jb;
-        const uint32_t r = first ? 0u : hi;
-        const uint32_t pj = first ? hi : in_p;
         const uint32_t o = key[0];
-        const uint32_t f = o >> jb;
-        const uint32_t st = f > r ? f : r;
-        const uint32_t c = st + pj;
-        const uint32_t nk = have ? ((c << jb) | j) : PAD;
-        const uint32_t ithr = have ? ((c + 1u) << jb) : PAD;
         uint32_t nkey[MMAX];
-        bool prev = true;
+        if (F) {
+            const uint32_t mx = first ? o : (o > in_key ? o : in_key);
+            const uint32_t pj = first ? (ap >> jb) : in_p;
+            const uint32_t c = (mx >> sh) + pj;
+            const uint32_t nk = have ? ((c << sh) | dsh | j) : PAD;
+            if (MMAX == 1) {
+                nkey[0] = nk;
+            } else {
+                nkey[0] = key[1 < MMAX ? 1 : 0] < nk ? key[1 < MMAX ? 1 : 0] : nk;
 #pragma unroll
-        for (int i = 0; i < MMAX; ++i) {
-            const bool lt = (i + 1 < MMAX) ? (key[(i + 1 < MMAX) ? i + 1 : i] < ithr) : false;
-            nkey[i] = lt ? key[(i + 1 < MMAX) ? i + 1 : i] : (prev ? nk : key[i]);
-            prev = lt;
+                for (int i = 1; i + 1 < MMAX; ++i) nkey[i] = umed3(key[i], nk, key[i + 1]);
+                nkey[MMAX - 1] = key[MMAX - 1] > nk ? key[MMAX - 1] : nk;
+            }
+        } else {
+            const uint32_t hi = x >> jb;
+            const uint32_t r = first ? 0u : hi;
+            const uint32_t pj = first ? hi : in_p;
+            const uint32_t f = o >> jb;
+            const uint32_t st = f > r ? f : r;
+            const uint32_t c = st + pj;
+            const uint32_t nk = have ? ((c << jb) | j) : PAD;
+            const uint32_t ithr = have ? ((c + 1u) << jb) : PAD;
+            bool prev = true;
+#pragma unroll
+            for (int i = 0; i < MMAX; ++i) {
+                const bool lt = (i + 1 < MMAX) ? (key[(i + 1 < MMAX) ? i + 1 : i] < ithr) : false;
+                nkey[i] = lt ? key[(i + 1 < MMAX) ? i + 1 : i] : (prev ? nk : key[i]);
+                prev = lt;
+            }
         }
 #pragma unroll
         for (int i = 0; i < MMAX; ++i) key[i] = nkey[i];
@@ -313,8 +344,8 @@ __device__ __forceinline__ void pipe_step(uint32_t (&key)[MMAX], uint32_t& o_key
 
 // One group of S lanes decodes one permutation; lane k runs stage k.
 //
-// Stage k keeps its m_k machine-free times as a sorted list of keys
-// (completion << jb | job) in registers; a machine that has not run a job yet
+// Stage k keeps its m_k machine-free times as a sorted list of keys (one of
+// pipe_step's two formats) in registers; a machine that has not run a job yet
 // holds key 0, a padding entry (fewer than MMAX machines) 0xFFFFFFFF.  Each
 // step dispatches the next job: it takes the machine of entry 0 (free first;
 // ties on time only relabel machines), starts at max(free, ready) and inserts
@@ -337,9 +368,9 @@ __device__ __forceinline__ void pipe_step(uint32_t (&key)[MMAX], uint32_t& o_key
 //
 // AP[t] = (p[job][0] << jb) | job for the permutation's t-th job.  Returns
 // the makespan on the lane of the last stage.
-template <int MMAX, typename PT>
-__device__ __forceinline__ uint32_t decode_pipelined(const uint32_t* AP, const PT* prow_next, const int* mach,
-                                                     int k, int S, int n, int jb, bool active)
+template <int MMAX, bool F, typename PT>
+__device__ __forceinline__ uint32_t decode_pipelined_keys(const uint32_t* AP, const PT* prow_next, const int* mach,
+                                                          int k, int S, int n, int jb, bool active)
 {
     constexpr uint32_t PAD = 0xFFFFFFFFu;
     int a_k = 0, total = n;
@@ -360,38 +391,61 @@ __device__ __forceinline__ uint32_t decode_pipelined(const uint32_t* AP, const P
     const uint32_t un = (uint32_t)n;
     const uint32_t n_act = active ? (last ? un : un + (uint32_t)mstage) : 0u;
     uint32_t pn_pre = (uint32_t)prow_next[0];
+    // three-field keys: the dispatch index of step it is it - a_k
+    const uint32_t sh = 2u * ujb, dstep = 1u << ujb;
+    uint32_t dsh = F ? (uint32_t)(0 - a_k) << ujb : 0u;
     // the steady stretch starts on a multiple of 4 so that its job words can
     // be read four at a time (AP is 16-byte aligned)
     const int steady0 = (a_last + 3) & ~3;
     const int fill_end = steady0 < n ? steady0 : n;
     int it = 0;
-    for (; it < fill_end; ++it)
-        pipe_step<MMAX, true, PT>(key, o_key, o_p, pn_pre, AP[it], (uint32_t)(it - a_k), n_act, un, first, ujb,
-                                  jmask, prow_next);
+    for (; it < fill_end; ++it) {
+        pipe_step<MMAX, true, F, PT>(key, o_key, o_p, pn_pre, AP[it], (uint32_t)(it - a_k), n_act, un, first, ujb,
+                                     jmask, prow_next, sh, dsh);
+        dsh += dstep;
+    }
     if (it + 3 < n) {
         uint4 cur = *reinterpret_cast<const uint4*>(AP + it);
         for (; it + 3 < n; it += 4) {
             const int nx = (it + 7 < n) ? it + 4 : it;
             const uint4 nxt = *reinterpret_cast<const uint4*>(AP + nx);
             asm volatile("" ::: "memory");   // keep the read ahead of the four steps
-            pipe_step<MMAX, false, PT>(key, o_key, o_p, pn_pre, cur.x, 0u, 0u, un, first, ujb, jmask, prow_next);
-            pipe_step<MMAX, false, PT>(key, o_key, o_p, pn_pre, cur.y, 0u, 0u, un, first, ujb, jmask, prow_next);
-            pipe_step<MMAX, false, PT>(key, o_key, o_p, pn_pre, cur.z, 0u, 0u, un, first, ujb, jmask, prow_next);
-            pipe_step<MMAX, false, PT>(key, o_key, o_p, pn_pre, cur.w, 0u, 0u, un, first, ujb, jmask, prow_next);
+            pipe_step<MMAX, false, F, PT>(key, o_key, o_p, pn_pre, cur.x, 0u, 0u, un, first, ujb, jmask, prow_next,
+                                          sh, dsh);
+            pipe_step<MMAX, false, F, PT>(key, o_key, o_p, pn_pre, cur.y, 0u, 0u, un, first, ujb, jmask, prow_next,
+                                          sh, dsh + dstep);
+            pipe_step<MMAX, false, F, PT>(key, o_key, o_p, pn_pre, cur.z, 0u, 0u, un, first, ujb, jmask, prow_next,
+                                          sh, dsh + 2u * dstep);
+            pipe_step<MMAX, false, F, PT>(key, o_key, o_p, pn_pre, cur.w, 0u, 0u, un, first, ujb, jmask, prow_next,
+                                          sh, dsh + 3u * dstep);
+            dsh += 4u * dstep;
             cur = nxt;
         }
     }
-    for (; it < total; ++it)
-        pipe_step<MMAX, true, PT>(key, o_key, o_p, pn_pre, AP[it < n ? it : n - 1], (uint32_t)(it - a_k), n_act,
-                                  un, first, ujb, jmask, prow_next);
+    for (; it < total; ++it) {
+        pipe_step<MMAX, true, F, PT>(key, o_key, o_p, pn_pre, AP[it < n ? it : n - 1], (uint32_t)(it - a_k), n_act,
+                                     un, first, ujb, jmask, prow_next, sh, dsh);
+        dsh += dstep;
+    }
     // the last stage's list now holds every machine's final completion time
     uint32_t cmax = 0;
 #pragma unroll
     for (int i = 0; i < MMAX; ++i) {
-        const uint32_t c = (key[i] == PAD) ? 0u : (key[i] >> jb);
+        const uint32_t c = (key[i] == PAD) ? 0u : (key[i] >> (F ? sh : ujb));
         cmax = c > cmax ? c : cmax;
     }
     return cmax;
+}
+
+// The pipelined decode with the instance's key format: three-field keys
+// where every completion fits their completion field (psh = 2 jb, set when
+// the sum of all processing times does), else two-field keys.
+template <int MMAX, typename PT>
+__device__ __forceinline__ uint32_t decode_pipelined(const uint32_t* AP, const PT* prow_next, const int* mach,
+                                                     int k, int S, int n, int jb, int psh, bool active)
+{
+    if (psh > 0) return decode_pipelined_keys<MMAX, true, PT>(AP, prow_next, mach, k, S, n, jb, active);
+    return decode_pipelined_keys<MMAX, false, PT>(AP, prow_next, mach, k, S, n, jb, active);
 }
 
 // AP[t] = (p[A[t]][0] << jb) | A[t], built by the group's lanes.
@@ -1082,7 +1136,7 @@ __global__ void __launch_bounds__(512) k_generation(const InstDesc* __restrict__
 
     uint32_t* AP = reinterpret_cast<uint32_t*>(B);   // B..V: n_pad words
     build_ap<PT>(AP, A, pT, n, jb, k, S, active);
-    const uint32_t cm = decode_pipelined<MMAX, PT>(AP, prow_next, I->mach, k, S, n, jb, active);
+    const uint32_t cm = decode_pipelined<MMAX, PT>(AP, prow_next, I->mach, k, S, n, jb, I->psh, active);
     const int src = active ? (g * S + S - 1) : lane;
     const int cmg = __shfl((int)cm, src, 64);
 
@@ -1180,7 +1234,7 @@ __global__ void __launch_bounds__(512) k_evaluate(const InstDesc* __restrict__ I
     uint32_t* AP = reinterpret_cast<uint32_t*>(A + n_pad);   // B..V: n_pad words
     build_ap<PT>(AP, A, pT, n, jb, k, S, active);
     const uint32_t cm = decode_pipelined<MMAX, PT>(AP, pT + (size_t)(k + 1 < S ? k + 1 : S - 1) * pt_stride<PT>(n_pad), I->mach,
-                                                   k, S, n, jb, active);
+                                                   k, S, n, jb, I->psh, active);
     if (active && k == S - 1) out[idx] = gbad ? -1 : (int)cm;
     if (active && k == 0 && gbad) atomicOr(&ctl->err, 1);
 }
@@ -1229,7 +1283,7 @@ __global__ void __launch_bounds__(512) k_candidates(const InstDesc* __restrict__
         uint32_t* AP = reinterpret_cast<uint32_t*>(B);
         build_ap<PT>(AP, A, pT, n, jb, k, S, active);
         const uint32_t cm = decode_pipelined<MMAX, PT>(AP, pT + (size_t)(k + 1 < S ? k + 1 : S - 1) * pt_stride<PT>(n_pad),
-                                                       I->mach, k, S, n, jb, active);
+                                                       I->mach, k, S, n, jb, I->psh, active);
         const int cmg = __shfl((int)cm, active ? (g * S + S - 1) : lane, 64);
         if (active && k == 0) Tout[q] = __fdiv_rn((float)(cmg - I->LB), (float)I->LB);
     }

@@ -57,14 +57,6 @@ __host__ __device__ inline size_t lane_eval_wave_lds(int n, int msum)
     return align16(st > seen ? st : seen);
 }
 
-// Median of three unsigned words (one VALU operation).
-__device__ __forceinline__ uint32_t umed3(uint32_t a, uint32_t b, uint32_t c)
-{
-    uint32_t r;
-    asm("v_med3_u32 %0, %1, %2, %3" : "=v"(r) : "v"(a), "v"(b), "v"(c));
-    return r;
-}
-
 // One stage over one window.  r[i] holds slot lo + i: a key from the
 // previous stage, or a gene at stage 0 (completion 0).  Key formats:
 //   F = false: completion << jb | job.  A new key goes after every entry
