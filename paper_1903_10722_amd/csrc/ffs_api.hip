@@ -44,6 +44,19 @@ __global__ void __launch_bounds__(256) k_build_table(const int* __restrict__ p, 
     else reinterpret_cast<uint16_t*>(pT)[i] = (uint16_t)v;
 }
 
+// Completion shifts of the three-field decode key (completion, dispatch
+// index, job): the lane decode's where its completion field holds 1.5 times
+// the lower bound LB (makespans above it fall back to the two-field key),
+// the pipelined decode's where every completion (at most the sum E of all
+// processing times) fits, the key 0xFFFFFFFF staying padding; 0: not used.
+static void key_shifts(int jb, long long LB, long long E, int& fsh, int& psh)
+{
+    const bool ok = 2 * jb <= 30;
+    const long long cap = ok ? (1ll << (32 - 2 * jb)) : 0;
+    fsh = (ok && 3 * LB < 2 * cap) ? 2 * jb : 0;
+    psh = (ok && E < cap - 1) ? 2 * jb : 0;
+}
+
 namespace {
 
 struct HostIsland {
@@ -1427,13 +1440,7 @@ int ffs_bind_workspace(ffs_ctx* c, void* dptr, size_t bytes)
         d.n_pad = I.n_pad;
         d.jb = I.jb;
         d.G = I.G;
-        // the lane decode's three-field key (completion, dispatch index,
-        // job) where its completion field holds 1.5 times the lower bound
-        // (makespans above it fall back to the two-field key)
-        d.fsh = (2 * I.jb <= 30 && 3 * I.LB < 2 * (1ll << (32 - 2 * I.jb))) ? 2 * I.jb : 0;
-        // the pipelined decode's where every completion (at most the sum of
-        // all processing times) fits, the key 0xFFFFFFFF staying padding
-        d.psh = (2 * I.jb <= 30 && I.E < (1ll << (32 - 2 * I.jb)) - 1) ? 2 * I.jb : 0;
+        key_shifts(I.jb, I.LB, I.E, d.fsh, d.psh);
         d.island0 = isl_base;
         d.n_islands = (int)I.isl.size();
         d.interval = (I.isl.size() >= 2) ? I.cfg.migration_interval : 0;
@@ -2107,6 +2114,21 @@ int ffs_evaluate_noalloc(void* hip_stream, int32_t n, int32_t S, const int32_t* 
     d.S = S;
     d.n_pad = n_pad;
     d.jb = jb;
+    {
+        // lower bound: the longest job, and every stage's work over its machines
+        long long LB = 0;
+        for (int j = 0; j < n; ++j) {
+            long long sj = 0;
+            for (int k = 0; k < S; ++k) sj += p[(size_t)j * S + k];
+            LB = std::max(LB, sj);
+        }
+        for (int k = 0; k < S; ++k) {
+            long long pk = 0;
+            for (int j = 0; j < n; ++j) pk += p[(size_t)j * S + k];
+            LB = std::max(LB, (pk + machines[k] - 1) / machines[k]);
+        }
+        key_shifts(jb, LB, E, d.fsh, d.psh);
+    }
     d.G = std::min(kWave / S, std::max(1, 32768 / (2 * group_stride(n_pad))));
     d.msum = msum;
     for (int k = 0; k < S; ++k) d.mach[k] = machines[k];

@@ -213,7 +213,7 @@ struct GenesI32 {
 // lane_stage).  pT is the LDS table (row stride pts), mach the stage machine
 // counts, st this wave's LDS state (msum keys per lane, lane-interleaved).
 template <int MMAX, bool F, typename PT, typename Src>
-__device__ uint32_t lane_decode_keys(const Src& src, const PT* pT, int pts, const int* mach, int S, int n, int jb,
+__device__ __forceinline__ uint32_t lane_decode_keys(const Src& src, const PT* pT, int pts, const int* mach, int S, int n, int jb,
                                      uint32_t sh, uint32_t* st, int lane, uint32_t& cor)
 {
     const uint32_t ujb = (uint32_t)jb, jmask = (1u << jb) - 1u;
@@ -258,21 +258,33 @@ __device__ uint32_t lane_decode_keys(const Src& src, const PT* pT, int pts, cons
     return cmax;
 }
 
+// The two-field decode as a function of its own (the fallback of the
+// three-field one, whose code stays out of the kernel's main path).
+template <int MMAX, typename PT, typename Src>
+__device__ __attribute__((noinline)) uint32_t lane_decode_twofield(const Src& src, const PT* pT, int pts,
+                                                                   const int* mach, int S, int n, int jb,
+                                                                   uint32_t* st, int lane)
+{
+    uint32_t cor = 0u;
+    return lane_decode_keys<MMAX, false, PT>(src, pT, pts, mach, S, n, jb, 0u, st, lane, cor);
+}
+
 // Makespan of one chromosome per lane.  With fsh > 0 (the instance's
 // completions can fit below 2^(32 - fsh), fsh = 2 jb) the three-field key
 // goes first; if any lane's completions outgrow it, the wave decodes again
 // with the two-field key and those lanes take that result.
 template <int MMAX, typename PT, typename Src>
-__device__ uint32_t lane_decode(const Src& src, const PT* pT, int pts, const int* mach, int S, int n, int jb,
+__device__ __forceinline__ uint32_t lane_decode(const Src& src, const PT* pT, int pts, const int* mach, int S, int n, int jb,
                                 int fsh, uint32_t* st, int lane)
 {
     uint32_t cor = 0u;
     if (fsh > 0) {
         const uint32_t cm = lane_decode_keys<MMAX, true, PT>(src, pT, pts, mach, S, n, jb, (uint32_t)fsh, st, lane, cor);
-        const bool ovf = (cor >> (32 - fsh)) != 0u;
-        if (__ballot(ovf) == 0ull) return cm;
-        const uint32_t cm2 = lane_decode_keys<MMAX, false, PT>(src, pT, pts, mach, S, n, jb, 0u, st, lane, cor);
-        return ovf ? cm2 : cm;
+        const bool redo = (cor >> (32 - fsh)) != 0u;
+        if (__ballot(redo) == 0ull) return cm;
+        // rare: out of line
+        const uint32_t cm2 = lane_decode_twofield<MMAX, PT>(src, pT, pts, mach, S, n, jb, st, lane);
+        return redo ? cm2 : cm;
     }
     return lane_decode_keys<MMAX, false, PT>(src, pT, pts, mach, S, n, jb, 0u, st, lane, cor);
 }
