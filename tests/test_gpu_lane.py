@@ -40,6 +40,10 @@ SHAPES = [
     ("single_machines", 40, 6, 1, 1, [1] * 6, 99, 300, 300),
     ("eight_machines", 50, 3, 1, 8, [8, 1, 7], 99, 300, 300),
     ("wide_p", 60, 4, 1, 4, None, 5000, 300, 300),
+    # processing times of 1-3 (1-2): equal completions everywhere, so the order among them (dispatch
+    # order, the keys' tie-break) decides most dispatches; both fit the three-field keys
+    ("tie_heavy", 300, 6, 1, 4, None, 3, 2001, 600),
+    ("tie_heavy_wide_lists", 64, 4, 5, 8, None, 2, 1500, 1500),
     ("short_rows", 5, 7, 1, 4, None, 99, 200, 200),
     ("flush_spans_windows", 17, 3, 5, 8, [8, 7, 6], 99, 300, 300),
     ("many_stages", 12, 40, 1, 3, None, 99, 150, 150),
